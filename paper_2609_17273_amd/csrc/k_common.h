@@ -1,0 +1,272 @@
+// Device helpers shared by the kernels: grid/window arithmetic, log-domain
+// line intensities, and the Faddeeva function w(z) = exp(-z^2) erfc(-iz).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "faddeeva_table.h"
+#include "xsec_internal.h"
+
+namespace xs {
+
+// ---------------------------------------------------------------------------
+// Grid and cut-off window (section "Spectral synthesis"): grid point
+// nu_k = nu0 + k dnu receives line i iff |nu_k - nu_i| <= cut.  Both roundings
+// are done exactly as written (no FMA contraction), so every precision of the
+// path includes the same bins.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double nu_of_bin(double nu0, double dnu, int64_t k) {
+#pragma clang fp contract(off)
+  return nu0 + (double)k * dnu;
+}
+
+__device__ __forceinline__ bool in_window(double nuk, double nui, double cut) {
+#pragma clang fp contract(off)
+  return fabs(nuk - nui) <= cut;
+}
+
+// First/last bin of the window clipped to [0, nb-1]; false if empty.  The
+// closed-form bounds widened by two bins are tightened by the exact predicate
+// (the window is contiguous because nu_k and the rounded difference are
+// monotone in k).
+__device__ inline bool line_window(double nui, double cut, double nu0, double dnu, int64_t nb,
+                                   int64_t& klo, int64_t& khi) {
+#pragma clang fp contract(off)
+  double lo = ceil((nui - cut - nu0) / dnu) - 2.0;
+  double hi = floor((nui + cut - nu0) / dnu) + 2.0;
+  if (!(hi >= 0.0) || !(lo <= (double)(nb - 1))) return false;
+  int64_t a = lo < 0.0 ? 0 : (int64_t)lo;
+  int64_t b = hi > (double)(nb - 1) ? nb - 1 : (int64_t)hi;
+  while (a <= b && !in_window(nu_of_bin(nu0, dnu, a), nui, cut)) ++a;
+  while (b >= a && !in_window(nu_of_bin(nu0, dnu, b), nui, cut)) --b;
+  klo = a;
+  khi = b;
+  return a <= b;
+}
+
+// Nearest grid index of nu (the line's home bin) and the residual
+// delta = nu - nu_{k_c} in [-dnu/2, dnu/2] up to rounding.
+__device__ __forceinline__ int64_t home_bin(double nui, double nu0, double dnu) {
+  double t = rint((nui - nu0) / dnu);
+  t = fmin(fmax(t, -4.0e18), 4.0e18);
+  return (int64_t)t;
+}
+
+// ---------------------------------------------------------------------------
+// Line intensity in log form, ln|S| and its sign (nu > 0 assumed):
+//  absorption LTE  (Eq. abs intensity lte):
+//     ln(g_u A / (8 pi c nu^2)) - c2 E_l / T + ln(1 - exp(-c2 nu / T)) - ln Q
+//  absorption 2T   (Eqs. nlte v, nlte ab 2T):
+//     ... - c2 E_l,vib/Tv - c2 E_l,rot/Tr + ln|1 - exp(-c2 (nu_vib/Tv + nu_rot/Tr))| - ln Q
+//     (negative intensity under population inversion)
+//  emission LTE    (Eq. ems intensity lte):  ln(g_u h c A nu / (4 pi)) - c2 E_u / T - ln Q
+//  emission 2T     (Eq. nlte em 2T):         ... - c2 E_u,vib/Tv - c2 E_u,rot/Tr - ln Q
+// (1 - exp(-x)) is formed as -expm1(-x); a per-line log scale s adds s.
+// ---------------------------------------------------------------------------
+// A line is usable only if its state indices (and, for two temperatures,
+// their manifold indices) are inside the caller's tables.
+__device__ __forceinline__ bool line_indices_ok(const StatesView& st, int32_t u, int32_t l, int pop) {
+  if ((uint32_t)u >= (uint64_t)st.n || (uint32_t)l >= (uint64_t)st.n) return false;
+  if (pop == XS_NLTE_2T &&
+      ((uint32_t)st.v[u] >= (uint32_t)st.n_v || (uint32_t)st.v[l] >= (uint32_t)st.n_v))
+    return false;
+  return true;
+}
+
+struct LineState {
+  double Eu, El, gu, evu, evl;
+};
+
+__device__ inline double ln_intensity(int mode, int pop, const LineState& ls, double A,
+                                      double nu, double T, double Tv, double Tr, double lnQ,
+                                      double lscale, int& sign) {
+  sign = 1;
+  double r;
+  if (mode == XS_ABSORPTION) {
+    r = log(ls.gu * A) - log(8.0 * kPI * kC) - 2.0 * log(nu);
+    if (pop == XS_LTE) {
+      r += -kC2 * ls.El / T + log(-expm1(-kC2 * nu / T));
+    } else {
+      double nuv = ls.evu - ls.evl;
+      double nur = (ls.Eu - ls.evu) - (ls.El - ls.evl);
+      double x = kC2 * (nuv / Tv + nur / Tr);
+      double st = -expm1(-x);
+      if (st < 0.0) sign = -1;
+      r += -kC2 * ls.evl / Tv - kC2 * (ls.El - ls.evl) / Tr + log(fabs(st));
+    }
+  } else {
+    r = log(ls.gu * kH * kC * A * nu / (4.0 * kPI));
+    if (pop == XS_LTE)
+      r += -kC2 * ls.Eu / T;
+    else
+      r += -kC2 * ls.evu / Tv - kC2 * (ls.Eu - ls.evu) / Tr;
+  }
+  return r - lnQ + lscale;
+}
+
+// Order-preserving map of doubles to unsigned keys (for an atomic max).
+__device__ __forceinline__ unsigned long long dbl_key(double v) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double key_dbl(unsigned long long k) {
+  unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  return __longlong_as_double((long long)b);
+}
+
+// ---------------------------------------------------------------------------
+// Faddeeva function.  Far region |z| >= 8: the Gauss-Hermite rule with 2P
+// nodes applied to w(z) = (i/pi) int exp(-t^2)/(z - t) dt; each node pair
+// +-t_j contributes (i/pi) W_j 2z/(z^2 - tau_j), tau_j = t_j^2, so with
+// u = x^2 and z^2 = u - y^2 + 2ixy,
+//   Re w = (2y/pi) sum_j W_j (u + y^2 + tau_j) / ((u - y^2 - tau_j)^2 + 4 y^2 u),
+// a sum of positive terms (no cancellation where Re w << |w|).  Near region
+// |z| < 8: Taylor series about the nearest tabulated anchor.
+// ---------------------------------------------------------------------------
+struct GH {
+  static constexpr double t2[1] = XS_GH2_TAU;
+  static constexpr double w2[1] = XS_GH2_W;
+  static constexpr double t4[2] = XS_GH4_TAU;
+  static constexpr double w4[2] = XS_GH4_W;
+  static constexpr double t6[3] = XS_GH6_TAU;
+  static constexpr double w6[3] = XS_GH6_W;
+  static constexpr double t8[4] = XS_GH8_TAU;
+  static constexpr double w8[4] = XS_GH8_W;
+  static constexpr double t12[6] = XS_GH12_TAU;
+  static constexpr double w12[6] = XS_GH12_W;
+};
+
+template <int NP>
+__device__ __forceinline__ const double* gh_tau() {
+  if constexpr (NP == 1) return GH::t2;
+  else if constexpr (NP == 2) return GH::t4;
+  else if constexpr (NP == 3) return GH::t6;
+  else if constexpr (NP == 4) return GH::t8;
+  else return GH::t12;
+}
+template <int NP>
+__device__ __forceinline__ const double* gh_w() {
+  if constexpr (NP == 1) return GH::w2;
+  else if constexpr (NP == 2) return GH::w4;
+  else if constexpr (NP == 3) return GH::w6;
+  else if constexpr (NP == 4) return GH::w8;
+  else return GH::w12;
+}
+
+// sum_j W_j n_j / d_j with n_j = u + y2 + tau_j, d_j = (u - y2 - tau_j)^2 + q u,
+// q = 4 y^2 (the caller multiplies by 2y/pi).  One node pair, or two pairs in
+// FP64: a single division of the combined fraction.  Otherwise one reciprocal
+// per pair: lanes of a row near a narrow line reach u ~ 1e18, where the
+// product of the d_j would overflow (FP32: u > ~1e9; FP64 with 6 pairs:
+// u > ~1e25).
+template <int NP, typename R>
+__device__ __forceinline__ R gh_re_sum(R u, R y2, R q) {
+  const double* tau = gh_tau<NP>();
+  const double* W = gh_w<NP>();
+  const R qu = q * u;
+  if constexpr (NP == 1 || (NP == 2 && sizeof(R) == 8)) {
+    R num = (R)0, den = (R)1;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const R p = y2 + (R)tau[j];
+      const R a = u - p;
+      const R d = fma(a, a, qu);
+      num = fma(num, d, (R)W[j] * (u + p) * den);
+      den = den * d;
+    }
+    if constexpr (sizeof(R) == 4)
+      return num * __builtin_amdgcn_rcpf(den);
+    else
+      return num / den;
+  } else {
+    R sum = (R)0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const R p = y2 + (R)tau[j];
+      const R a = u - p;
+      const R d = fma(a, a, qu);
+      R id;
+      if constexpr (sizeof(R) == 4) id = __builtin_amdgcn_rcpf(d);
+      else id = (R)1 / d;
+      sum = fma((R)W[j] * (u + p), id, sum);
+    }
+    return sum;
+  }
+}
+
+// Taylor series of w about the nearest anchor z0 = STEP (i + i j) of the
+// generated table, K terms; x may be negative (w(-x+iy) = conj w(x+iy)).
+template <int K>
+__device__ inline void w_core(double x, double y, double& wr, double& wi) {
+  const double ax = fabs(x);
+  // nearest anchor, clamped to the table (also for NaN or negative input)
+  const double fi = fmin(fmax(ax * (1.0 / XS_FT_STEP) + 0.5, 0.0), (double)(XS_FT_NA - 1));
+  const double fj = fmin(fmax(y * (1.0 / XS_FT_STEP) + 0.5, 0.0), (double)(XS_FT_NA - 1));
+  const int i = (fi == fi) ? (int)fi : 0;
+  const int j = (fj == fj) ? (int)fj : 0;
+  const double hr = ax - XS_FT_STEP * i, hi = y - XS_FT_STEP * j;
+  const double* c = xs_ft_coef + (size_t)((i * XS_FT_NA + j) * (XS_FT_KMAX + 1)) * 2;
+  double pr = c[2 * K], pi = c[2 * K + 1];
+#pragma unroll
+  for (int k = K - 1; k >= 0; --k) {
+    double nr = fma(pr, hr, fma(-pi, hi, c[2 * k]));
+    double ni = fma(pr, hi, fma(pi, hr, c[2 * k + 1]));
+    pr = nr;
+    pi = ni;
+  }
+  wr = pr;
+  wi = x < 0.0 ? -pi : pi;
+}
+
+// w and w' about the anchor (w' = sum k c_k h^(k-1)).
+template <int K>
+__device__ inline void w_core_d(double x, double y, double& wr, double& wi, double& dr,
+                                double& di) {
+  const double ax = fabs(x);
+  // nearest anchor, clamped to the table (also for NaN or negative input)
+  const double fi = fmin(fmax(ax * (1.0 / XS_FT_STEP) + 0.5, 0.0), (double)(XS_FT_NA - 1));
+  const double fj = fmin(fmax(y * (1.0 / XS_FT_STEP) + 0.5, 0.0), (double)(XS_FT_NA - 1));
+  const int i = (fi == fi) ? (int)fi : 0;
+  const int j = (fj == fj) ? (int)fj : 0;
+  const double hr = ax - XS_FT_STEP * i, hi = y - XS_FT_STEP * j;
+  const double* c = xs_ft_coef + (size_t)((i * XS_FT_NA + j) * (XS_FT_KMAX + 1)) * 2;
+  double pr = c[2 * K], pi = c[2 * K + 1];
+  double qr = K * c[2 * K], qi = K * c[2 * K + 1];
+#pragma unroll
+  for (int k = K - 1; k >= 0; --k) {
+    double nr = fma(pr, hr, fma(-pi, hi, c[2 * k]));
+    double ni = fma(pr, hi, fma(pi, hr, c[2 * k + 1]));
+    pr = nr;
+    pi = ni;
+    if (k >= 1) {
+      double mr = fma(qr, hr, fma(-qi, hi, k * c[2 * k]));
+      double mi = fma(qr, hi, fma(qi, hr, k * c[2 * k + 1]));
+      qr = mr;
+      qi = mi;
+    }
+  }
+  wr = pr;
+  wi = pi;
+  dr = qr;
+  di = qi;
+  if (x < 0.0) {  // w(-conj z) = conj w(z);  w'(-conj z) = -conj w'(z)
+    wi = -wi;
+    dr = -dr;
+  }
+}
+
+// FP64 Re w(x + iy), y >= 0, relative accuracy ~1e-14 (bands chosen per |z|).
+__device__ inline double re_w_f64(double x, double y) {
+  const double u = x * x, y2 = y * y, rho = u + y2, q = 4.0 * y2;
+  const double cy = 2.0 * y / kPI;
+  if (rho >= 9.0e6) return cy * gh_re_sum<1>(u, y2, q);
+  if (rho >= 6400.0) return cy * gh_re_sum<2>(u, y2, q);
+  if (rho >= 400.0) return cy * gh_re_sum<3>(u, y2, q);
+  if (rho >= 144.0) return cy * gh_re_sum<4>(u, y2, q);
+  if (rho >= 64.0) return cy * gh_re_sum<6>(u, y2, q);
+  double wr, wi;
+  w_core<22>(x, y, wr, wi);
+  return wr;
+}
+
+}  // namespace xs

@@ -1,0 +1,464 @@
+// Line-side kernels: partition functions, the intensity pass, bucketing of
+// lines by home bin (stable LSD radix sort) and the sorted line records.
+#include "k_common.h"
+
+namespace xs {
+
+// ---------------------------------------------------------------------------
+// Partition functions, Eq. (pf): Q(T) = sum_n g_n exp(-c2 E_n / T) and
+// dQ/dT = sum_n g_n (c2 E_n / T^2) exp(-c2 E_n / T); two temperatures,
+// Eq. (Q nlte 2T), with E_rot = E - E_vib(v).  FP64, deterministic two-stage
+// tree reduction (per-block partials, then one block per slot).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] += sh[tid + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_partition(ModelDev m, const SlotDev* slots,
+                                                   StatesView st, double* qpart) {
+  __shared__ double sh[256];
+  const int slot = blockIdx.y;
+  const SlotDev sd = slots[slot];
+  double q = 0.0, dq = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < st.n; i += (int64_t)gridDim.x * 256) {
+    const double E = st.E[i];
+    if (m.pop == XS_LTE) {
+      const double b = st.g[i] * exp(-kC2 * E / sd.T);
+      q += b;
+      dq += b * (kC2 * E / (sd.T * sd.T));
+    } else {
+      const int32_t vi = st.v[i];
+      if ((uint32_t)vi < (uint32_t)st.n_v) {  // states with an invalid manifold index are skipped
+        const double ev = st.ev[vi];
+        q += st.g[i] * exp(-kC2 * ev / sd.Tv - kC2 * (E - ev) / sd.Tr);
+      }
+    }
+  }
+  q = block_sum256(q, sh);
+  dq = block_sum256(dq, sh);
+  if (threadIdx.x == 0) {
+    qpart[(slot * 2 + 0) * kQBlocks + blockIdx.x] = q;
+    qpart[(slot * 2 + 1) * kQBlocks + blockIdx.x] = dq;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_partition_final(ModelDev m, const double* qpart,
+                                                         double* Q, double* dQ,
+                                                         unsigned long long* smax) {
+  __shared__ double sh[256];
+  const int slot = blockIdx.x;
+  double q = block_sum256(qpart[(slot * 2 + 0) * kQBlocks + threadIdx.x], sh);
+  double dq = block_sum256(qpart[(slot * 2 + 1) * kQBlocks + threadIdx.x], sh);
+  if (threadIdx.x == 0) {
+    Q[slot] = q;
+    dQ[slot] = (m.pop == XS_LTE) ? dq : __longlong_as_double(0x7ff8000000000000ll);
+    smax[slot] = 0ull;  // reset the running max of ln|S| for the intensity pass
+  }
+}
+
+void launch_partition(const ModelDev& m, const Work& w, const StatesView& st, hipStream_t s) {
+  hipLaunchKernelGGL(k_partition, dim3(kQBlocks, m.n_slots), dim3(256), 0, s, m, w.slot, st,
+                     w.qpart);
+  hipLaunchKernelGGL(k_partition_final, dim3(m.n_slots), dim3(256), 0, s, m, w.qpart, w.Q, w.dQ,
+                     w.smax);
+}
+
+__global__ void k_q_out(ModelDev m, const CondDev* cond, const double* Q, const double* dQ,
+                        double* Qo, double* dQo) {
+  const int c = threadIdx.x;
+  if (c < m.n_cond) {
+    Qo[c] = Q[cond[c].slot];
+    if (dQo) dQo[c] = dQ[cond[c].slot];
+  }
+}
+
+void launch_q_out(const ModelDev& m, const Work& w, double* Q, double* dQ, hipStream_t s) {
+  hipLaunchKernelGGL(k_q_out, dim3(1), dim3(256), 0, s, m, w.cond, w.Q, w.dQ, Q, dQ);
+}
+
+// ---------------------------------------------------------------------------
+// Intensity pass 1: nu_i = E_u - E_l; keep lines with nu > 0 whose window
+// (widest cut-off) reaches the grid; key = bucket of the home bin
+// k_c = rint((nu - nu0)/dnu), clamped to the grid's buckets (lines past
+// either end keep their wings, section "Spectral synthesis"); dropped lines
+// get key n_buckets.  FP32 form: running max of ln|S| per slot.  Counters:
+// kept lines and window pairs (exact windows per distinct cut-off).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ LineState line_state(const StatesView& st, int32_t u, int32_t l,
+                                                int pop) {
+  LineState s;
+  s.Eu = st.E[u];
+  s.El = st.E[l];
+  s.gu = st.g[u];
+  if (pop == XS_NLTE_2T) {
+    s.evu = st.ev[st.v[u]];
+    s.evl = st.ev[st.v[l]];
+  } else {
+    s.evu = s.evl = 0.0;
+  }
+  return s;
+}
+
+__global__ __launch_bounds__(256) void k_lines_pass1(ModelDev m, const SlotDev* slots,
+                                                     const double* Q, const double* cutc,
+                                                     const int32_t* cutm, StatesView st,
+                                                     LinesView ln, int32_t* key,
+                                                     unsigned long long* smax,
+                                                     unsigned long long* stats) {
+  __shared__ double smx[256];
+  __shared__ unsigned long long scnt[3];
+  if (threadIdx.x < 3) scnt[threadIdx.x] = 0;
+  __syncthreads();
+  double lmax[8];
+  for (int q = 0; q < 8; ++q) lmax[q] = -INFINITY;
+  unsigned long long kept = 0, pairs = 0, bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ln.n;
+       i += (int64_t)gridDim.x * 256) {
+    const int32_t u = ln.up[i], l = ln.lo[i];
+    int32_t kk = m.n_buckets;
+    if (!line_indices_ok(st, u, l, m.pop)) {
+      ++bad;
+      key[i] = kk;
+      continue;
+    }
+    const double nu = st.E[u] - st.E[l];
+    int64_t a, b;
+    if (nu > 0.0 && line_window(nu, m.max_cut, m.nu0, m.dnu, m.n_bins, a, b)) {
+      int64_t kc = home_bin(nu, m.nu0, m.dnu);
+      int64_t bk = kc < 0 ? 0 : kc / m.bucket_bins;
+      kk = (int32_t)(bk < m.n_buckets - 1 ? bk : m.n_buckets - 1);
+      ++kept;
+      for (int q = 0; q < m.n_cut_classes; ++q) {
+        if (line_window(nu, cutc[q], m.nu0, m.dnu, m.n_bins, a, b))
+          pairs += (unsigned long long)(b - a + 1) * (unsigned long long)cutm[q];
+      }
+      if (m.prec == XS_FP32) {
+        const LineState ls = line_state(st, u, l, m.pop);
+        const double A = (double)ln.A[i];
+        const double sc = ln.lscale ? (double)ln.lscale[i] : 0.0;
+        for (int q = 0; q < m.n_slots && q < 8; ++q) {
+          const SlotDev sd = slots[q];
+          int sg;
+          double lS = ln_intensity(m.mode, m.pop, ls, A, nu, sd.T, sd.Tv, sd.Tr, log(Q[q]), sc, sg);
+          if (lS > lmax[q]) lmax[q] = lS;
+        }
+        for (int q = 8; q < m.n_slots; ++q) {  // rare: more than 8 temperatures
+          const SlotDev sd = slots[q];
+          int sg;
+          double lS = ln_intensity(m.mode, m.pop, ls, A, nu, sd.T, sd.Tv, sd.Tr, log(Q[q]), sc, sg);
+          if (lS > -INFINITY) atomicMax(smax + q, dbl_key(lS));
+        }
+      }
+    }
+    key[i] = kk;
+  }
+  atomicAdd(&scnt[0], kept);
+  atomicAdd(&scnt[1], pairs);
+  atomicAdd(&scnt[2], bad);
+  if (m.prec == XS_FP32) {
+    for (int q = 0; q < m.n_slots && q < 8; ++q) {
+      smx[threadIdx.x] = lmax[q];
+      __syncthreads();
+      for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) smx[threadIdx.x] = fmax(smx[threadIdx.x], smx[threadIdx.x + s2]);
+        __syncthreads();
+      }
+      if (threadIdx.x == 0 && smx[0] > -INFINITY) atomicMax(smax + q, dbl_key(smx[0]));
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(stats + 1, scnt[0]);
+    atomicAdd(stats + 2, scnt[1]);
+    atomicAdd(stats + 3, scnt[2]);
+  }
+}
+
+__global__ void k_scale_final(ModelDev m, const unsigned long long* smax, double* sb) {
+  const int q = threadIdx.x;
+  if (q < m.n_slots) sb[q] = smax[q] ? key_dbl(smax[q]) : 0.0;
+}
+
+void launch_lines_pass1(const ModelDev& m, const Work& w, const StatesView& st,
+                        const LinesView& ln, hipStream_t s) {
+  int64_t blocks = (ln.n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_lines_pass1, dim3((unsigned)blocks), dim3(256), 0, s, m, w.slot, w.Q,
+                     w.cut_class, w.cut_mult, st, ln, w.key, w.smax, w.stats);
+  hipLaunchKernelGGL(k_scale_final, dim3(1), dim3(256), 0, s, m, w.smax, w.sb);
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of the bucket keys, 8 bits per pass.  Each block owns
+// kSortBlock consecutive keys.  Pass: (1) per-block digit histogram;
+// (2) exclusive scan of the digit-major [256][blocks] table; (3) stable
+// scatter: the rank of a key among equal digits of its block is the running
+// count from earlier steps + the counts of earlier waves in this step + the
+// number of earlier lanes of its wave with the same digit (8 ballots).
+// Stability makes the sorted order, and so every later summation order,
+// deterministic.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sort_hist(const int32_t* keys, int64_t n, int shift,
+                                                   int32_t* hist, int nblk) {
+  __shared__ int h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortBlock;
+  for (int s = 0; s < kSortItems; ++s) {
+    const int64_t i = base + s * 256 + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+  }
+  __syncthreads();
+  hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of int32 arrays: per-block scan of 1024 elements, block sums
+// scanned by one block, then added back.
+__device__ __forceinline__ int block_excl_scan256(int v, int* sh, int& total) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    int t = tid >= o ? sh[tid - o] : 0;
+    __syncthreads();
+    sh[tid] += t;
+    __syncthreads();
+  }
+  int incl = sh[tid];
+  total = sh[255];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_blocks(int32_t* a, int64_t n, int32_t* sums) {
+  __shared__ int sh[256];
+  const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x * 4;
+  int v[4], s = 0;
+  for (int j = 0; j < 4; ++j) {
+    v[j] = (base + j < n) ? a[base + j] : 0;
+    s += v[j];
+  }
+  int total;
+  int ex = block_excl_scan256(s, sh, total);
+  for (int j = 0; j < 4; ++j) {
+    if (base + j < n) a[base + j] = ex;
+    ex += v[j];
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void k_scan_sums(int32_t* sums, int64_t n) {
+  __shared__ int sh[256];
+  int carry = 0;
+  for (int64_t b0 = 0; b0 < n; b0 += 256) {
+    const int64_t i = b0 + threadIdx.x;
+    int v = i < n ? sums[i] : 0;
+    int total;
+    int ex = block_excl_scan256(v, sh, total);
+    if (i < n) sums[i] = ex + carry;
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(int32_t* a, int64_t n, const int32_t* sums) {
+  const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x * 4;
+  const int add = sums[blockIdx.x];
+  for (int j = 0; j < 4; ++j)
+    if (base + j < n) a[base + j] += add;
+}
+
+__global__ __launch_bounds__(256) void k_sort_scatter(const int32_t* keys, const int32_t* vals,
+                                                      int64_t n, int shift, const int32_t* offs,
+                                                      int nblk, int32_t* okeys, int32_t* ovals) {
+  __shared__ int run[256];
+  __shared__ int wc[4][256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  run[tid] = offs[tid * nblk + blockIdx.x];
+  wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortBlock;
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int s = 0; s < kSortItems; ++s) {
+    const int64_t i = base + s * 256 + tid;
+    const bool act = i < n;
+    const int k = act ? keys[i] : 0;
+    const int d = (k >> shift) & 255;
+    unsigned long long same = __ballot(act);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const unsigned long long bb = __ballot(act && ((d >> b) & 1));
+      same &= ((d >> b) & 1) ? bb : ~bb;
+    }
+    const int rank = __popcll(same & lt);
+    const bool leader = act && rank == 0;
+    if (leader) wc[wave][d] = __popcll(same);
+    __syncthreads();
+    if (act) {
+      int pos = run[d] + rank;
+      for (int w2 = 0; w2 < wave; ++w2) pos += wc[w2][d];
+      okeys[pos] = k;
+      ovals[pos] = vals ? vals[i] : (int32_t)i;
+    }
+    __syncthreads();
+    run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+    wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0;
+    __syncthreads();
+  }
+}
+
+static void scan_excl(int32_t* a, int64_t n, int32_t* sums, hipStream_t s) {
+  const int64_t nb = (n + 1023) / 1024;
+  hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(256), 0, s, a, n, sums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, sums, nb);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(256), 0, s, a, n, sums);
+}
+
+void launch_radix_sort(const ModelDev& m, const Work& w, int64_t n, hipStream_t s,
+                       int32_t** sorted_keys, int32_t** sorted_vals) {
+  int bits = 1;
+  while ((1ll << bits) <= (long long)m.n_buckets) ++bits;
+  const int passes = (bits + 7) / 8;
+  const int nblk = (int)((n + kSortBlock - 1) / kSortBlock);
+  const int32_t* ik = w.key;
+  const int32_t* iv = nullptr;
+  int32_t* ok = w.keyA;
+  int32_t* ov = w.valA;
+  for (int p = 0; p < passes; ++p) {
+    if (nblk > 0) {
+      hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(256), 0, s, ik, n, 8 * p, w.hist, nblk);
+      scan_excl(w.hist, (int64_t)256 * nblk, w.hsum, s);
+      hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(256), 0, s, ik, iv, n, 8 * p, w.hist,
+                         nblk, ok, ov);
+    }
+    ik = ok;
+    iv = ov;
+    ok = (ok == w.keyA) ? w.keyB : w.keyA;
+    ov = (ov == w.valA) ? w.valB : w.valA;
+  }
+  *sorted_keys = const_cast<int32_t*>(ik);
+  *sorted_vals = const_cast<int32_t*>(iv);
+}
+
+// ---------------------------------------------------------------------------
+// Bucket offsets from the sorted keys (position n acts as key n_buckets + 1,
+// so every bucket 0..n_buckets gets its start; off[n_buckets] = kept lines),
+// and the sorted line records: nu, gamma_ref, n_exp, original index, and the
+// intensity of every slot, S (FP64) or S~ = sign exp(ln|S| - s_b) (FP32).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_offsets(const int32_t* skeys, int64_t n, int nbk,
+                                                 int32_t* off) {
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p <= n;
+       p += (int64_t)gridDim.x * 256) {
+    const int k = (p < n) ? skeys[p] : nbk + 1;
+    const int kp = (p > 0) ? skeys[p - 1] : -1;
+    for (int b = kp + 1; b <= k && b <= nbk; ++b) off[b] = (int32_t)p;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_records(ModelDev m, const SlotDev* slots, const double* Q,
+                                                 const double* sb, StatesView st, LinesView ln,
+                                                 const int32_t* svals, const int32_t* off,
+                                                 int64_t max_lines, double* rnu, float* rgref,
+                                                 float* rnexp, int32_t* ridx, void* rS) {
+  const int64_t nk = off[m.n_buckets];
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < nk;
+       p += (int64_t)gridDim.x * 256) {
+    const int32_t i = svals[p];
+    const int32_t u = ln.up[i], l = ln.lo[i];
+    const double nu = st.E[u] - st.E[l];
+    rnu[p] = nu;
+    rgref[p] = ln.gref ? ln.gref[i] : (float)ln.gref_scalar;
+    rnexp[p] = ln.nexp ? ln.nexp[i] : (float)ln.nexp_scalar;
+    ridx[p] = i;
+    const LineState ls = line_state(st, u, l, m.pop);
+    const double A = (double)ln.A[i];
+    const double sc = ln.lscale ? (double)ln.lscale[i] : 0.0;
+    for (int q = 0; q < m.n_slots; ++q) {
+      const SlotDev sd = slots[q];
+      int sg;
+      const double lS = ln_intensity(m.mode, m.pop, ls, A, nu, sd.T, sd.Tv, sd.Tr, log(Q[q]), sc, sg);
+      if (m.prec == XS_FP32)
+        ((float*)rS)[(int64_t)q * max_lines + p] = (float)(sg * exp(lS - sb[q]));
+      else
+        ((double*)rS)[(int64_t)q * max_lines + p] = sg * exp(lS);
+    }
+  }
+}
+
+void launch_offsets_records(const ModelDev& m, const Work& w, const StatesView& st,
+                            const LinesView& ln, const int32_t* skeys, const int32_t* svals,
+                            int64_t n, hipStream_t s) {
+  int64_t blocks = (n + 256) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_offsets, dim3((unsigned)blocks), dim3(256), 0, s, skeys, n, m.n_buckets,
+                     w.off);
+  hipLaunchKernelGGL(k_records, dim3((unsigned)blocks), dim3(256), 0, s, m, w.slot, w.Q, w.sb, st,
+                     ln, svals, w.off, w.max_lines, w.rnu, w.rgref, w.rnexp, w.ridx, w.rS);
+}
+
+// ---------------------------------------------------------------------------
+// Stick spectrum output: S of every line for every condition, original order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_intensity_out(ModelDev m, const CondDev* cond,
+                                                       const SlotDev* slots, const double* Q,
+                                                       const double* sb, StatesView st,
+                                                       LinesView ln, void* S, double* lsc) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ln.n;
+       i += (int64_t)gridDim.x * 256) {
+    const int32_t u = ln.up[i], l = ln.lo[i];
+    const bool ok = line_indices_ok(st, u, l, m.pop);
+    const double nu = ok ? st.E[u] - st.E[l] : 0.0;
+    const LineState ls = ok ? line_state(st, u, l, m.pop) : LineState{0, 0, 0, 0, 0};
+    const double A = (double)ln.A[i];
+    const double sc = ln.lscale ? (double)ln.lscale[i] : 0.0;
+    for (int c = 0; c < m.n_cond; ++c) {
+      const int q = cond[c].slot;
+      const SlotDev sd = slots[q];
+      double v = 0.0;
+      if (nu > 0.0) {
+        int sg;
+        const double lS = ln_intensity(m.mode, m.pop, ls, A, nu, sd.T, sd.Tv, sd.Tr, log(Q[q]), sc, sg);
+        v = (m.prec == XS_FP32) ? sg * exp(lS - sb[q]) : sg * exp(lS);
+      }
+      if (m.prec == XS_FP32)
+        ((float*)S)[(int64_t)c * ln.n + i] = (float)v;
+      else
+        ((double*)S)[(int64_t)c * ln.n + i] = v;
+    }
+  }
+  if (lsc && blockIdx.x == 0 && threadIdx.x < m.n_cond) lsc[threadIdx.x] = sb[cond[threadIdx.x].slot];
+}
+
+void launch_intensity_out(const ModelDev& m, const Work& w, const StatesView& st,
+                          const LinesView& ln, void* S, double* log_scale, hipStream_t s) {
+  int64_t blocks = (ln.n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_intensity_out, dim3((unsigned)blocks), dim3(256), 0, s, m, w.cond, w.slot,
+                     w.Q, w.sb, st, ln, S, log_scale);
+}
+
+// Clear the per-call counters and the work queue (a kernel, not a memset, so
+// the step can be captured in a graph).
+__global__ void k_reset(int32_t* counter, unsigned long long* stats) {
+  const int t = threadIdx.x;
+  if (t < 64) counter[t] = 0;
+  if (t < 8) stats[t] = 0ull;
+}
+
+void launch_reset(const Work& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, w.counter, w.stats);
+}
+
+}  // namespace xs

@@ -1,0 +1,707 @@
+// Host runtime of the cross-section library: the C-ABI of include/xsec.h.
+//
+// A plan holds the model, grid and conditions, the kernel configuration and
+// the caller-bound device workspace.  Each call validates every argument on
+// the host first (no HIP call before validation succeeds), then enqueues the
+// path on the plan's stream:
+//   partition functions -> intensity pass 1 (keys, ln S max) -> stable radix
+//   sort by bucket -> bucket offsets + sorted records -> profile pass
+//   (gather or scatter) [-> adjoint].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "xsec_internal.h"
+
+using namespace xs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+bool finite(double v) { return std::isfinite(v); }
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return XS_EDEVICE;
+  }
+  return XS_OK;
+}
+
+}  // namespace
+
+struct xs_plan {
+  xs_model model;
+  xs_grid grid;
+  std::vector<xs_condition> conds;
+  int64_t max_lines;
+  hipStream_t stream;
+  int device;
+  int n_cu;
+  std::string arch;
+  // derived
+  ModelDev md;
+  std::vector<CondDev> cdev;
+  std::vector<SlotDev> sdev;
+  std::vector<double> cut_class;
+  std::vector<int32_t> cut_mult;
+  Tiling tiling;
+  int32_t bucket_bins;
+  // workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  Work w;
+  // graph
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int64_t last_lines_in = 0;
+};
+
+namespace {
+
+int validate_model(const xs_model* m) {
+  if (!m) return fail(XS_EINVAL, "model is NULL");
+  if (m->profile < XS_DOPPLER || m->profile > XS_VOIGT) return fail(XS_EINVAL, "model.profile out of range");
+  if (m->mode < XS_ABSORPTION || m->mode > XS_EMISSION) return fail(XS_EINVAL, "model.mode out of range");
+  if (m->population < XS_LTE || m->population > XS_NLTE_2T) return fail(XS_EINVAL, "model.population out of range");
+  if (m->precision < XS_FP64 || m->precision > XS_FP32) return fail(XS_EINVAL, "model.precision out of range");
+  if (m->algo < XS_GATHER || m->algo > XS_SCATTER) return fail(XS_EINVAL, "model.algo out of range");
+  if ((m->profile == XS_DOPPLER || m->profile == XS_VOIGT) && !(m->mass_amu > 0.0 && finite(m->mass_amu)))
+    return fail(XS_EINVAL, "model.mass_amu must be > 0");
+  if (!(m->T_ref > 0.0 && finite(m->T_ref))) return fail(XS_EINVAL, "model.T_ref must be > 0");
+  if (!(m->P_ref > 0.0 && finite(m->P_ref))) return fail(XS_EINVAL, "model.P_ref must be > 0");
+  if (m->profile == XS_GAUSSIAN && !(m->hwhm_fixed > 0.0 && finite(m->hwhm_fixed)))
+    return fail(XS_EINVAL, "model.hwhm_fixed must be > 0 for XS_GAUSSIAN");
+  return XS_OK;
+}
+
+int validate_grid(const xs_grid* g) {
+  if (!g) return fail(XS_EINVAL, "grid is NULL");
+  if (!finite(g->nu0)) return fail(XS_EINVAL, "grid.nu0 not finite");
+  if (!(g->dnu > 0.0 && finite(g->dnu))) return fail(XS_EINVAL, "grid.dnu must be > 0");
+  if (g->n_bins < 1 || g->n_bins > (int64_t(1) << 30)) return fail(XS_EINVAL, "grid.n_bins must be in [1, 2^30]");
+  return XS_OK;
+}
+
+int validate_conds(const xs_model* m, const xs_grid* g, int32_t n, const xs_condition* c) {
+  if (n < 1 || n > kMaxCond) return fail(XS_EINVAL, "n_cond must be in [1, 256]");
+  if (!c) return fail(XS_EINVAL, "conditions are NULL");
+  for (int i = 0; i < n; ++i) {
+    const xs_condition& q = c[i];
+    std::string id = "condition " + std::to_string(i) + ": ";
+    if (!(q.cutoff > 0.0 && finite(q.cutoff))) return fail(XS_EINVAL, id + "cutoff must be > 0");
+    if (q.cutoff / g->dnu > double(1 << 28)) return fail(XS_EINVAL, id + "cutoff / dnu too large");
+    if (!(q.P >= 0.0 && finite(q.P))) return fail(XS_EINVAL, id + "P must be >= 0");
+    if (m->profile == XS_LORENTZ && !(q.P > 0.0)) return fail(XS_EINVAL, id + "P must be > 0 for XS_LORENTZ");
+    if (m->population == XS_LTE) {
+      if (!(q.T > 0.0 && finite(q.T))) return fail(XS_EINVAL, id + "T must be > 0");
+    } else {
+      if (!(q.T_vib > 0.0 && finite(q.T_vib))) return fail(XS_EINVAL, id + "T_vib must be > 0");
+      if (!(q.T_rot > 0.0 && finite(q.T_rot))) return fail(XS_EINVAL, id + "T_rot must be > 0");
+    }
+  }
+  return XS_OK;
+}
+
+int validate_states(const xs_plan* p, const xs_states* s) {
+  if (!s) return fail(XS_EINVAL, "states is NULL");
+  if (s->n < 1 || s->n > (int64_t(1) << 31) - 1) return fail(XS_EINVAL, "states.n must be in [1, 2^31-1]");
+  if (!s->energy || !s->g_tot) return fail(XS_EINVAL, "states.energy / states.g_tot is NULL");
+  if (p->model.population == XS_NLTE_2T) {
+    if (!s->v || !s->e_vib) return fail(XS_EINVAL, "two-temperature runs need states.v and states.e_vib");
+    if (s->n_v < 1) return fail(XS_EINVAL, "states.n_v must be >= 1");
+  }
+  return XS_OK;
+}
+
+int validate_lines(const xs_plan* p, const xs_lines* l) {
+  if (!l) return fail(XS_EINVAL, "lines is NULL");
+  if (l->n < 0 || l->n > p->max_lines) return fail(XS_EINVAL, "lines.n must be in [0, max_lines]");
+  if (l->n > 0 && (!l->upper || !l->lower || !l->einstein_a))
+    return fail(XS_EINVAL, "lines.upper / lower / einstein_a is NULL");
+  const int prof = p->model.profile;
+  if ((prof == XS_LORENTZ || prof == XS_VOIGT)) {
+    if (!l->gamma_ref && !(l->gamma_ref_scalar >= 0.0 && finite(l->gamma_ref_scalar)))
+      return fail(XS_EINVAL, "lines.gamma_ref_scalar must be >= 0");
+    if (!l->n_exp && !finite(l->n_exp_scalar)) return fail(XS_EINVAL, "lines.n_exp_scalar not finite");
+  }
+  return XS_OK;
+}
+
+int validate_config(const xs_config* c) {
+  if (!c) return fail(XS_EINVAL, "config is NULL");
+  const int t = c->tile_bins;
+  const bool ok_tile = (t == 512 || t == 1024 || t == 2048);
+  if (!ok_tile) return fail(XS_EINVAL, "config.tile_bins must be 512, 1024 or 2048");
+  const int b = c->bucket_bins;
+  if (b < 64 || b > 4096 || (b & (b - 1))) return fail(XS_EINVAL, "config.bucket_bins must be a power of two in [64, 4096]");
+  if (c->persistent != 0 && c->persistent != 1) return fail(XS_EINVAL, "config.persistent must be 0 or 1");
+  if (c->waves_per_cu < 4 || c->waves_per_cu > 64) return fail(XS_EINVAL, "config.waves_per_cu must be in [4, 64]");
+  return XS_OK;
+}
+
+StatesView view(const xs_states* s) {
+  StatesView v;
+  v.n = s->n;
+  v.E = s->energy;
+  v.g = s->g_tot;
+  v.v = s->v;
+  v.ev = s->e_vib;
+  v.n_v = s->n_v;
+  return v;
+}
+
+LinesView view(const xs_lines* l) {
+  LinesView v;
+  v.n = l->n;
+  v.up = l->upper;
+  v.lo = l->lower;
+  v.A = l->einstein_a;
+  v.gref = l->gamma_ref;
+  v.nexp = l->n_exp;
+  v.lscale = l->log_scale;
+  v.gref_scalar = l->gamma_ref_scalar;
+  v.nexp_scalar = l->n_exp_scalar;
+  return v;
+}
+
+// Tile shape for a tile size: 64 lanes x per_lane bins x waves.
+void tiling_for(xs_plan* p, int tile_bins, int persistent, int waves_per_cu) {
+  Tiling t;
+  t.tile_bins = tile_bins;
+  t.waves = 4;
+  t.per_lane = tile_bins / 256;
+  if (tile_bins == 2048) {  // 8 bins per lane, 4 waves
+    t.per_lane = 8;
+  }
+  t.persistent = persistent;
+  t.grid_blocks = std::max(1, p->n_cu * waves_per_cu / t.waves);
+  p->tiling = t;
+}
+
+void derive(xs_plan* p) {
+  const xs_model& m = p->model;
+  ModelDev& d = p->md;
+  d.profile = m.profile;
+  d.mode = m.mode;
+  d.pop = m.population;
+  d.prec = m.precision;
+  d.nu0 = p->grid.nu0;
+  d.dnu = p->grid.dnu;
+  d.n_bins = p->grid.n_bins;
+  d.T_ref = m.T_ref;
+  d.P_ref = m.P_ref;
+  d.hwhm_fixed = m.hwhm_fixed;
+  d.mass_amu = m.mass_amu;
+  d.n_cond = (int32_t)p->conds.size();
+  d.bucket_bins = p->bucket_bins;
+  d.n_buckets = (int32_t)((p->grid.n_bins + p->bucket_bins - 1) / p->bucket_bins);
+  // intensity slots: distinct population temperatures
+  p->sdev.clear();
+  p->cdev.clear();
+  p->cut_class.clear();
+  p->cut_mult.clear();
+  double maxcut = 0.0;
+  for (const xs_condition& c : p->conds) {
+    SlotDev s;
+    if (m.population == XS_LTE) {
+      s.T = c.T;
+      s.Tv = c.T;
+      s.Tr = c.T;
+    } else {
+      s.T = c.T_rot;
+      s.Tv = c.T_vib;
+      s.Tr = c.T_rot;
+    }
+    int slot = -1;
+    for (size_t q = 0; q < p->sdev.size(); ++q)
+      if (p->sdev[q].Tv == s.Tv && p->sdev[q].Tr == s.Tr) slot = (int)q;
+    if (slot < 0) {
+      slot = (int)p->sdev.size();
+      p->sdev.push_back(s);
+    }
+    CondDev cd;
+    cd.T = c.T;
+    cd.P = c.P;
+    cd.Tv = c.T_vib;
+    cd.Tr = c.T_rot;
+    cd.cut = c.cutoff;
+    cd.Tk = (m.population == XS_LTE) ? c.T : c.T_rot;
+    cd.dop = (m.profile == XS_GAUSSIAN || m.profile == XS_LORENTZ)
+                 ? 0.0
+                 : std::sqrt(2.0 * kKB * cd.Tk * kLN2 / (m.mass_amu * kAMU)) / kC;
+    cd.hwhm = m.hwhm_fixed;
+    cd.lnTr = std::log(m.T_ref / cd.Tk);
+    cd.pfac = c.P / m.P_ref;
+    cd.slot = slot;
+    cd.wbins = (int32_t)std::ceil(c.cutoff / p->grid.dnu) + 2;
+    p->cdev.push_back(cd);
+    maxcut = std::max(maxcut, c.cutoff);
+    int cc = -1;
+    for (size_t q = 0; q < p->cut_class.size(); ++q)
+      if (p->cut_class[q] == c.cutoff) cc = (int)q;
+    if (cc < 0) {
+      p->cut_class.push_back(c.cutoff);
+      p->cut_mult.push_back(1);
+    } else {
+      p->cut_mult[cc] += 1;
+    }
+  }
+  d.n_slots = (int32_t)p->sdev.size();
+  d.n_cut_classes = (int32_t)p->cut_class.size();
+  d.max_cut = maxcut;
+}
+
+size_t layout(xs_plan* p, char* base, Work* w) {
+  const ModelDev& d = p->md;
+  const int64_t L = p->max_lines;
+  const int nsb = (int)((L + kSortBlock - 1) / kSortBlock);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + std::max<size_t>(bytes, 1));
+    return base ? (void*)(base + at) : nullptr;
+  };
+  Work x;
+  x.cond = (CondDev*)take(sizeof(CondDev) * d.n_cond);
+  x.slot = (SlotDev*)take(sizeof(SlotDev) * d.n_slots);
+  x.model = (ModelDev*)take(sizeof(ModelDev));
+  x.qpart = (double*)take(sizeof(double) * d.n_slots * 2 * kQBlocks);
+  x.Q = (double*)take(sizeof(double) * d.n_slots);
+  x.dQ = (double*)take(sizeof(double) * d.n_slots);
+  x.smax = (unsigned long long*)take(8 * d.n_slots);
+  x.sb = (double*)take(8 * d.n_slots);
+  x.key = (int32_t*)take(4 * L);
+  x.keyA = (int32_t*)take(4 * L);
+  x.keyB = (int32_t*)take(4 * L);
+  x.valA = (int32_t*)take(4 * L);
+  x.valB = (int32_t*)take(4 * L);
+  x.hist = (int32_t*)take(4 * (size_t)256 * nsb);
+  x.hsum = (int32_t*)take(4 * ((size_t)256 * nsb / 1024 + 2));
+  x.off = (int32_t*)take(4 * (size_t)(d.n_buckets + 2));
+  x.rnu = (double*)take(8 * L);
+  x.rgref = (float*)take(4 * L);
+  x.rnexp = (float*)take(4 * L);
+  x.ridx = (int32_t*)take(4 * L);
+  x.rS = take((size_t)(d.prec == XS_FP32 ? 4 : 8) * d.n_slots * L);
+  x.counter = (int32_t*)take(4 * 64);
+  x.stats = (unsigned long long*)take(8 * 8);
+  x.adjpart = (double*)take(sizeof(double) * d.n_cond * 2 * kAdjBlocks);
+  x.cut_class = (double*)take(sizeof(double) * d.n_cut_classes);
+  x.cut_mult = (int32_t*)take(sizeof(int32_t) * d.n_cut_classes);
+  x.max_lines = L;
+  x.n_sort_blocks = nsb;
+  if (w) *w = x;
+  return o;
+}
+
+int upload(xs_plan* p) {
+  const ModelDev& d = p->md;
+  int rc;
+  if ((rc = hip_check(hipMemcpyAsync(p->w.cond, p->cdev.data(), sizeof(CondDev) * d.n_cond,
+                                     hipMemcpyHostToDevice, p->stream), "upload conditions")))
+    return rc;
+  if ((rc = hip_check(hipMemcpyAsync(p->w.slot, p->sdev.data(), sizeof(SlotDev) * d.n_slots,
+                                     hipMemcpyHostToDevice, p->stream), "upload slots")))
+    return rc;
+  if ((rc = hip_check(hipMemcpyAsync(p->w.model, &p->md, sizeof(ModelDev), hipMemcpyHostToDevice,
+                                     p->stream), "upload model")))
+    return rc;
+  if ((rc = hip_check(hipMemcpyAsync(p->w.cut_class, p->cut_class.data(),
+                                     sizeof(double) * d.n_cut_classes, hipMemcpyHostToDevice,
+                                     p->stream), "upload cut-offs")))
+    return rc;
+  if ((rc = hip_check(hipMemcpyAsync(p->w.cut_mult, p->cut_mult.data(),
+                                     sizeof(int32_t) * d.n_cut_classes, hipMemcpyHostToDevice,
+                                     p->stream), "upload cut-off counts")))
+    return rc;
+  return hip_check(hipStreamSynchronize(p->stream), "upload sync");
+}
+
+// Everything up to the sorted records; returns XS_OK once enqueued.
+int preprocess(xs_plan* p, const xs_states* st, const xs_lines* ln) {
+  const StatesView sv = view(st);
+  const LinesView lv = view(ln);
+  launch_reset(p->w, p->stream);
+  launch_partition(p->md, p->w, sv, p->stream);
+  launch_lines_pass1(p->md, p->w, sv, lv, p->stream);
+  int32_t *sk = nullptr, *svv = nullptr;
+  launch_radix_sort(p->md, p->w, lv.n, p->stream, &sk, &svv);
+  launch_offsets_records(p->md, p->w, sv, lv, sk ? sk : p->w.keyA, svv ? svv : p->w.valA, lv.n,
+                         p->stream);
+  p->last_lines_in = lv.n;
+  return hip_check(hipGetLastError(), "preprocess launch");
+}
+
+int profile_pass(xs_plan* p, double* sigma, int accumulate) {
+  if (p->model.algo == XS_SCATTER)
+    launch_scatter(p->md, p->w, sigma, accumulate, 0, p->stream);
+  else
+    launch_gather(p->md, p->w, p->tiling, sigma, accumulate, p->stream);
+  return hip_check(hipGetLastError(), "profile launch");
+}
+
+int check_call(xs_plan* p, const xs_states* st, const xs_lines* ln) {
+  if (!p) return fail(XS_EINVAL, "plan is NULL");
+  if (!p->ws) return fail(XS_EWORKSPACE, "no workspace bound (xs_plan_set_workspace)");
+  int rc;
+  if ((rc = validate_states(p, st))) return rc;
+  if (ln && (rc = validate_lines(p, ln))) return rc;
+  return XS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* xs_last_error(void) { return g_err.c_str(); }
+
+const char* xs_version(void) { return "xsec 0.1 (gfx950)"; }
+
+int xs_plan_create(xs_plan** out, const xs_model* model, const xs_grid* grid, int32_t n_cond,
+                   const xs_condition* conds, int64_t max_lines, void* stream) {
+  if (!out) return fail(XS_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc;
+  if ((rc = validate_model(model))) return rc;
+  if ((rc = validate_grid(grid))) return rc;
+  if ((rc = validate_conds(model, grid, n_cond, conds))) return rc;
+  if (max_lines < 1 || max_lines > (int64_t(1) << 31) - 1)
+    return fail(XS_EINVAL, "max_lines must be in [1, 2^31-1]");
+  xs_plan* p = new (std::nothrow) xs_plan();
+  if (!p) return fail(XS_ENOMEM, "plan allocation failed");
+  p->model = *model;
+  p->grid = *grid;
+  p->conds.assign(conds, conds + n_cond);
+  p->max_lines = max_lines;
+  p->stream = (hipStream_t)stream;
+  p->bucket_bins = 256;
+  if ((rc = hip_check(hipGetDevice(&p->device), "hipGetDevice"))) {
+    delete p;
+    return rc;
+  }
+  hipDeviceProp_t prop;
+  if ((rc = hip_check(hipGetDeviceProperties(&prop, p->device), "hipGetDeviceProperties"))) {
+    delete p;
+    return rc;
+  }
+  p->n_cu = prop.multiProcessorCount;
+  p->arch = prop.gcnArchName;
+  derive(p);
+  tiling_for(p, 1024, 1, 16);
+  std::memset(&p->w, 0, sizeof(p->w));
+  *out = p;
+  g_err.clear();
+  return XS_OK;
+}
+
+int xs_plan_set_conditions(xs_plan* p, int32_t n_cond, const xs_condition* conds) {
+  if (!p) return fail(XS_EINVAL, "plan is NULL");
+  if (n_cond != (int32_t)p->conds.size()) return fail(XS_EINVAL, "n_cond differs from the plan's");
+  int rc;
+  if ((rc = validate_conds(&p->model, &p->grid, n_cond, conds))) return rc;
+  p->conds.assign(conds, conds + n_cond);
+  const int32_t old_slots = p->md.n_slots, old_cc = p->md.n_cut_classes;
+  derive(p);
+  if (p->md.n_slots > old_slots || p->md.n_cut_classes > old_cc) {
+    // more intensity slots or cut-off classes than the workspace was carved for
+    if (p->ws && p->ws_bytes < layout(p, nullptr, nullptr)) {
+      p->ws = nullptr;
+      return fail(XS_EWORKSPACE, "workspace too small for the new conditions; rebind it");
+    }
+  }
+  if (p->gexec) {
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+  }
+  if (p->graph) {
+    (void)hipGraphDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  if (p->ws) {
+    layout(p, (char*)p->ws, &p->w);
+    return upload(p);
+  }
+  return XS_OK;
+}
+
+void xs_plan_destroy(xs_plan* p) {
+  if (!p) return;
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  delete p;
+}
+
+int xs_plan_workspace_bytes(const xs_plan* p, size_t* bytes) {
+  if (!p || !bytes) return fail(XS_EINVAL, "plan or bytes is NULL");
+  *bytes = layout(const_cast<xs_plan*>(p), nullptr, nullptr);
+  return XS_OK;
+}
+
+int xs_plan_set_workspace(xs_plan* p, void* dptr, size_t bytes) {
+  if (!p) return fail(XS_EINVAL, "plan is NULL");
+  if (!dptr || ((uintptr_t)dptr & 255)) return fail(XS_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  size_t need = layout(p, nullptr, nullptr);
+  if (bytes < need) return fail(XS_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  p->ws = dptr;
+  p->ws_bytes = bytes;
+  layout(p, (char*)dptr, &p->w);
+  return upload(p);
+}
+
+int xs_plan_set_config(xs_plan* p, const xs_config* c) {
+  if (!p) return fail(XS_EINVAL, "plan is NULL");
+  int rc;
+  if ((rc = validate_config(c))) return rc;
+  if (c->bucket_bins != p->bucket_bins) {
+    p->bucket_bins = c->bucket_bins;
+    derive(p);
+    if (p->ws) {  // the bucket table size changed: re-carve and re-upload
+      size_t need = layout(p, nullptr, nullptr);
+      if (p->ws_bytes < need) {
+        p->ws = nullptr;
+        return fail(XS_EWORKSPACE, "workspace too small for the new bucket size; rebind it");
+      }
+      layout(p, (char*)p->ws, &p->w);
+      if ((rc = upload(p))) return rc;
+    }
+  }
+  tiling_for(p, c->tile_bins, c->persistent, c->waves_per_cu);
+  return XS_OK;
+}
+
+int xs_plan_get_config(const xs_plan* p, xs_config* c) {
+  if (!p || !c) return fail(XS_EINVAL, "plan or config is NULL");
+  c->tile_bins = p->tiling.tile_bins;
+  c->bucket_bins = p->bucket_bins;
+  c->persistent = p->tiling.persistent;
+  c->waves_per_cu = p->tiling.grid_blocks * p->tiling.waves / std::max(1, p->n_cu);
+  return XS_OK;
+}
+
+int xs_partition_function(xs_plan* p, const xs_states* st, double* Q, double* dQdT) {
+  int rc;
+  if ((rc = check_call(p, st, nullptr))) return rc;
+  if (!Q) return fail(XS_EINVAL, "Q is NULL");
+  launch_partition(p->md, p->w, view(st), p->stream);
+  launch_q_out(p->md, p->w, Q, dQdT, p->stream);
+  return hip_check(hipGetLastError(), "partition launch");
+}
+
+int xs_line_intensities(xs_plan* p, const xs_states* st, const xs_lines* ln, void* S,
+                        double* log_scale) {
+  int rc;
+  if ((rc = check_call(p, st, ln))) return rc;
+  if (!S && ln->n > 0) return fail(XS_EINVAL, "S is NULL");
+  if (p->model.precision == XS_FP32 && !log_scale) return fail(XS_EINVAL, "log_scale is NULL (FP32 form)");
+  const StatesView sv = view(st);
+  const LinesView lv = view(ln);
+  launch_reset(p->w, p->stream);
+  launch_partition(p->md, p->w, sv, p->stream);
+  launch_lines_pass1(p->md, p->w, sv, lv, p->stream);
+  if (ln->n > 0) launch_intensity_out(p->md, p->w, sv, lv, S, log_scale, p->stream);
+  return hip_check(hipGetLastError(), "intensity launch");
+}
+
+int xs_cross_section(xs_plan* p, const xs_states* st, const xs_lines* ln, double* sigma,
+                     int32_t accumulate) {
+  int rc;
+  if ((rc = check_call(p, st, ln))) return rc;
+  if (!sigma) return fail(XS_EINVAL, "sigma is NULL");
+  if (accumulate != 0 && accumulate != 1) return fail(XS_EINVAL, "accumulate must be 0 or 1");
+  if ((rc = preprocess(p, st, ln))) return rc;
+  return profile_pass(p, sigma, accumulate);
+}
+
+int xs_cross_section_adjoint(xs_plan* p, const xs_states* st, const xs_lines* ln,
+                             const double* g, double* dT, double* dP, double* dgref, double* dnexp,
+                             double* dls) {
+  int rc;
+  if ((rc = check_call(p, st, ln))) return rc;
+  if (p->model.population != XS_LTE)
+    return fail(XS_EUNSUPPORTED, "adjoint: two-temperature populations are not supported");
+  if (!g || !dT || !dP || !dls) return fail(XS_EINVAL, "adjoint: dL_dsigma, dL_dT, dL_dP and dL_dlog_scale are required");
+  if ((rc = preprocess(p, st, ln))) return rc;
+  launch_adjoint(p->md, p->w, view(st), view(ln), g, dT, dP, dgref, dnexp, dls, ln->n, p->stream);
+  return hip_check(hipGetLastError(), "adjoint launch");
+}
+
+int xs_plan_capture(xs_plan* p, const xs_states* st, const xs_lines* ln, double* sigma,
+                    int32_t accumulate) {
+  int rc;
+  if ((rc = check_call(p, st, ln))) return rc;
+  if (!sigma) return fail(XS_EINVAL, "sigma is NULL");
+  if (accumulate != 0 && accumulate != 1) return fail(XS_EINVAL, "accumulate must be 0 or 1");
+  if (!p->cap_stream &&
+      (rc = hip_check(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "capture stream")))
+    return rc;
+  if (p->gexec) {
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+  }
+  if (p->graph) {
+    (void)hipGraphDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  // capture on the library stream, replay on the plan's stream
+  hipStream_t keep = p->stream;
+  p->stream = p->cap_stream;
+  if ((rc = hip_check(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture"))) {
+    p->stream = keep;
+    return rc;
+  }
+  int rc1 = preprocess(p, st, ln);
+  int rc2 = rc1 ? rc1 : profile_pass(p, sigma, accumulate);
+  hipGraph_t g = nullptr;
+  int rc3 = hip_check(hipStreamEndCapture(p->cap_stream, &g), "end capture");
+  p->stream = keep;
+  if (rc2 || rc3) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc2 ? rc2 : rc3;
+  }
+  p->graph = g;
+  return hip_check(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0), "graph instantiate");
+}
+
+int xs_plan_replay(xs_plan* p) {
+  if (!p) return fail(XS_EINVAL, "plan is NULL");
+  if (!p->gexec) return fail(XS_EINVAL, "no captured graph (xs_plan_capture)");
+  return hip_check(hipGraphLaunch(p->gexec, p->stream), "graph launch");
+}
+
+int xs_plan_get_stats(xs_plan* p, xs_stats* s) {
+  if (!p || !s) return fail(XS_EINVAL, "plan or stats is NULL");
+  if (!p->ws) return fail(XS_EWORKSPACE, "no workspace bound");
+  unsigned long long h[8] = {0};
+  int rc;
+  if ((rc = hip_check(hipMemcpyAsync(h, p->w.stats, sizeof(h), hipMemcpyDeviceToHost, p->stream), "stats copy")))
+    return rc;
+  if ((rc = hip_check(hipStreamSynchronize(p->stream), "stats sync"))) return rc;
+  s->lines_in = p->last_lines_in;
+  s->lines_kept = (int64_t)h[1];
+  s->window_pairs = (int64_t)h[2];
+  const int64_t nt = (p->grid.n_bins + p->tiling.tile_bins - 1) / p->tiling.tile_bins;
+  s->work_items = nt * (int64_t)p->conds.size();
+  s->lines_invalid = (int64_t)h[3];
+  return XS_OK;
+}
+
+int xs_plan_sync(xs_plan* p) {
+  if (!p) return fail(XS_EINVAL, "plan is NULL");
+  return hip_check(hipStreamSynchronize(p->stream), "stream sync");
+}
+
+// ---- autotuner ----------------------------------------------------------
+static std::string tune_key(const xs_plan* p, int64_t n_lines) {
+  double maxcut = 0.0;
+  for (auto& c : p->conds) maxcut = std::max(maxcut, c.cutoff);
+  const int64_t wb = (int64_t)std::ceil(maxcut / p->grid.dnu);
+  int lb = 0;
+  while ((int64_t(1) << (lb + 1)) <= std::max<int64_t>(n_lines, 1)) ++lb;
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s|p%d|f%d|w%lld|n2^%d|c%d", p->arch.c_str(), p->model.profile,
+                p->model.precision, (long long)wb, lb, (int)p->conds.size());
+  return buf;
+}
+
+static bool cache_lookup(const char* path, const std::string& key, xs_config* c) {
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    char k[256];
+    int t, b, per, wv;
+    if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"tile_bins\": %d, \"bucket_bins\": %d, \"persistent\": %d, \"waves_per_cu\": %d",
+                    k, &t, &b, &per, &wv) == 5 && key == k) {
+      c->tile_bins = t;
+      c->bucket_bins = b;
+      c->persistent = per;
+      c->waves_per_cu = wv;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+static void cache_store(const char* path, const std::string& key, const xs_config& c, double ms) {
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "{\"key\": \"%s\", \"tile_bins\": %d, \"bucket_bins\": %d, \"persistent\": %d, \"waves_per_cu\": %d, \"ms\": %.4f}\n",
+               key.c_str(), c.tile_bins, c.bucket_bins, c.persistent, c.waves_per_cu, ms);
+  std::fclose(f);
+}
+
+int xs_plan_autotune(xs_plan* p, const xs_states* st, const xs_lines* ln, double* sigma,
+                     const char* cache_path) {
+  int rc;
+  if ((rc = check_call(p, st, ln))) return rc;
+  if (!sigma) return fail(XS_EINVAL, "sigma is NULL");
+  const std::string key = tune_key(p, ln->n);
+  xs_config best;
+  if (cache_lookup(cache_path, key, &best)) return xs_plan_set_config(p, &best);
+  if (p->model.algo != XS_GATHER) return XS_OK;
+  if ((rc = preprocess(p, st, ln))) return rc;
+  hipEvent_t e0, e1;
+  if ((rc = hip_check(hipEventCreate(&e0), "event"))) return rc;
+  if ((rc = hip_check(hipEventCreate(&e1), "event"))) {
+    (void)hipEventDestroy(e0);
+    return rc;
+  }
+  const int tiles[3] = {512, 1024, 2048};
+  const int waves[3] = {8, 16, 32};
+  double best_ms = 1e300;
+  xs_config cur;
+  cur.bucket_bins = p->bucket_bins;
+  for (int ti = 0; ti < 3 && !rc; ++ti) {
+    for (int per = 0; per < 2 && !rc; ++per) {
+      for (int wi = 0; wi < (per ? 3 : 1) && !rc; ++wi) {
+        cur.tile_bins = tiles[ti];
+        cur.persistent = per;
+        cur.waves_per_cu = per ? waves[wi] : 16;
+        tiling_for(p, cur.tile_bins, cur.persistent, cur.waves_per_cu);
+        float ms_best = 1e30f;
+        for (int rep = 0; rep < 3 && !rc; ++rep) {
+          launch_reset(p->w, p->stream);
+          (void)hipEventRecord(e0, p->stream);
+          rc = profile_pass(p, sigma, 0);
+          (void)hipEventRecord(e1, p->stream);
+          if (!rc) rc = hip_check(hipEventSynchronize(e1), "autotune sync");
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0) ms_best = std::min(ms_best, ms);
+        }
+        if (!rc && ms_best < best_ms) {
+          best_ms = ms_best;
+          best = cur;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  tiling_for(p, best.tile_bins, best.persistent, best.waves_per_cu);
+  cache_store(cache_path, key, best, best_ms);
+  return XS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Internal interface between the host runtime (xsec_api.cpp) and the HIP
+// kernels (k_*.hip): device-side parameter blocks and launch wrappers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/xsec.h"
+
+namespace xs {
+
+// CODATA 2018 exact SI values in CGS; c2 = h c / k_B (second radiation
+// constant, symbol table of the paper).
+constexpr double kH = 6.62607015e-27;      // erg s
+constexpr double kC = 2.99792458e10;       // cm / s
+constexpr double kKB = 1.380649e-16;       // erg / K
+constexpr double kAMU = 1.66053906660e-24; // g
+constexpr double kC2 = kH * kC / kKB;      // cm K
+constexpr double kPI = 3.14159265358979323846;
+constexpr double kLN2 = 0.69314718055994530942;
+
+constexpr int kMaxCond = 256;
+constexpr int kQBlocks = 256;     // partial sums per slot in the partition-function reduction
+constexpr int kAdjBlocks = 2048;  // persistent blocks of the adjoint (fixed: deterministic sums)
+constexpr int kSortItems = 16;    // keys per thread in the radix sort (4096 per block)
+constexpr int kSortBlock = 256 * kSortItems;
+
+// Per-condition scalars, uploaded with the workspace.
+struct CondDev {
+  double T, P, Tv, Tr, cut;
+  double Tk;      // kinetic temperature of the widths (T, or T_rot for two temperatures)
+  double dop;     // Doppler HWHM per unit wavenumber: alpha = nu * dop (0 for fixed Gaussian)
+  double hwhm;    // fixed Gaussian HWHM
+  double lnTr;    // ln(T_ref / Tk)
+  double pfac;    // P / P_ref
+  int32_t slot;   // intensity slot (distinct T or (T_vib, T_rot))
+  int32_t wbins;  // ceil(cut / dnu) + 2: bound on |k - k_c| inside the window
+};
+
+// Per intensity slot: the temperatures of the populations.
+struct SlotDev {
+  double T, Tv, Tr;
+};
+
+// Model and grid scalars shared by the kernels.
+struct ModelDev {
+  int32_t profile, mode, pop, prec;
+  double nu0, dnu;
+  int64_t n_bins;
+  double T_ref, P_ref, hwhm_fixed, mass_amu;
+  int32_t n_cond, n_slots;
+  int32_t bucket_bins, n_buckets;  // lines bucketed by k_c / bucket_bins; key n_buckets = dropped
+  int32_t n_cut_classes;           // distinct cut-offs (window statistics)
+  double max_cut;
+};
+
+// Views of the caller's inputs.
+struct StatesView {
+  int64_t n;
+  const double* E;
+  const double* g;
+  const int32_t* v;
+  const double* ev;
+  int32_t n_v;
+};
+struct LinesView {
+  int64_t n;
+  const int32_t* up;
+  const int32_t* lo;
+  const float* A;
+  const float* gref;
+  const float* nexp;
+  const float* lscale;
+  double gref_scalar, nexp_scalar;
+};
+
+// Workspace pointers (carved by the host runtime from the caller's buffer).
+struct Work {
+  CondDev* cond;            // [n_cond]
+  SlotDev* slot;            // [n_slots]
+  ModelDev* model;          // [1]
+  double* qpart;            // [n_slots][2][kQBlocks]
+  double* Q;                // [n_slots]
+  double* dQ;               // [n_slots]
+  unsigned long long* smax; // [n_slots] ordered keys of max ln|S|
+  double* sb;               // [n_slots] log scale s_b (FP32 form)
+  int32_t* key;             // [max_lines] bucket key per line
+  int32_t* keyA;            // sort ping-pong
+  int32_t* keyB;
+  int32_t* valA;
+  int32_t* valB;
+  int32_t* hist;            // [256 * n_sort_blocks] (+ scan block sums)
+  int32_t* hsum;            // scan block sums
+  int32_t* off;             // [n_buckets + 2] bucket offsets into the sorted records
+  double* rnu;              // sorted records: nu
+  float* rgref;             //                 gamma_ref
+  float* rnexp;             //                 n_exp
+  int32_t* ridx;            //                 original line index
+  void* rS;                 //                 S (f64) or S~ (f32), [n_slots][max_lines]
+  int32_t* counter;         // [64] work queues
+  unsigned long long* stats;// [8]
+  double* adjpart;          // [n_cond][2][kAdjBlocks]
+  double* cut_class;        // [n_cut_classes] distinct cut-offs
+  int32_t* cut_mult;        // [n_cut_classes] conditions sharing each cut-off
+  int64_t max_lines;
+  int32_t n_sort_blocks;
+};
+
+struct Tiling {
+  int32_t tile_bins;   // bins per gather work item
+  int32_t per_lane;    // consecutive bins per lane
+  int32_t waves;       // waves per workgroup
+  int32_t persistent;
+  int32_t grid_blocks; // persistent grid size
+};
+
+// ---- launch wrappers (k_lines.hip) ----
+void launch_partition(const ModelDev& m, const Work& w, const StatesView& st, hipStream_t s);
+void launch_lines_pass1(const ModelDev& m, const Work& w, const StatesView& st,
+                        const LinesView& ln, hipStream_t s);
+void launch_radix_sort(const ModelDev& m, const Work& w, int64_t n, hipStream_t s,
+                       int32_t** sorted_keys, int32_t** sorted_vals);
+void launch_offsets_records(const ModelDev& m, const Work& w, const StatesView& st,
+                            const LinesView& ln, const int32_t* skeys, const int32_t* svals,
+                            int64_t n, hipStream_t s);
+void launch_intensity_out(const ModelDev& m, const Work& w, const StatesView& st,
+                          const LinesView& ln, void* S, double* log_scale, hipStream_t s);
+void launch_q_out(const ModelDev& m, const Work& w, double* Q, double* dQ, hipStream_t s);
+void launch_reset(const Work& w, hipStream_t s);
+
+// ---- profile pass (k_profile.hip) ----
+void launch_gather(const ModelDev& m, const Work& w, const Tiling& t, double* sigma,
+                   int accumulate, hipStream_t s);
+void launch_scatter(const ModelDev& m, const Work& w, double* sigma, int accumulate,
+                    int64_t n_lines, hipStream_t s);
+
+// ---- adjoint (k_adjoint.hip) ----
+void launch_adjoint(const ModelDev& m, const Work& w, const StatesView& st, const LinesView& ln,
+                    const double* g, double* dT, double* dP, double* dgref, double* dnexp,
+                    double* dls, int64_t n_lines, hipStream_t s);
+
+}  // namespace xs

@@ -1,0 +1,93 @@
+"""Shared helpers of the GPU tests: run the HIP path through the C-ABI binding
+and the oracle on the same seeded inputs, and compare them."""
+from __future__ import annotations
+
+import functools
+import sys
+import time
+from typing import Optional
+
+import numpy as np
+
+import oracle
+import synth
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_err(got: np.ndarray, ref: np.ndarray, peak: Optional[float] = None, thr: float = 1e-6):
+    """Max relative error over bins with ref >= thr * peak, and the paper's
+    normalised L1 error sum|got - ref| / sum|ref| (Eq. profile_gpu_error)."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    peak = float(np.max(np.abs(ref))) if peak is None else peak
+    m = np.abs(ref) >= thr * peak
+    if not m.any():
+        return 0.0, 0.0, 0
+    e = float(np.max(np.abs(got[m] - ref[m]) / np.abs(ref[m])))
+    l1 = float(np.sum(np.abs(got - ref)) / max(np.sum(np.abs(ref)), 1e-300))
+    return e, l1, int(m.sum())
+
+
+def X():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU")
+    import paper_2609_17273_amd as P
+    P.lib()
+    return P
+
+
+def gpu_inputs(wl, lines, log_scale=None):
+    P = X()
+    return P.DeviceStates.from_numpy(wl.states), P.DeviceLines.from_numpy(lines, log_scale=log_scale)
+
+
+def make_plan(wl, precision, max_lines, algo=0, conditions=None):
+    P = X()
+    return P.Plan(wl.profile, wl.mode, wl.population, precision, wl.grid,
+                  conditions if conditions is not None else wl.conditions, max_lines,
+                  mass_amu=wl.mass_amu, algo=algo, T_ref=wl.T_ref, P_ref=wl.P_ref,
+                  hwhm_fixed=wl.hwhm_fixed)
+
+
+def gpu_sigma(wl, lines, precision, algo=0, config=None, log_scale=None):
+    import torch
+    plan = make_plan(wl, precision, max(lines.n, 1), algo)
+    if config:
+        plan.set_config(**config)
+    ds, dl = gpu_inputs(wl, lines, log_scale)
+    t0 = time.time()
+    sig = plan.cross_section(ds, dl)
+    torch.cuda.synchronize()
+    st = plan.stats()
+    out = sig.cpu().numpy()
+    plan.close()
+    return out, st, time.time() - t0
+
+
+@functools.lru_cache(maxsize=16)
+def _cached_workload(key):
+    k, kw = key
+    return synth.config(k, **dict(kw))
+
+
+def workload(k, **kw):
+    return _cached_workload((k, tuple(sorted(kw.items()))))
+
+
+@functools.lru_cache(maxsize=32)
+def _oracle_sigma(key, ci, bins_key):
+    k, kw = key
+    wl = _cached_workload(key)
+    bins = None if bins_key is None else np.frombuffer(bins_key, dtype=np.int64)
+    r = oracle.run_condition(wl, wl.lines(), wl.conditions[ci], bins=bins)
+    return r.sigma
+
+
+def oracle_sigma(wl_key_k, wl_kw, ci=0, bins=None):
+    key = (wl_key_k, tuple(sorted(wl_kw.items())))
+    return _oracle_sigma(key, ci, None if bins is None else np.ascontiguousarray(bins, np.int64).tobytes())
