@@ -1,0 +1,275 @@
+#!/usr/bin/env python3
+"""Benchmark of the line-list cross-section path on one MI355X.
+
+Workload (the 1e7-line Voigt case the metric is quoted on): LTE absorption,
+1e6 states (E exponential, mean 8000 cm^-1, cap 40000; J 0-120), 1e7
+transitions (nu in (0, 20000], A 10^U(-8,3), gamma_ref 10^U(log 0.02, log 0.1),
+n_exp U(0.3, 0.8)), T = 2000 K, P = 1 bar, mass 30 amu, Voigt profile, grid
+0-20000 cm^-1 step 0.01 (2,000,001 points), cut-off 25 cm^-1.  Seeded
+synthetic data (generator ``synth``), uploaded to HBM before timing.
+
+One step = the whole hot path once, FP32 log-scaled form:
+  prepare (Q(T), S_i, bucketing, records) -> profile pass (sigma) ->
+  dL/dsigma of L = sum_k w_k (sigma_k - t_k)^2 (target t at 1700 K, 0.8 bar) ->
+  adjoint pass (dL/dT, dL/dP, dL/dgamma_ref, dL/dn_exp, dL/dlog_scale).
+``value`` = profile evaluations per second over the step (forward and
+adjoint window evaluations: each kept line times its window bins on the
+grid, counted exactly by the library).  Also reported: the same step in the
+FP64 form (speedup FP32 / FP64), the adjoint / forward time ratio, the
+line-parallel atomic scatter, the roofline of the dominant kernel, and the
+oracle timed on the host (``cpu_baseline``).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per profile evaluation, counted on the far-wing formula
+# that covers > 95% of the window (one Gauss-Hermite node pair), FMA = 2:
+#   forward FP32:  x = fma(j,a,-b); u = x*x; n = u+p; a = u-p; qu = q*u;
+#                  d = fma(a,a,qu); r = rcp(d); t = n*r; acc = fma(c,t,acc)   -> 12 flops
+#   forward FP64 (2 pairs, 80 <= |z| < 3000): x = (nu_k - nu)*inv (2); u (1);
+#                  per pair p, n, a, d=fma, W*n*den, num=fma, den*d (10) -> 20;
+#                  division (1); acc fma (2)                                  -> 26 flops
+#   adjoint FP32:  x (2); u, zi, zi^2 (3); per pair A, A^2, d, rcp, id^2 (5);
+#                  Re w, R1, RG sums (14); scaling (3); 3 FP64 accumulations (6) -> 33 flops
+#   adjoint FP64 (2 pairs): x (2); u, zi, zi^2 (3); 2 x (5 + 14) -> 38; scaling (3);
+#                  3 FP64 accumulations (6)                                  -> 52 flops
+FLOPS_PER_EVAL = {("fwd", "f32"): 12, ("fwd", "f64"): 26, ("adj", "f32"): 33, ("adj", "f64"): 52}
+# MI355X vector peaks, no packed-FP32 (packed FP32 is disabled in this build):
+# 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP32
+# and FP64 alike.  The published 157.3 TFLOP/s FP32 figure needs packed math.
+PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
+KERNEL_SOURCES = ["paper_2609_17273_amd/csrc/k_profile.hip", "paper_2609_17273_amd/csrc/k_adjoint.hip",
+                  "paper_2609_17273_amd/csrc/k_common.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_key: str):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    e = d.get(kernel_key)
+    if not e or e.get("source_hash") != source_hash():
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def run_step(plan, ds, dl, sig, w, target, ev):
+    import torch
+    ev[0].record()
+    plan.prepare(ds, dl)
+    ev[1].record()
+    plan.profile(out=sig)
+    ev[2].record()
+    g = (2.0 * w) * (sig - target)
+    ev[3].record()
+    r = plan.profile_adjoint(ds, dl, g)
+    ev[4].record()
+    return r
+
+
+def time_steps(plan, ds, dl, sig, w, target, steps, warmup):
+    import torch
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(max(steps, 1))]
+    for _ in range(warmup):
+        run_step(plan, ds, dl, sig, w, target, evs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        run_step(plan, ds, dl, sig, w, target, evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = {"prepare": 0.0, "forward": 0.0, "loss_grad": 0.0, "adjoint": 0.0}
+    for e in evs[:steps]:
+        per["prepare"] += e[0].elapsed_time(e[1]) / steps
+        per["forward"] += e[1].elapsed_time(e[2]) / steps
+        per["loss_grad"] += e[2].elapsed_time(e[3]) / steps
+        per["adjoint"] += e[3].elapsed_time(e[4]) / steps
+    return (t1 - t0) * 1e3 / max(steps, 1), per
+
+
+def cpu_baseline(wl, lines, cond, n_sample=16000):
+    """The oracle (FP64, OpenMP) on this host: sigma at a random sample of grid
+    points of the same workload, all lines; evaluations counted exactly as
+    the (line, bin) pairs inside the cut-off."""
+    import numpy as np
+    import oracle
+    import synth
+    bins = synth.sample_bins(wl.grid.n_bins, n_sample, 4242)
+    Q, _ = oracle.partition(wl.states, wl.population, cond.T)
+    nu, S, keep = oracle.intensities(wl.states, lines, wl.mode, wl.population, cond.T, Q)
+    alpha, gamma = oracle.widths(nu, lines, wl.profile, cond.T, cond.P, wl.mass_amu)
+    snu = np.sort(nu[nu > 0])
+    nuk = wl.grid.nu0 + bins * wl.grid.dnu
+    evals = int(np.sum(np.searchsorted(snu, nuk + cond.cutoff, side="right")
+                       - np.searchsorted(snu, nuk - cond.cutoff, side="left")))
+    t0 = time.perf_counter()
+    oracle.sigma(nu, S, alpha, gamma, wl.profile, wl.grid, cond.cutoff, bins)
+    dt = time.perf_counter() - t0
+    return {"value": evals / dt, "unit": "profile evals/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": (f"sigma at {n_sample} random grid points of the 2,000,001-point grid over all "
+                       f"1e7 lines ({evals:.3e} evaluations, {dt:.1f} s including the oracle's sort of "
+                       f"the lines by wavenumber)")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and scatter comparisons")
+    ap.add_argument("--n-lines", type=int, default=None, help="(testing) fewer lines")
+    ap.add_argument("--calib-copy", action="store_true", help="run only a 1 GiB device copy (PMC calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how it would shard); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    torch.cuda.set_device(0)
+    if args.calib_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied 1 GiB x 5")
+        return
+
+    import synth
+    import paper_2609_17273_amd as X
+
+    t_gen = time.perf_counter()
+    wl = synth.config(2, n_lines=args.n_lines)
+    lines = wl.lines()
+    cond = wl.conditions[0]
+    log(f"generated {lines.n} lines, {wl.states.n} states in {time.perf_counter() - t_gen:.1f} s")
+    ds = X.DeviceStates.from_numpy(wl.states)
+    dl = X.DeviceLines.from_numpy(lines)
+    w = torch.as_tensor(wl.bin_weights(), device="cuda")
+    sig = torch.empty((1, wl.grid.n_bins), dtype=torch.float64, device="cuda")
+
+    def plan_for(prec, algo=X.XS_GATHER, conds=None):
+        return X.Plan(X.XS_VOIGT, X.XS_ABSORPTION, X.XS_LTE, prec, wl.grid,
+                      conds or wl.conditions, lines.n, mass_amu=wl.mass_amu, algo=algo)
+
+    # target spectrum at 1700 K, 0.8 bar (FP64 form), before timing
+    tp = plan_for(X.XS_FP64, conds=[synth.Condition(1700.0, 0.8, 25.0)])
+    target = tp.cross_section(ds, dl)[0].clone().reshape(1, -1)
+    tp.close()
+    del tp
+
+    p32 = plan_for(X.XS_FP32)
+    cfg = p32.autotune(ds, dl, sig, cache_path=os.path.join("/tmp", "xsec_autotune.json"))
+    log(f"autotuned: {cfg}")
+    ms32, per32 = time_steps(p32, ds, dl, sig, w, target, args.steps, args.warmup)
+    st = p32.stats()
+    pairs = st["window_pairs"]
+    log(f"fp32 step {ms32:.2f} ms {per32} pairs {pairs:.3e}")
+
+    extras = {}
+    if not args.no_extras:
+        p64 = plan_for(X.XS_FP64)
+        p64.set_config(**cfg)
+        ms64, per64 = time_steps(p64, ds, dl, sig, w, target, max(2, args.steps // 2), 1)
+        log(f"fp64 step {ms64:.2f} ms {per64}")
+        extras["fp64"] = {"ms_per_step": round(ms64, 3), "stage_ms": {k: round(v, 3) for k, v in per64.items()},
+                          "evals_per_s": 2 * pairs / (ms64 / 1e3)}
+        extras["fp32_over_fp64_speedup"] = {"step": round(ms64 / ms32, 3),
+                                            "profile_pass": round(per64["forward"] / per32["forward"], 3),
+                                            "adjoint": round(per64["adjoint"] / per32["adjoint"], 3)}
+        p64.close()
+        for prec, name in ((X.XS_FP32, "f32"), (X.XS_FP64, "f64")):
+            ps = plan_for(prec, algo=X.XS_SCATTER)
+            ps.prepare(ds, dl)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ps.profile(out=sig)
+            e0.record()
+            ps.profile(out=sig)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            extras[f"scatter_{name}"] = {"profile_pass_ms": round(ms, 3), "evals_per_s": pairs / (ms / 1e3)}
+            log(f"scatter {name}: {ms:.2f} ms")
+            ps.close()
+        extras["gather_over_scatter_speedup_f32"] = round(extras["scatter_f32"]["profile_pass_ms"] / per32["forward"], 2)
+
+    # roofline of the dominant kernel (events around each launch, same stream)
+    rl = {}
+    for kind, ms in (("fwd", per32["forward"]), ("adj", per32["adjoint"])):
+        flops = FLOPS_PER_EVAL[(kind, "f32")] * pairs
+        ach = flops / (ms / 1e3) / 1e12
+        key = "gather_c2_f32" if kind == "fwd" else "adjoint_c2_f32"
+        rl[kind] = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                    "frac": round(ach / PEAK_TFLOPS["f32"], 4), "traffic": traffic_from_profiles(key),
+                    "kernel": "k_gather<float,Voigt>" if kind == "fwd" else "k_adjoint<float,Voigt>",
+                    "avg_launch_ms": round(ms, 3), "flops_per_eval": FLOPS_PER_EVAL[(kind, "f32")],
+                    "evals_per_launch": pairs}
+    dom = "adj" if per32["adjoint"] >= per32["forward"] else "fwd"
+    other = "fwd" if dom == "adj" else "adj"
+
+    evals_step = 2 * pairs
+    value = evals_step / (ms32 / 1e3)
+    out = {
+        "metric": "profile evals/s & lines/s for sigma(nu) at 1e7 lines; batched FP32 vs FP64; adj/fwd",
+        "value": value,
+        "unit": "profile evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded generator of the 1e7-line Voigt workload; no dataset)",
+        "config": {"workload": "config 2: LTE Voigt absorption, 1e6 states, 1e7 lines, T 2000 K, P 1 bar, "
+                               "grid 0-20000 cm^-1 step 0.01 (2,000,001 points), cut-off 25 cm^-1; step = "
+                               "prepare + sigma + dL/dsigma + adjoint, FP32 log-scaled form",
+                   "lines": lines.n, "states": wl.states.n, "grid_points": wl.grid.n_bins,
+                   "lines_kept": st["lines_kept"], "window_pairs": pairs, "kernel_config": cfg},
+        "stage_ms": {k: round(v, 3) for k, v in per32.items()},
+        "forward_evals_per_s": pairs / (per32["forward"] / 1e3),
+        "lines_per_s": lines.n / (ms32 / 1e3),
+        "adj_over_fwd": round(per32["adjoint"] / per32["forward"], 3),
+        "roofline": rl[dom],
+        "roofline_other": rl[other],
+        **extras,
+    }
+    if not args.no_cpu_baseline:
+        t = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(wl, lines, cond)
+        log(f"cpu baseline {out['cpu_baseline']['value']:.3e} evals/s in {time.perf_counter() - t:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -221,6 +221,24 @@ int xs_cross_section_adjoint(xs_plan* plan, const xs_states* states, const xs_li
                              const double* dL_dsigma, double* dL_dT, double* dL_dP,
                              double* dL_dgamma_ref, double* dL_dn_exp, double* dL_dlog_scale);
 
+/* The two stages of xs_cross_section, for callers that reuse one line list
+ * (the paper's combined stick-spectrum / cross-section mode) or time the
+ * profile kernel on its own.
+ * xs_prepare: partition functions, intensities, bucketing of the lines by
+ *   home bin and the sorted line records, kept in the workspace.
+ * xs_profile_pass: the profile pass (gather or scatter per model.algo) over the
+ *   records of the last xs_prepare; same sigma contract as xs_cross_section.
+ * xs_profile_adjoint: the adjoint over the records of the last xs_prepare;
+ *   same contract as xs_cross_section_adjoint (states and lines must be the
+ *   ones given to xs_prepare).
+ * Calling xs_profile_pass / xs_profile_adjoint without a preceding xs_prepare on the same workspace
+ * returns XS_EINVAL. */
+int xs_prepare(xs_plan* plan, const xs_states* states, const xs_lines* lines);
+int xs_profile_pass(xs_plan* plan, double* sigma, int32_t accumulate);
+int xs_profile_adjoint(xs_plan* plan, const xs_states* states, const xs_lines* lines,
+                       const double* dL_dsigma, double* dL_dT, double* dL_dP,
+                       double* dL_dgamma_ref, double* dL_dn_exp, double* dL_dlog_scale);
+
 /* Record one xs_cross_section call with these arguments into a HIP graph
  * (no kernel runs during capture); xs_plan_replay launches it on the plan's
  * stream.  The pointers are kept until destroy or the next capture. */

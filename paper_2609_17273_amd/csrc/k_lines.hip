@@ -461,4 +461,13 @@ void launch_reset(const Work& w, hipStream_t s) {
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, w.counter, w.stats);
 }
 
+// Only the work queue (the counters of xs_prepare are kept).
+__global__ void k_reset_queue(int32_t* counter) {
+  if (threadIdx.x < 64) counter[threadIdx.x] = 0;
+}
+
+void launch_reset_queue(const Work& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, w.counter);
+}
+
 }  // namespace xs

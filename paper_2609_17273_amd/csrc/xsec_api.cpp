@@ -69,6 +69,7 @@ struct xs_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int64_t last_lines_in = 0;
+  bool prepared = false;     // records of an xs_prepare are in the workspace
 };
 
 namespace {
@@ -344,6 +345,7 @@ int preprocess(xs_plan* p, const xs_states* st, const xs_lines* ln) {
   launch_offsets_records(p->md, p->w, sv, lv, sk ? sk : p->w.keyA, svv ? svv : p->w.valA, lv.n,
                          p->stream);
   p->last_lines_in = lv.n;
+  p->prepared = true;
   return hip_check(hipGetLastError(), "preprocess launch");
 }
 
@@ -415,6 +417,7 @@ int xs_plan_set_conditions(xs_plan* p, int32_t n_cond, const xs_condition* conds
   int rc;
   if ((rc = validate_conds(&p->model, &p->grid, n_cond, conds))) return rc;
   p->conds.assign(conds, conds + n_cond);
+  p->prepared = false;
   const int32_t old_slots = p->md.n_slots, old_cc = p->md.n_cut_classes;
   derive(p);
   if (p->md.n_slots > old_slots || p->md.n_cut_classes > old_cc) {
@@ -460,6 +463,7 @@ int xs_plan_set_workspace(xs_plan* p, void* dptr, size_t bytes) {
   if (bytes < need) return fail(XS_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
   p->ws = dptr;
   p->ws_bytes = bytes;
+  p->prepared = false;
   layout(p, (char*)dptr, &p->w);
   return upload(p);
 }
@@ -470,6 +474,7 @@ int xs_plan_set_config(xs_plan* p, const xs_config* c) {
   if ((rc = validate_config(c))) return rc;
   if (c->bucket_bins != p->bucket_bins) {
     p->bucket_bins = c->bucket_bins;
+    p->prepared = false;
     derive(p);
     if (p->ws) {  // the bucket table size changed: re-carve and re-upload
       size_t need = layout(p, nullptr, nullptr);
@@ -526,6 +531,35 @@ int xs_cross_section(xs_plan* p, const xs_states* st, const xs_lines* ln, double
   if (accumulate != 0 && accumulate != 1) return fail(XS_EINVAL, "accumulate must be 0 or 1");
   if ((rc = preprocess(p, st, ln))) return rc;
   return profile_pass(p, sigma, accumulate);
+}
+
+int xs_prepare(xs_plan* p, const xs_states* st, const xs_lines* ln) {
+  int rc;
+  if ((rc = check_call(p, st, ln))) return rc;
+  return preprocess(p, st, ln);
+}
+
+int xs_profile_pass(xs_plan* p, double* sigma, int32_t accumulate) {
+  if (!p) return fail(XS_EINVAL, "plan is NULL");
+  if (!p->ws) return fail(XS_EWORKSPACE, "no workspace bound (xs_plan_set_workspace)");
+  if (!p->prepared) return fail(XS_EINVAL, "xs_profile_pass before xs_prepare");
+  if (!sigma) return fail(XS_EINVAL, "sigma is NULL");
+  if (accumulate != 0 && accumulate != 1) return fail(XS_EINVAL, "accumulate must be 0 or 1");
+  launch_reset_queue(p->w, p->stream);
+  return profile_pass(p, sigma, accumulate);
+}
+
+int xs_profile_adjoint(xs_plan* p, const xs_states* st, const xs_lines* ln, const double* g,
+                       double* dT, double* dP, double* dgref, double* dnexp, double* dls) {
+  int rc;
+  if ((rc = check_call(p, st, ln))) return rc;
+  if (!p->prepared) return fail(XS_EINVAL, "xs_profile_adjoint before xs_prepare");
+  if (p->model.population != XS_LTE)
+    return fail(XS_EUNSUPPORTED, "adjoint: two-temperature populations are not supported");
+  if (!g || !dT || !dP || !dls) return fail(XS_EINVAL, "adjoint: dL_dsigma, dL_dT, dL_dP and dL_dlog_scale are required");
+  if (ln->n != p->last_lines_in) return fail(XS_EINVAL, "adjoint: lines differ from the prepared ones");
+  launch_adjoint(p->md, p->w, view(st), view(ln), g, dT, dP, dgref, dnexp, dls, ln->n, p->stream);
+  return hip_check(hipGetLastError(), "adjoint launch");
 }
 
 int xs_cross_section_adjoint(xs_plan* p, const xs_states* st, const xs_lines* ln,

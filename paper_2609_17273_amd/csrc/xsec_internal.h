@@ -126,6 +126,7 @@ void launch_intensity_out(const ModelDev& m, const Work& w, const StatesView& st
                           const LinesView& ln, void* S, double* log_scale, hipStream_t s);
 void launch_q_out(const ModelDev& m, const Work& w, double* Q, double* dQ, hipStream_t s);
 void launch_reset(const Work& w, hipStream_t s);
+void launch_reset_queue(const Work& w, hipStream_t s);
 
 // ---- profile pass (k_profile.hip) ----
 void launch_gather(const ModelDev& m, const Work& w, const Tiling& t, double* sigma,

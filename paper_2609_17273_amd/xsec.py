@@ -88,6 +88,9 @@ SIGNATURES = {
     "xs_cross_section": (C.c_int, [_P, C.POINTER(xs_states), C.POINTER(xs_lines), _P, C.c_int32]),
     "xs_cross_section_adjoint": (C.c_int, [_P, C.POINTER(xs_states), C.POINTER(xs_lines), _P, _P, _P,
                                            _P, _P, _P]),
+    "xs_prepare": (C.c_int, [_P, C.POINTER(xs_states), C.POINTER(xs_lines)]),
+    "xs_profile_pass": (C.c_int, [_P, _P, C.c_int32]),
+    "xs_profile_adjoint": (C.c_int, [_P, C.POINTER(xs_states), C.POINTER(xs_lines), _P, _P, _P, _P, _P, _P]),
     "xs_plan_capture": (C.c_int, [_P, C.POINTER(xs_states), C.POINTER(xs_lines), _P, C.c_int32]),
     "xs_plan_replay": (C.c_int, [_P]),
     "xs_plan_autotune": (C.c_int, [_P, C.POINTER(xs_states), C.POINTER(xs_lines), _P, C.c_char_p]),
@@ -174,6 +177,19 @@ def xs_cross_section(plan, states, lines, sigma_ptr, accumulate=0):
 def xs_cross_section_adjoint(plan, states, lines, g_ptr, dT_ptr, dP_ptr, dgref_ptr, dnexp_ptr, dls_ptr):
     return _check(lib().xs_cross_section_adjoint(plan, C.byref(states), C.byref(lines), g_ptr, dT_ptr,
                                                  dP_ptr, dgref_ptr, dnexp_ptr, dls_ptr))
+
+
+def xs_prepare(plan, states, lines):
+    return _check(lib().xs_prepare(plan, C.byref(states), C.byref(lines)))
+
+
+def xs_profile_pass(plan, sigma_ptr, accumulate=0):
+    return _check(lib().xs_profile_pass(plan, sigma_ptr, accumulate))
+
+
+def xs_profile_adjoint(plan, states, lines, g_ptr, dT_ptr, dP_ptr, dgref_ptr, dnexp_ptr, dls_ptr):
+    return _check(lib().xs_profile_adjoint(plan, C.byref(states), C.byref(lines), g_ptr, dT_ptr, dP_ptr,
+                                           dgref_ptr, dnexp_ptr, dls_ptr))
 
 
 def xs_plan_capture(plan, states, lines, sigma_ptr, accumulate=0):
@@ -346,7 +362,20 @@ class Plan:
         xs_cross_section(self.h, states.struct(), lines.struct(), out.data_ptr(), int(accumulate))
         return out
 
-    def adjoint(self, states: DeviceStates, lines: DeviceLines, dL_dsigma):
+    def prepare(self, states: DeviceStates, lines: DeviceLines):
+        xs_prepare(self.h, states.struct(), lines.struct())
+
+    def profile(self, out=None, accumulate=False):
+        t = self.torch
+        if out is None:
+            out = t.empty((self.n_cond, self.grid.n_bins), dtype=t.float64, device="cuda")
+        xs_profile_pass(self.h, out.data_ptr(), int(accumulate))
+        return out
+
+    def profile_adjoint(self, states: DeviceStates, lines: DeviceLines, dL_dsigma):
+        return self.adjoint(states, lines, dL_dsigma, prepared=True)
+
+    def adjoint(self, states: DeviceStates, lines: DeviceLines, dL_dsigma, prepared=False):
         t = self.torch
         g = dL_dsigma.contiguous()
         dT = t.empty(self.n_cond, dtype=t.float64, device="cuda")
@@ -354,8 +383,9 @@ class Plan:
         dgr = t.empty(lines.n, dtype=t.float64, device="cuda")
         dne = t.empty(lines.n, dtype=t.float64, device="cuda")
         dls = t.empty(lines.n, dtype=t.float64, device="cuda")
-        xs_cross_section_adjoint(self.h, states.struct(), lines.struct(), g.data_ptr(), dT.data_ptr(),
-                                 dP.data_ptr(), dgr.data_ptr(), dne.data_ptr(), dls.data_ptr())
+        f = xs_profile_adjoint if prepared else xs_cross_section_adjoint
+        f(self.h, states.struct(), lines.struct(), g.data_ptr(), dT.data_ptr(), dP.data_ptr(),
+          dgr.data_ptr(), dne.data_ptr(), dls.data_ptr())
         return dict(dT=dT, dP=dP, d_gamma_ref=dgr, d_n_exp=dne, d_log_scale=dls)
 
     def capture(self, states: DeviceStates, lines: DeviceLines, out, accumulate=False):
