@@ -127,17 +127,20 @@ typedef struct {
   double n_exp_scalar;
 } xs_lines;
 
-/* Kernel configuration.  tile_bins: grid points per gather work item
- * (512, 1024 or 2048: 4 waves x 64 lanes x 2, 4 or 8 consecutive bins per
- * lane); bucket_bins: grid points per line bucket (power of two, 64..4096);
- * persistent: 1 = one persistent launch pulling (condition, tile) items from a
- * device queue, 0 = one workgroup per item; waves_per_cu: size of the
- * persistent grid in waves per compute unit (4..64). */
+/* Kernel configuration.  A gather work item is one tile of
+ * tile_bins = tile_waves x 64 lanes x (2, 4 or 8) grid points: each wave owns
+ * 64 x per-lane points, each lane every 64th of them.  tile_waves: 1, 2 or 4;
+ * tile_bins: 128 .. 2048 as above; bucket_bins: grid points per line bucket
+ * (power of two, 64..4096); persistent: 1 = one persistent launch pulling
+ * (condition, tile) items from a device queue, 0 = one workgroup per item;
+ * waves_per_cu: size of the persistent grid in waves per compute unit
+ * (4..64). */
 typedef struct {
   int32_t tile_bins;
   int32_t bucket_bins;
   int32_t persistent;
-  int32_t waves_per_cu;  /* persistent grid = 256 CUs x waves_per_cu/4 workgroups */
+  int32_t waves_per_cu;
+  int32_t tile_waves;
 } xs_config;
 
 /* Counters of the last xs_cross_section / adjoint call (read after sync). */

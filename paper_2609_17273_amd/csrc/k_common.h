@@ -197,7 +197,7 @@ __device__ __forceinline__ R gh_re_sum(R u, R y2, R q) {
 // Taylor series of w about the nearest anchor z0 = STEP (i + i j) of the
 // generated table, K terms; x may be negative (w(-x+iy) = conj w(x+iy)).
 template <int K>
-__device__ inline void w_core(double x, double y, double& wr, double& wi) {
+__device__ __noinline__ void w_core(double x, double y, double& wr, double& wi) {
   const double ax = fabs(x);
   // nearest anchor, clamped to the table (also for NaN or negative input)
   const double fi = fmin(fmax(ax * (1.0 / XS_FT_STEP) + 0.5, 0.0), (double)(XS_FT_NA - 1));
@@ -207,7 +207,7 @@ __device__ inline void w_core(double x, double y, double& wr, double& wi) {
   const double hr = ax - XS_FT_STEP * i, hi = y - XS_FT_STEP * j;
   const double* c = xs_ft_coef + (size_t)((i * XS_FT_NA + j) * (XS_FT_KMAX + 1)) * 2;
   double pr = c[2 * K], pi = c[2 * K + 1];
-#pragma unroll
+#pragma unroll 2
   for (int k = K - 1; k >= 0; --k) {
     double nr = fma(pr, hr, fma(-pi, hi, c[2 * k]));
     double ni = fma(pr, hi, fma(pi, hr, c[2 * k + 1]));
@@ -256,7 +256,7 @@ __device__ inline void w_core_d(double x, double y, double& wr, double& wi, doub
 }
 
 // FP64 Re w(x + iy), y >= 0, relative accuracy ~1e-14 (bands chosen per |z|).
-__device__ inline double re_w_f64(double x, double y) {
+__device__ __noinline__ double re_w_f64(double x, double y) {
   const double u = x * x, y2 = y * y, rho = u + y2, q = 4.0 * y2;
   const double cy = 2.0 * y / kPI;
   if (rho >= 9.0e6) return cy * gh_re_sum<1>(u, y2, q);

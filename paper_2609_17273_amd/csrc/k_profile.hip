@@ -17,51 +17,18 @@
 
 namespace xs {
 
-// Per-(line, condition) record staged in LDS.
-struct RecF {
-  int kc, klo, khi, flag;
-  float a, b, y, y2, q, c0, cy, pad;
-};
-struct RecD {
-  int kc, klo, khi, flag;
-  float af, bf, y2f, pad;
-  double nu, inv, y, y2, q, c0, cy, pad2;
-};
-
-struct GatherArgs {
-  ModelDev m;
-  const CondDev* cond;
-  const double* sb;
-  const int32_t* off;
-  const double* rnu;
-  const float* rgref;
-  const float* rnexp;
-  const void* rS;
-  int64_t max_lines;
-  int32_t* counter;
-  double* sigma;
-  int32_t accumulate;
-  int32_t n_tiles;
-  int64_t n_items;
-  int32_t tile_bins;
-  int32_t persistent;
-};
-
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ float uni(float v) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-__device__ __forceinline__ double uni(double v) {
-  long long b = __double_as_longlong(v);
-  int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
-  int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Per-(line, condition) parameters.  For every profile the lane variable is
-// x = (k - k_c) a - b = (nu_k - nu_i) * inv, with inv = 1/alpha (Gaussian, so
-// f = c0 2^{-x^2}), 1/gamma (Lorentzian, f = c0 / (1 + x^2)) or
-// 1/(sg sqrt 2) = sqrt(ln 2)/alpha (Voigt, f = c0 Re w(x + i y)).
+// ---------------------------------------------------------------------------
+// Per-(line, condition) constants.  The lane variable is
+//   x = (nu_k - nu_i) * inv = (k - k_c) a - b,  a = dnu inv,  b = delta inv,
+// with inv = 1/alpha (Gaussian: f = c0 2^{-x^2}), 1/gamma (Lorentzian:
+// f = c0 / (1 + x^2)) or 1/(sg sqrt 2) = sqrt(ln 2)/alpha (Voigt:
+// f = c0 Re w(x + i y)).  For the Voigt far region each Gauss-Hermite node
+// pair j contributes, with u = x^2, p_j = y^2 + tau_j, q_j = 2 y^2 - 2 tau_j,
+//   c0 (2y/pi) W_j (u + p_j) / ((u - p_j)^2 + 4 y^2 u)
+//     = (cW_j u + cW_j p_j) / (u (u + q_j) + p_j^2),
+// so a far-wing evaluation is 2 FMA, 1 add, 1 reciprocal and 1 FMA into the
+// accumulator after x and u.
+// ---------------------------------------------------------------------------
 struct LineParams {
   double inv, y, c0;
 };
@@ -88,10 +55,112 @@ __device__ __forceinline__ LineParams line_params(const ModelDev& m, const CondD
   return lp;
 }
 
-// Staging: does line p touch bins [tlo, thi] under condition cd?  Fills rec.
-template <typename Rec, int PROF>
+// Far-region pair constants (cW, cW p, q, p^2) for node pair (tau, W).
+template <typename R>
+struct Pair {
+  R cw, cwp, q, p2;
+};
+template <typename R>
+__device__ __forceinline__ Pair<R> make_pair(double c0, double y, double tau, double W) {
+  const double y2 = y * y, p = y2 + tau;
+  const double cw = c0 * (2.0 * y / kPI) * W;
+  Pair<R> r;
+  r.cw = (R)cw;
+  r.cwp = (R)(cw * p);
+  r.q = (R)(2.0 * y2 - 2.0 * tau);
+  r.p2 = (R)(p * p);
+  return r;
+}
+
+// Bin ranges of a line inside which a cheaper formula is not valid:
+// |x| < X  <=>  k - k_c in ((b - X)/a, (b + X)/a); widened by one bin so the
+// float evaluation of x cannot leave a range through rounding.  Empty ranges
+// use lo > hi sentinels that intersect nothing.
+struct KRange {
+  int lo, hi;
+};
+__device__ __forceinline__ KRange x_range(double X, double a, double b, int64_t kc, int64_t klo,
+                                          int64_t khi) {
+  KRange r;
+  if (!(X > 0.0)) {
+    r.lo = 0x7fffffff;
+    r.hi = -0x7fffffff;
+    return r;
+  }
+  double lo = floor((b - X) / a) - 1.0 + (double)kc;
+  double hi = ceil((b + X) / a) + 1.0 + (double)kc;
+  lo = fmax(lo, (double)klo - 1.0);
+  hi = fmin(hi, (double)khi + 1.0);
+  if (lo > hi) {
+    r.lo = 0x7fffffff;
+    r.hi = -0x7fffffff;
+    return r;
+  }
+  r.lo = (int)lo;
+  r.hi = (int)hi;
+  return r;
+}
+
+// Row classes of a staged line, 2 bits per wave of the tile: 0 = the row
+// gets nothing (outside the window, or a Gaussian row where 2^{-x^2}
+// vanishes); 1 = the whole row is inside the window and takes the first
+// uniform formula (FP32: one node pair / Gaussian / Lorentzian; FP64: one
+// node pair / Gaussian / Lorentzian); 3 = inside the window, second uniform
+// formula (FP32: two node pairs; FP64: two node pairs); 2 = general per-chunk
+// path (window edges, the core, lines evaluated in FP64).
+constexpr int kRowSkip = 0, kRowF1 = 1, kRowGeneral = 2, kRowF2 = 3;
+
+// FP32 form.  The fast-path fields come first (two 16-byte LDS reads).
+//   rB: bins that are not far-wing (one node pair) -- for the Gaussian, the
+//       bins where 2^{-x^2} is not zero in FP32; rC: bins near the core that
+//       need the per-lane choice (Taylor core or two node pairs).
+struct RecF {
+  int cls;
+  float a, nb, jfb;  // x = (jfb + offset of the bin in the tile) a + nb; jfb = tlo - k_c
+  Pair<float> A;
+  int klo, khi, flag, kc;
+  KRange rB, rC;
+  float c0, y, pad0, pad1;
+  Pair<float> B1, B2;
+};
+// FP64 form.  r[0..4]: bins with |z|^2 below 9e6, 6400, 400, 144, 64 (the
+// thresholds of the 1, 2, 3, 4 and 6 node-pair bands); for the Gaussian,
+// r[0] holds the bins where 2^{-x^2} is not zero in FP64.
+struct RecD {
+  int cls, klo, khi, flag;
+  KRange r[5];
+  int kc, pad2;
+  double nu, inv, y, c0;
+  Pair<double> A, B1, B2;
+};
+
+struct GatherArgs {
+  ModelDev m;
+  const CondDev* cond;
+  const double* sb;
+  const int32_t* off;
+  const double* rnu;
+  const float* rgref;
+  const float* rnexp;
+  const void* rS;
+  int64_t max_lines;
+  int32_t* counter;
+  double* sigma;
+  int32_t accumulate;
+  int32_t n_tiles;
+  int64_t n_items;
+  int32_t tile_bins;
+  int32_t persistent;
+};
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ bool meets(int lo, int hi, const KRange& r) { return hi >= r.lo && lo <= r.hi; }
+
+// Staging: does line p touch bins [tlo, thi] under condition cd?  Fills rec,
+// including the class of each wave's row (rows of rowb bins from tlo).
+template <typename Rec, int PROF, int WAVES>
 __device__ bool stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int64_t tlo,
-                           int64_t thi, Rec& r) {
+                           int64_t thi, int rowb, Rec& r) {
   const ModelDev& m = g.m;
   const double nu = g.rnu[p];
   int64_t klo, khi;
@@ -105,119 +174,171 @@ __device__ bool stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, in
   if (S == 0.0) return false;
   const int64_t kc = home_bin(nu, m.nu0, m.dnu);
   const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
-  LineParams lp = line_params<PROF>(m, cd, nu, (double)g.rgref[p], (double)g.rnexp[p], S);
-  r.kc = (int)kc;
-  r.klo = (int)(klo > tlo ? klo : tlo);
-  r.khi = (int)(khi < thi ? khi : thi);
+  const LineParams lp = line_params<PROF>(m, cd, nu, (double)g.rgref[p], (double)g.rnexp[p], S);
+  klo = klo > tlo ? klo : tlo;
+  khi = khi < thi ? khi : thi;
+  r.klo = (int)klo;
+  r.khi = (int)khi;
   r.flag = 0;
+  r.kc = (int)kc;
   const double a = m.dnu * lp.inv, b = delta * lp.inv;
+  const double y2 = lp.y * lp.y;
+  using R = decltype(r.A.cw);
+  if (PROF == XS_VOIGT) {
+    r.A = make_pair<R>(lp.c0, lp.y, GH::t2[0], GH::w2[0]);
+    r.B1 = make_pair<R>(lp.c0, lp.y, GH::t4[0], GH::w4[0]);
+    r.B2 = make_pair<R>(lp.c0, lp.y, GH::t4[1], GH::w4[1]);
+  }
+  auto xr = [&](double rho) { return x_range(sqrt(fmax(rho - y2, 0.0)), a, b, kc, klo, khi); };
+  const KRange none = x_range(0.0, a, b, kc, klo, khi);
+  // class of the row [lo, hi] given the ranges of the first and second uniform formula
+  auto row_class = [&](int lo, int hi, KRange zero, KRange not1, KRange not2, bool can2) {
+    if (hi < klo || lo > khi) return kRowSkip;
+    if (!meets(lo, hi, zero)) return kRowSkip;
+    const bool inside = klo <= lo && khi >= hi;
+    if (!inside || r.flag) return kRowGeneral;
+    if (!meets(lo, hi, not1)) return kRowF1;
+    if (can2 && !meets(lo, hi, not2)) return kRowF2;
+    return kRowGeneral;
+  };
+  KRange zero, not1, not2;
+  bool can2;
   if constexpr (sizeof(Rec) == sizeof(RecF)) {
     r.a = (float)a;
-    r.b = (float)b;
-    r.y = (float)lp.y;
-    r.y2 = (float)(lp.y * lp.y);
-    r.q = (float)(4.0 * lp.y * lp.y);
+    r.nb = (float)(-b);
+    r.jfb = (float)(tlo - kc);  // integer, exact in FP32 within a window
     r.c0 = (float)lp.c0;
-    r.cy = (float)(lp.c0 * 2.0 * lp.y / kPI);
-    // FP32 keeps (x^2 + y^2)^2 finite for |x|, y < ~1e9; beyond that
-    // (lines with nu of a few 1e-3 cm^-1 or less) evaluate in FP64.
-    double xmax = fmax(fabs((double)(r.klo - r.kc) * a - b), fabs((double)(r.khi - r.kc) * a - b));
-    if (PROF == XS_VOIGT && (xmax > 1.0e9 || lp.y > 1.0e9)) r.flag = 1;
+    r.y = (float)lp.y;
+    if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+      r.rB = x_range(sqrt(160.0), a, b, kc, klo, khi);
+      r.rC = none;
+      zero = r.rB;
+      // a row inside the nonzero range takes the Gaussian directly
+      not1 = KRange{-0x7fffffff, 0x7fffffff};
+      if (r.rB.lo <= r.rB.hi) {
+        not1 = KRange{(int)klo, r.rB.lo - 1};   // bins left of the nonzero range
+      }
+      not2 = KRange{r.rB.hi + 1, (int)khi};     // bins right of it
+      can2 = false;
+    } else if (PROF == XS_VOIGT) {
+      r.rB = xr(900.0 * 1.001);
+      r.rC = xr(64.0 * 1.001);
+      // FP32 keeps u (u + q) + p^2 finite for |x|, y < ~1e9; lines beyond that
+      // (nu of a few 1e-3 cm^-1 or less) are evaluated in FP64.
+      const double xmax = fmax(fabs((double)(klo - kc) * a - b), fabs((double)(khi - kc) * a - b));
+      if (xmax > 1.0e9 || lp.y > 1.0e9) r.flag = 1;
+      zero = KRange{(int)klo, (int)khi};
+      not1 = r.rB;
+      not2 = r.rC;
+      can2 = true;
+    } else {
+      r.rB = none;
+      r.rC = none;
+      zero = KRange{(int)klo, (int)khi};
+      not1 = none;
+      not2 = none;
+      can2 = false;
+    }
   } else {
-    r.af = (float)a;
-    r.bf = (float)b;
-    r.y2f = (float)(lp.y * lp.y);
     r.nu = nu;
     r.inv = lp.inv;
     r.y = lp.y;
-    r.y2 = lp.y * lp.y;
-    r.q = 4.0 * lp.y * lp.y;
     r.c0 = lp.c0;
-    r.cy = lp.c0 * 2.0 * lp.y / kPI;
-  }
-  return true;
-}
-
-// Contribution of one line to one bin given x (profile value times c0),
-// FP32 form.  band: 1 = one Gauss-Hermite pair, 2 = two pairs, 0 = per lane.
-template <int PROF>
-__device__ __forceinline__ float eval_f32(const RecF& r, float x, int band) {
-  if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
-    return r.c0 * __builtin_amdgcn_exp2f(-x * x);
-  } else if (PROF == XS_LORENTZ) {
-    return r.c0 * __builtin_amdgcn_rcpf(fmaf(x, x, 1.0f));
-  } else {
-    const float u = x * x;
-    if (band == 1) return r.cy * gh_re_sum<1, float>(u, r.y2, r.q);
-    if (band == 2 || u + r.y2 >= 64.0f) return r.cy * gh_re_sum<2, float>(u, r.y2, r.q);
-    double wr, wi;
-    w_core<16>((double)x, (double)r.y, wr, wi);
-    return r.c0 * (float)wr;
-  }
-}
-
-// FP64 form: x from the exact difference nu_k - nu_i.
-template <int PROF>
-__device__ __forceinline__ double eval_f64(const RecD& r, double x, int band) {
-  if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
-    return r.c0 * exp2(-x * x);
-  } else if (PROF == XS_LORENTZ) {
-    return r.c0 / fma(x, x, 1.0);
-  } else {
-    const double u = x * x;
-    switch (band) {
-      case 1: return r.cy * gh_re_sum<1, double>(u, r.y2, r.q);
-      case 2: return r.cy * gh_re_sum<2, double>(u, r.y2, r.q);
-      case 3: return r.cy * gh_re_sum<3, double>(u, r.y2, r.q);
-      case 4: return r.cy * gh_re_sum<4, double>(u, r.y2, r.q);
-      case 6: return r.cy * gh_re_sum<6, double>(u, r.y2, r.q);
-      default: break;
+    if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+      r.r[0] = x_range(sqrt(1100.0), a, b, kc, klo, khi);
+      zero = r.r[0];
+      not1 = KRange{-0x7fffffff, 0x7fffffff};
+      if (r.r[0].lo <= r.r[0].hi) not1 = KRange{(int)klo, r.r[0].lo - 1};
+      not2 = KRange{r.r[0].hi + 1, (int)khi};
+      can2 = false;
+    } else if (PROF == XS_VOIGT) {
+      r.r[0] = xr(9.0e6 * 1.001);
+      r.r[1] = xr(6400.0 * 1.001);
+      r.r[2] = xr(400.0 * 1.001);
+      r.r[3] = xr(144.0 * 1.001);
+      r.r[4] = xr(64.0 * 1.001);
+      zero = KRange{(int)klo, (int)khi};
+      not1 = r.r[0];
+      not2 = r.r[1];
+      can2 = true;
+    } else {
+      zero = KRange{(int)klo, (int)khi};
+      not1 = none;
+      not2 = none;
+      can2 = false;
     }
-    if (u + r.y2 >= 64.0) return r.cy * gh_re_sum<6, double>(u, r.y2, r.q);
-    double wr, wi;
-    w_core<22>(x, r.y, wr, wi);
-    return r.c0 * wr;
   }
+  // For the Gaussian the "first formula" test is: row inside the nonzero range.
+  int cls = 0;
+#pragma unroll
+  for (int w = 0; w < WAVES; ++w) {
+    const int lo = (int)tlo + w * rowb, hi = lo + rowb - 1;
+    int c;
+    if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+      if (hi < klo || lo > khi || !meets(lo, hi, zero)) c = kRowSkip;
+      else if (klo <= lo && khi >= hi && !meets(lo, hi, not1) && !meets(lo, hi, not2)) c = kRowF1;
+      else c = kRowGeneral;
+    } else {
+      c = row_class(lo, hi, zero, not1, not2, can2);
+    }
+    cls |= c << (2 * w);
+  }
+  r.cls = cls;
+  return cls != 0;
 }
 
-// Smallest |x| over the row [row_lo, row_lo + nb - 1] from its end bins.
-__device__ __forceinline__ float row_min_abs_x(int row_lo, int nb, int kc, float a, float b) {
-  float x0 = fmaf((float)(row_lo - kc), a, -b);
-  float x1 = fmaf((float)(row_lo + nb - 1 - kc), a, -b);
-  if (x0 <= 0.0f && x1 >= 0.0f) return 0.0f;
-  return fminf(fabsf(x0), fabsf(x1));
+// ---- far-region evaluators ------------------------------------------------
+__device__ __forceinline__ double rcp64(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp32(float d) { return __builtin_amdgcn_rcpf(d); }
+
+template <typename R>
+__device__ __forceinline__ R pair_term(const Pair<R>& P, R u) {
+  const R n = fma(P.cw, u, P.cwp);
+  const R d = fma(u, u + P.q, P.p2);
+  if constexpr (sizeof(R) == 4) return n * rcp32(d);
+  else return n * rcp64(d);
+}
+// two pairs as one fraction (FP64 only: the product of the d_j stays finite)
+__device__ __forceinline__ double pair2_term(const Pair<double>& P, const Pair<double>& Q, double u) {
+  const double n1 = fma(P.cw, u, P.cwp), d1 = fma(u, u + P.q, P.p2);
+  const double n2 = fma(Q.cw, u, Q.cwp), d2 = fma(u, u + Q.q, Q.p2);
+  return fma(n1, d2, n2 * d1) * rcp64(d1 * d2);
+}
+// NP node pairs from y (near-core chunks of the FP64 form; out of line, rare)
+template <int NP>
+__device__ __noinline__ double gh_pairs_y(double c0, double y, double u) {
+  const double* tau = gh_tau<NP>();
+  const double* W = gh_w<NP>();
+  const double y2 = y * y, cy = c0 * 2.0 * y / kPI;
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    const double p = y2 + tau[j];
+    s = fma(cy * W[j] * (u + p), rcp64(fma(u, u + (2.0 * y2 - 2.0 * tau[j]), p * p)), s);
+  }
+  return s;
 }
 
-// Band of a row (every lane uses at least as many Gauss-Hermite nodes as its
-// own |z| requires, so rows do not diverge); 0: some lane may be in the core.
-template <int PROF>
-__device__ __forceinline__ int row_band_f32(float xmin, float y2) {
-  if (PROF != XS_VOIGT) return 1;
-  float rho = xmin * xmin + y2;
-  if (rho >= 900.0f * 1.001f) return 1;
-  if (rho >= 64.0f * 1.001f) return 2;
-  return 0;
-}
-template <int PROF>
-__device__ __forceinline__ int row_band_f64(float xmin, float y2) {
-  if (PROF != XS_VOIGT) return 1;
-  float rho = xmin * xmin + y2;
-  if (rho >= 9.0e6f * 1.001f) return 1;
-  if (rho >= 6400.0f * 1.001f) return 2;
-  if (rho >= 400.0f * 1.001f) return 3;
-  if (rho >= 144.0f * 1.001f) return 4;
-  if (rho >= 64.0f * 1.001f) return 6;
-  return 0;
+// Per-lane evaluation of a chunk that reaches |z| < 8 (FP32 form).
+__device__ __noinline__ float voigt_near_f32(float x, float y, float c0, Pair<float> B1, Pair<float> B2) {
+  const float u = x * x;
+  if (u + y * y >= 64.0f) return pair_term<float>(B1, u) + pair_term<float>(B2, u);
+  double wr, wi;
+  w_core<16>((double)x, (double)y, wr, wi);
+  return c0 * (float)wr;
 }
 
-// A Gaussian row whose smallest |x| makes 2^{-x^2} vanish in the working
-// precision contributes exactly zero and is skipped.
-template <int PROF>
-__device__ __forceinline__ bool row_zero(float xmin, bool f32) {
-  if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) return xmin * xmin > (f32 ? 160.0f : 1100.0f);
-  return false;
-}
-
+// Tile layout: wave w owns the row [row_lo, row_lo + 64 M); lane l owns the
+// bins row_lo + 64 j + l, j = 0..M-1, so each "chunk" j is 64 consecutive
+// bins.  A line's narrow core region falls into one or two chunks, and every
+// per-chunk decision (window, band, zero skip) is a scalar compare of the
+// chunk's bin range with the line's precomputed ranges.
 template <typename Real, int PROF, int M, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_gather(GatherArgs g) {
   using Rec = typename std::conditional<sizeof(Real) == 4, RecF, RecD>::type;
@@ -228,7 +349,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_gather(GatherArgs g) {
   __shared__ int s_wcnt[WAVES];
   __shared__ long long s_item;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // wave index made explicitly uniform so row and chunk bounds live in SGPRs
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const ModelDev& m = g.m;
   long long item = blockIdx.x;
   for (;;) {
@@ -248,7 +370,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_gather(GatherArgs g) {
     const int64_t bhi = min<int64_t>(m.n_buckets - 1, (thi + cd.wbins) / m.bucket_bins);
     const int64_t plo = g.off[blo], phi = g.off[bhi + 1];
     const int row_lo = (int)tlo + wave * ROWB;
-    const int my_lo = row_lo + lane * M;
+    const int row_hi = row_lo + ROWB - 1;
+    const int my0 = row_lo + lane;          // bin of chunk 0 of this lane
+    const float lane_off = (float)(wave * ROWB + lane);  // offset of that bin in the tile
 
     double acc64[M];
     float acc32[M];
@@ -257,7 +381,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_gather(GatherArgs g) {
     for (int j = 0; j < M; ++j) {
       acc64[j] = 0.0;
       acc32[j] = 0.0f;
-      if (!F32) nuk[j] = nu_of_bin(m.nu0, m.dnu, my_lo + j);
+      if (!F32) nuk[j] = nu_of_bin(m.nu0, m.dnu, my0 + 64 * j);
     }
 
     for (int64_t p0 = plo; p0 < phi; p0 += NT) {
@@ -265,7 +389,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_gather(GatherArgs g) {
       Rec r;
       bool keep = false;
       const int64_t p = p0 + tid;
-      if (p < phi) keep = stage_line<Rec, PROF>(g, cd, p, tlo, thi, r);
+      if (p < phi) keep = stage_line<Rec, PROF, WAVES>(g, cd, p, tlo, thi, ROWB, r);
       const unsigned long long bal = __ballot(keep);
       const int before = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
                                                    __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
@@ -283,69 +407,142 @@ __global__ __launch_bounds__(64 * WAVES) void k_gather(GatherArgs g) {
 
       // ---- evaluate every staged line over this wave's row ----
       for (int l = 0; l < total; ++l) {
-        const int kc = uni(srec[l].kc), klo = uni(srec[l].klo), khi = uni(srec[l].khi);
-        if (khi < row_lo || klo > row_lo + ROWB - 1) continue;
-        const bool full = klo <= row_lo && khi >= row_lo + ROWB - 1;
+        const Rec& rr = srec[l];
+        const int cls = (uni(rr.cls) >> (2 * wave)) & 3;
+        if (cls == kRowSkip) continue;
         if constexpr (F32) {
-          const RecF rr = srec[l];
-          const float a = uni(rr.a), b = uni(rr.b);
-          const float xmin = row_min_abs_x(row_lo, ROWB, kc, a, b);
-          if (row_zero<PROF>(xmin, true)) continue;
-          if (PROF == XS_VOIGT && uni(rr.flag)) {
+          // x = (k - k_c) a - b, with k - k_c = (tlo - k_c) + (offset in tile): integers,
+          // exact in FP32 within a window
+          const float a = rr.a, nb = rr.nb;
+          const float jf0 = rr.jfb + lane_off;
+          if (cls != kRowGeneral) {
+            if (PROF == XS_LORENTZ) {
+              const float c0 = rr.c0;
 #pragma unroll
-            for (int j = 0; j < M; ++j) {
-              const int k = my_lo + j;
-              if (k >= klo && k <= khi) {
-                double x = (double)(k - kc) * (double)a - (double)b;
-                acc32[j] += (float)((double)rr.c0 * re_w_f64(x, (double)rr.y));
+              for (int j = 0; j < M; ++j) {
+                const float x = fmaf(jf0 + (float)(64 * j), a, nb);
+                acc32[j] = fmaf(c0, rcp32(fmaf(x, x, 1.0f)), acc32[j]);
+              }
+            } else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+              const float c0 = rr.c0;
+#pragma unroll
+              for (int j = 0; j < M; ++j) {
+                const float x = fmaf(jf0 + (float)(64 * j), a, nb);
+                acc32[j] = fmaf(c0, __builtin_amdgcn_exp2f(-(x * x)), acc32[j]);
+              }
+            } else if (cls == kRowF1) {
+              const float cw = rr.A.cw, cwp = rr.A.cwp, q = rr.A.q, p2 = rr.A.p2;
+#pragma unroll
+              for (int j = 0; j < M; ++j) {
+                const float x = fmaf(jf0 + (float)(64 * j), a, nb);
+                const float u = x * x;
+                acc32[j] = fmaf(fmaf(cw, u, cwp), rcp32(fmaf(u, u + q, p2)), acc32[j]);
+              }
+            } else {
+              const Pair<float> B1 = rr.B1, B2 = rr.B2;
+#pragma unroll
+              for (int j = 0; j < M; ++j) {
+                const float x = fmaf(jf0 + (float)(64 * j), a, nb);
+                const float u = x * x;
+                acc32[j] += pair_term<float>(B1, u) + pair_term<float>(B2, u);
               }
             }
             continue;
           }
-          const int band = row_band_f32<PROF>(xmin, uni(rr.y2));
-          RecF ru = rr;
-          ru.y2 = uni(rr.y2);
-          ru.q = uni(rr.q);
-          ru.c0 = uni(rr.c0);
-          ru.cy = uni(rr.cy);
-          ru.y = uni(rr.y);
-          if (full) {
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-              const float x = fmaf((float)(my_lo + j - kc), a, -b);
-              acc32[j] += eval_f32<PROF>(ru, x, band);
-            }
-          } else {
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-              const int k = my_lo + j;
-              const float x = fmaf((float)(k - kc), a, -b);
-              const float v = eval_f32<PROF>(ru, x, band);
-              acc32[j] += (k >= klo && k <= khi) ? v : 0.0f;
-            }
-          }
-        } else {
-          const RecD rr = srec[l];
-          const float xmin = row_min_abs_x(row_lo, ROWB, kc, uni(rr.af), uni(rr.bf));
-          if (row_zero<PROF>(xmin, false)) continue;
-          const int band = row_band_f64<PROF>(xmin, uni(rr.y2f));
-          RecD ru = rr;
-          ru.nu = uni(rr.nu);
-          ru.inv = uni(rr.inv);
-          ru.y = uni(rr.y);
-          ru.y2 = uni(rr.y2);
-          ru.q = uni(rr.q);
-          ru.c0 = uni(rr.c0);
-          ru.cy = uni(rr.cy);
+          // general path: per-chunk decisions
+          const int klo = uni(rr.klo), khi = uni(rr.khi);
+          const KRange rB = {uni(rr.rB.lo), uni(rr.rB.hi)};
+          const KRange rC = {uni(rr.rC.lo), uni(rr.rC.hi)};
+          const bool flag = PROF == XS_VOIGT && uni(rr.flag);
 #pragma unroll
           for (int j = 0; j < M; ++j) {
-            const int k = my_lo + j;
-            double x;
-            {
-#pragma clang fp contract(off)
-              x = (nuk[j] - ru.nu) * ru.inv;
+            const int cl = row_lo + 64 * j, ch = cl + 63;
+            if (ch < klo || cl > khi) continue;
+            const bool full = cl >= klo && ch <= khi;
+            const int k = my0 + 64 * j;
+            const float x = fmaf(jf0 + (float)(64 * j), a, nb);
+            float v;
+            if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+              if (!meets(cl, ch, rB)) continue;  // 2^{-x^2} is 0 in FP32 on this chunk
+              v = rr.c0 * __builtin_amdgcn_exp2f(-(x * x));
+            } else if (PROF == XS_LORENTZ) {
+              v = rr.c0 * rcp32(fmaf(x, x, 1.0f));
+            } else if (flag) {
+              const double xd = (double)(k - rr.kc) * (double)a + (double)nb;
+              v = (full || (k >= klo && k <= khi)) ? (float)((double)rr.c0 * re_w_f64(xd, (double)rr.y)) : 0.0f;
+            } else if (!meets(cl, ch, rB)) {
+              const float u = x * x;
+              const Pair<float> A = rr.A;
+              v = fmaf(A.cw, u, A.cwp) * rcp32(fmaf(u, u + A.q, A.p2));
+            } else if (!meets(cl, ch, rC)) {
+              const float u = x * x;
+              v = pair_term<float>(rr.B1, u) + pair_term<float>(rr.B2, u);
+            } else {
+              v = voigt_near_f32(x, rr.y, rr.c0, rr.B1, rr.B2);
             }
-            const double v = eval_f64<PROF>(ru, x, band);
+            acc32[j] += (full || (k >= klo && k <= khi)) ? v : 0.0f;
+          }
+        } else {
+          // FP64 form: x from the exact difference nu_k - nu_i
+          const double nu = rr.nu, inv = rr.inv;
+          double xs[M];
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+#pragma clang fp contract(off)
+            xs[j] = (nuk[j] - nu) * inv;
+          }
+          if (cls != kRowGeneral) {
+            if (PROF == XS_LORENTZ) {
+              const double c0 = rr.c0;
+#pragma unroll
+              for (int j = 0; j < M; ++j) acc64[j] = fma(c0, rcp64(fma(xs[j], xs[j], 1.0)), acc64[j]);
+            } else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+              const double c0 = rr.c0;
+#pragma unroll
+              for (int j = 0; j < M; ++j) acc64[j] = fma(c0, exp2(-(xs[j] * xs[j])), acc64[j]);
+            } else if (cls == kRowF1) {
+              const Pair<double> A = rr.A;
+#pragma unroll
+              for (int j = 0; j < M; ++j) acc64[j] += pair_term<double>(A, xs[j] * xs[j]);
+            } else {
+              const Pair<double> B1 = rr.B1, B2 = rr.B2;
+#pragma unroll
+              for (int j = 0; j < M; ++j) acc64[j] += pair2_term(B1, B2, xs[j] * xs[j]);
+            }
+            continue;
+          }
+          const int klo = uni(rr.klo), khi = uni(rr.khi);
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            const int cl = row_lo + 64 * j, ch = cl + 63;
+            if (ch < klo || cl > khi) continue;
+            const bool full = cl >= klo && ch <= khi;
+            const int k = my0 + 64 * j;
+            const double x = xs[j];
+            double v;
+            if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+              if (!meets(cl, ch, KRange{uni(rr.r[0].lo), uni(rr.r[0].hi)})) continue;
+              v = rr.c0 * exp2(-(x * x));
+            } else if (PROF == XS_LORENTZ) {
+              v = rr.c0 * rcp64(fma(x, x, 1.0));
+            } else {
+              const double u = x * x;
+              if (!meets(cl, ch, KRange{uni(rr.r[0].lo), uni(rr.r[0].hi)})) {
+                v = pair_term<double>(rr.A, u);
+              } else if (!meets(cl, ch, KRange{uni(rr.r[1].lo), uni(rr.r[1].hi)})) {
+                v = pair2_term(rr.B1, rr.B2, u);
+              } else if (!meets(cl, ch, KRange{uni(rr.r[2].lo), uni(rr.r[2].hi)})) {
+                v = gh_pairs_y<3>(rr.c0, rr.y, u);
+              } else if (!meets(cl, ch, KRange{uni(rr.r[3].lo), uni(rr.r[3].hi)})) {
+                v = gh_pairs_y<4>(rr.c0, rr.y, u);
+              } else if (!meets(cl, ch, KRange{uni(rr.r[4].lo), uni(rr.r[4].hi)}) || u + rr.y * rr.y >= 64.0) {
+                v = gh_pairs_y<6>(rr.c0, rr.y, u);
+              } else {
+                double wr, wi;
+                w_core<22>(x, rr.y, wr, wi);
+                v = rr.c0 * wr;
+              }
+            }
             if (full || (k >= klo && k <= khi)) acc64[j] += v;
           }
         }
@@ -365,7 +562,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_gather(GatherArgs g) {
     double* out = g.sigma + (int64_t)c * m.n_bins;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      const int64_t k = my_lo + j;
+      const int64_t k = my0 + 64 * j;
       if (k <= thi) {
         const double v = scale * acc64[j];
         out[k] = g.accumulate ? out[k] + v : v;
@@ -383,7 +580,7 @@ static void gather_dispatch(const GatherArgs& a, const Tiling& t, int blocks, hi
     hipLaunchKernelGGL((k_gather<Real, PROF, MM, WW>), dim3(blocks), dim3(64 * WW), 0, s, a); \
     return;                                                                                \
   }
-  XS_G(2, 4) XS_G(4, 4) XS_G(8, 4) XS_G(4, 8) XS_G(2, 8)
+  XS_G(4, 1) XS_G(8, 1) XS_G(4, 2) XS_G(8, 2) XS_G(2, 4) XS_G(4, 4) XS_G(8, 4)
 #undef XS_G
 }
 
@@ -418,6 +615,41 @@ void launch_gather(const ModelDev& m, const Work& w, const Tiling& t, double* si
     XS_P(double, XS_DOPPLER) XS_P(double, XS_GAUSSIAN) XS_P(double, XS_LORENTZ) XS_P(double, XS_VOIGT)
   }
 #undef XS_P
+}
+
+// Evaluators of the scatter (one lane per bin, band per lane).
+struct ScatF {
+  float a, b, y, y2, q, c0, cy;
+};
+struct ScatD {
+  double nu, inv, y, y2, q, c0, cy;
+};
+
+template <int PROF>
+__device__ __forceinline__ float eval_f32(const ScatF& r, float x) {
+  if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+    return r.c0 * __builtin_amdgcn_exp2f(-x * x);
+  } else if (PROF == XS_LORENTZ) {
+    return r.c0 * __builtin_amdgcn_rcpf(fmaf(x, x, 1.0f));
+  } else {
+    const float u = x * x;
+    if (u + r.y2 >= 900.0f) return r.cy * gh_re_sum<1, float>(u, r.y2, r.q);
+    if (u + r.y2 >= 64.0f) return r.cy * gh_re_sum<2, float>(u, r.y2, r.q);
+    double wr, wi;
+    w_core<16>((double)x, (double)r.y, wr, wi);
+    return r.c0 * (float)wr;
+  }
+}
+
+template <int PROF>
+__device__ __forceinline__ double eval_f64(const ScatD& r, double x) {
+  if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+    return r.c0 * exp2(-x * x);
+  } else if (PROF == XS_LORENTZ) {
+    return r.c0 / fma(x, x, 1.0);
+  } else {
+    return r.c0 * re_w_f64(x, r.y);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -458,10 +690,9 @@ __global__ __launch_bounds__(256) void k_scatter(ScatterArgs g) {
     LineParams lp = line_params<PROF>(m, cd, nu, (double)g.rgref[p], (double)g.rnexp[p], S);
     double* out = g.sigma + (int64_t)c * m.n_bins;
     if constexpr (sizeof(Real) == 4) {
-      RecF r;
+      ScatF r;
       const int64_t kc = home_bin(nu, m.nu0, m.dnu);
       const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
-      r.kc = (int)kc;
       r.a = (float)(m.dnu * lp.inv);
       r.b = (float)(delta * lp.inv);
       r.y = (float)lp.y;
@@ -478,13 +709,13 @@ __global__ __launch_bounds__(256) void k_scatter(ScatterArgs g) {
         if (wide)
           v = (float)(lp.c0 * re_w_f64((double)(k - kc) * (double)r.a - (double)r.b, lp.y));
         else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN)
-          v = (x * x > 160.0f) ? 0.0f : eval_f32<PROF>(r, x, 1);
+          v = (x * x > 160.0f) ? 0.0f : eval_f32<PROF>(r, x);
         else
-          v = eval_f32<PROF>(r, x, 0);
+          v = eval_f32<PROF>(r, x);
         if (v != 0.0f) unsafeAtomicAdd(out + k, scale * (double)v);
       }
     } else {
-      RecD r;
+      ScatD r;
       r.nu = nu;
       r.inv = lp.inv;
       r.y = lp.y;
@@ -500,9 +731,9 @@ __global__ __launch_bounds__(256) void k_scatter(ScatterArgs g) {
         }
         double v;
         if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN)
-          v = (x * x > 1100.0) ? 0.0 : eval_f64<PROF>(r, x, 1);
+          v = (x * x > 1100.0) ? 0.0 : eval_f64<PROF>(r, x);
         else
-          v = eval_f64<PROF>(r, x, 0);
+          v = eval_f64<PROF>(r, x);
         if (v != 0.0) unsafeAtomicAdd(out + k, v);
       }
     }

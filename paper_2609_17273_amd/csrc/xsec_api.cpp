@@ -145,9 +145,11 @@ int validate_lines(const xs_plan* p, const xs_lines* l) {
 
 int validate_config(const xs_config* c) {
   if (!c) return fail(XS_EINVAL, "config is NULL");
-  const int t = c->tile_bins;
-  const bool ok_tile = (t == 512 || t == 1024 || t == 2048);
-  if (!ok_tile) return fail(XS_EINVAL, "config.tile_bins must be 512, 1024 or 2048");
+  if (c->tile_waves != 1 && c->tile_waves != 2 && c->tile_waves != 4)
+    return fail(XS_EINVAL, "config.tile_waves must be 1, 2 or 4");
+  const int per_lane = c->tile_bins / (64 * c->tile_waves);
+  if (per_lane * 64 * c->tile_waves != c->tile_bins || (per_lane != 2 && per_lane != 4 && per_lane != 8))
+    return fail(XS_EINVAL, "config.tile_bins must be tile_waves x 64 x (2, 4 or 8)");
   const int b = c->bucket_bins;
   if (b < 64 || b > 4096 || (b & (b - 1))) return fail(XS_EINVAL, "config.bucket_bins must be a power of two in [64, 4096]");
   if (c->persistent != 0 && c->persistent != 1) return fail(XS_EINVAL, "config.persistent must be 0 or 1");
@@ -180,15 +182,12 @@ LinesView view(const xs_lines* l) {
   return v;
 }
 
-// Tile shape for a tile size: 64 lanes x per_lane bins x waves.
-void tiling_for(xs_plan* p, int tile_bins, int persistent, int waves_per_cu) {
+// Tile shape: tile_waves waves x 64 lanes x per-lane bins.
+void tiling_for(xs_plan* p, int tile_bins, int persistent, int waves_per_cu, int tile_waves) {
   Tiling t;
   t.tile_bins = tile_bins;
-  t.waves = 4;
-  t.per_lane = tile_bins / 256;
-  if (tile_bins == 2048) {  // 8 bins per lane, 4 waves
-    t.per_lane = 8;
-  }
+  t.waves = tile_waves;
+  t.per_lane = tile_bins / (64 * tile_waves);
   t.persistent = persistent;
   t.grid_blocks = std::max(1, p->n_cu * waves_per_cu / t.waves);
   p->tiling = t;
@@ -404,7 +403,7 @@ int xs_plan_create(xs_plan** out, const xs_model* model, const xs_grid* grid, in
   p->n_cu = prop.multiProcessorCount;
   p->arch = prop.gcnArchName;
   derive(p);
-  tiling_for(p, 1024, 1, 16);
+  tiling_for(p, 512, 0, 16, 1);
   std::memset(&p->w, 0, sizeof(p->w));
   *out = p;
   g_err.clear();
@@ -486,7 +485,7 @@ int xs_plan_set_config(xs_plan* p, const xs_config* c) {
       if ((rc = upload(p))) return rc;
     }
   }
-  tiling_for(p, c->tile_bins, c->persistent, c->waves_per_cu);
+  tiling_for(p, c->tile_bins, c->persistent, c->waves_per_cu, c->tile_waves);
   return XS_OK;
 }
 
@@ -496,6 +495,7 @@ int xs_plan_get_config(const xs_plan* p, xs_config* c) {
   c->bucket_bins = p->bucket_bins;
   c->persistent = p->tiling.persistent;
   c->waves_per_cu = p->tiling.grid_blocks * p->tiling.waves / std::max(1, p->n_cu);
+  c->tile_waves = p->tiling.waves;
   return XS_OK;
 }
 
@@ -661,13 +661,14 @@ static bool cache_lookup(const char* path, const std::string& key, xs_config* c)
   bool found = false;
   while (std::fgets(line, sizeof(line), f)) {
     char k[256];
-    int t, b, per, wv;
-    if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"tile_bins\": %d, \"bucket_bins\": %d, \"persistent\": %d, \"waves_per_cu\": %d",
-                    k, &t, &b, &per, &wv) == 5 && key == k) {
+    int t, b, per, wv, tw;
+    if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"tile_bins\": %d, \"bucket_bins\": %d, \"persistent\": %d, \"waves_per_cu\": %d, \"tile_waves\": %d",
+                    k, &t, &b, &per, &wv, &tw) == 6 && key == k) {
       c->tile_bins = t;
       c->bucket_bins = b;
       c->persistent = per;
       c->waves_per_cu = wv;
+      c->tile_waves = tw;
       found = true;
     }
   }
@@ -679,8 +680,8 @@ static void cache_store(const char* path, const std::string& key, const xs_confi
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "{\"key\": \"%s\", \"tile_bins\": %d, \"bucket_bins\": %d, \"persistent\": %d, \"waves_per_cu\": %d, \"ms\": %.4f}\n",
-               key.c_str(), c.tile_bins, c.bucket_bins, c.persistent, c.waves_per_cu, ms);
+  std::fprintf(f, "{\"key\": \"%s\", \"tile_bins\": %d, \"bucket_bins\": %d, \"persistent\": %d, \"waves_per_cu\": %d, \"tile_waves\": %d, \"ms\": %.4f}\n",
+               key.c_str(), c.tile_bins, c.bucket_bins, c.persistent, c.waves_per_cu, c.tile_waves, ms);
   std::fclose(f);
 }
 
@@ -700,40 +701,39 @@ int xs_plan_autotune(xs_plan* p, const xs_states* st, const xs_lines* ln, double
     (void)hipEventDestroy(e0);
     return rc;
   }
-  const int tiles[3] = {512, 1024, 2048};
-  const int waves[3] = {8, 16, 32};
+  // candidates: (tile_waves, bins per lane) and persistent or not
+  const int shapes[7][2] = {{1, 4}, {1, 8}, {2, 4}, {2, 8}, {4, 2}, {4, 4}, {4, 8}};
   double best_ms = 1e300;
   xs_config cur;
   cur.bucket_bins = p->bucket_bins;
-  for (int ti = 0; ti < 3 && !rc; ++ti) {
+  for (int si = 0; si < 7 && !rc; ++si) {
     for (int per = 0; per < 2 && !rc; ++per) {
-      for (int wi = 0; wi < (per ? 3 : 1) && !rc; ++wi) {
-        cur.tile_bins = tiles[ti];
-        cur.persistent = per;
-        cur.waves_per_cu = per ? waves[wi] : 16;
-        tiling_for(p, cur.tile_bins, cur.persistent, cur.waves_per_cu);
-        float ms_best = 1e30f;
-        for (int rep = 0; rep < 3 && !rc; ++rep) {
-          launch_reset(p->w, p->stream);
-          (void)hipEventRecord(e0, p->stream);
-          rc = profile_pass(p, sigma, 0);
-          (void)hipEventRecord(e1, p->stream);
-          if (!rc) rc = hip_check(hipEventSynchronize(e1), "autotune sync");
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          if (rep > 0) ms_best = std::min(ms_best, ms);
-        }
-        if (!rc && ms_best < best_ms) {
-          best_ms = ms_best;
-          best = cur;
-        }
+      cur.tile_waves = shapes[si][0];
+      cur.tile_bins = shapes[si][0] * 64 * shapes[si][1];
+      cur.persistent = per;
+      cur.waves_per_cu = per ? 32 : 16;
+      tiling_for(p, cur.tile_bins, cur.persistent, cur.waves_per_cu, cur.tile_waves);
+      float ms_best = 1e30f;
+      for (int rep = 0; rep < 3 && !rc; ++rep) {
+        launch_reset_queue(p->w, p->stream);
+        (void)hipEventRecord(e0, p->stream);
+        rc = profile_pass(p, sigma, 0);
+        (void)hipEventRecord(e1, p->stream);
+        if (!rc) rc = hip_check(hipEventSynchronize(e1), "autotune sync");
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) ms_best = std::min(ms_best, ms);
+      }
+      if (!rc && ms_best < best_ms) {
+        best_ms = ms_best;
+        best = cur;
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  tiling_for(p, best.tile_bins, best.persistent, best.waves_per_cu);
+  tiling_for(p, best.tile_bins, best.persistent, best.waves_per_cu, best.tile_waves);
   cache_store(cache_path, key, best, best_ms);
   return XS_OK;
 }
