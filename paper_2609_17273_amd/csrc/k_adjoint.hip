@@ -9,9 +9,10 @@
 //   dL/dn_i         += S C gamma ln(T_ref/T)
 //   dL/dT_c         += S [A dlnS/dT + B sg/(2T) - C n gamma/T]
 //   dL/dP_c         += S C gamma / P
-// One wave owns one sorted line (all conditions), lanes stride the window;
-// sums are FP64.  Blocks own fixed line sets and the per-condition scalars
-// are reduced in a fixed order, so results are deterministic.
+// Lanes own lines (a per-line reduction over bins needs no cross-lane sums);
+// FP32 partial sums are flushed to FP64.  Blocks own fixed line sets and the
+// per-condition scalars are reduced in a fixed order, so results are
+// deterministic.
 #include "k_common.h"
 
 namespace xs {
@@ -125,32 +126,276 @@ __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return __builtin_amdgcn_readfirstlane(v);
+}
 
+__device__ __forceinline__ float arcp(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double arcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
+// One Gauss-Hermite node pair (tau = t^2, weight W) of the far-region form
+//   Re w = y sum_j K_j (u + p_j)/d_j,  d_j = u (u + q_j) + p_j^2,
+//   p_j = y^2 + tau_j,  q_j = 2 y^2 - 2 tau_j,  K_j = 2 W_j / pi,  u = x^2,
+// and its derivatives, with e = (u + p)/d:
+//   dRe w/dy  = sum_j K_j [(u + p + 2 y^2)/d - 4 y^2 e^2]
+//   x dRe w/dx = 2 y sum_j K_j (u/d) [(p^2 - p q)/d - (u/d)(u + 2 p)]
+// Every product is formed from ratios of size <= 1/u, so FP32 neither
+// overflows nor underflows for |x|, y < 1e9.
+template <typename R>
+struct PairD {
+  R q, p2, p, c3, K;
+};
+template <typename R>
+__device__ __forceinline__ PairD<R> pair_d(double y, double tau, double W) {
+  const double y2 = y * y, p = y2 + tau, q = 2.0 * y2 - 2.0 * tau;
+  PairD<R> r;
+  r.q = (R)q;
+  r.p2 = (R)(p * p);
+  r.p = (R)p;
+  r.c3 = (R)(p * (p - q));
+  r.K = (R)(2.0 * W / kPI);
+  return r;
+}
+template <typename R>
+__device__ __forceinline__ void pair_adj(const PairD<R>& P, R u, R ty2, R fy2, R& e, R& s, R& t) {
+  const R d = fma(u, u + P.q, P.p2);
+  const R rd = arcp(d);
+  const R n1 = u + P.p;
+  e = n1 * rd;
+  s = fma(-fy2 * e, e, fma(ty2, rd, e));
+  const R ur = u * rd;
+  t = ur * fma(-ur, n1 + P.p, P.c3 * rd);
+}
+
+// Per-lane state of one line under one condition.
+template <typename R>
+struct AdjLine {
+  R a, nb;            // x = r a + nb, r = k - k_c
+  R ty2, fy2;         // 2 y^2, 4 y^2
+  PairD<R> P[3];      // node pairs of the far-region levels (Voigt)
+  double ad, bd, y;   // FP64 copies for the general path
+  int kc, rlo, rhi;   // home bin; window in r
+};
+
+// Far-region levels of the Voigt adjoint: level l uses the rule with l+1 node
+// pairs where rho = x^2 + y^2 >= kLev[l]; inside the last level the general
+// per-lane path picks more pairs or the Taylor core.
+template <typename R>
+struct Levels;
+template <>
+struct Levels<float> {
+  static constexpr int n = 2;
+  static constexpr double rho[2] = {900.0, 64.0};
+};
+template <>
+struct Levels<double> {
+  static constexpr int n = 3;
+  static constexpr double rho[3] = {9.0e6, 6400.0, 400.0};
+};
+
+// Voigt values for the general path, out of line (Taylor core and up to six
+// node pairs): Re w, Re G and Im w' at (x, y) with the given band.
+template <typename R>
+struct Grad3 {
+  R f, fs, fg;
+};
+template <typename R>
+__device__ __noinline__ Grad3<R> voigt_grad(R x, R y, int band) {
+  Grad3<R> g;
+  prof_grad<R, XS_VOIGT>(x, y, 0.0, 0.0, band, g.f, g.fs, g.fg);
+  return g;
+}
+
+// General per-lane evaluation at r (masked by the window): old-convention
+// values Re w / Re G / Im w' (Voigt), e / e (2 ln2 u - 1) (Gaussian),
+// 1/(1+u) / (u-1)/(1+u)^2 (Lorentz), accumulated in FP64.
+template <typename R, int PROF>
+__device__ __forceinline__ void general_eval(const AdjLine<R>& L, bool wide, int r, double gk, double& sA,
+                                             double& sB, double& sC) {
+  if (PROF == XS_VOIGT) {
+    double f, fs, fg;
+    if (sizeof(R) == 4 && wide) {
+      const Grad3<double> v = voigt_grad<double>((double)r * L.ad - L.bd, L.y, 0);
+      f = v.f;
+      fs = v.fs;
+      fg = v.fg;
+    } else {
+      const R x = fma((R)r, L.a, L.nb);
+      const R y = (R)L.y;
+      const R rho = x * x + y * y;
+      int band;
+      if (sizeof(R) == 4) band = rho >= (R)(900.0 * 1.001) ? 1 : (rho >= (R)(64.0 * 1.001) ? 2 : 0);
+      else band = rho >= (R)(9.0e6 * 1.001) ? 1 : rho >= (R)(6400.0 * 1.001) ? 2 : rho >= (R)(400.0 * 1.001) ? 3
+                : rho >= (R)(144.0 * 1.001) ? 4 : rho >= (R)(64.0 * 1.001) ? 6 : 0;
+      const Grad3<R> v = voigt_grad<R>(x, y, band);
+      f = (double)v.f;
+      fs = (double)v.fs;
+      fg = (double)v.fg;
+    }
+    sA = fma(gk, f, sA);
+    sB = fma(gk, fs, sB);
+    sC = fma(gk, fg, sC);
+  } else {
+    const R x = fma((R)r, L.a, L.nb);
+    R f, fs, fg;
+    prof_grad<R, PROF>(x, (R)0, 0.0, 0.0, 1, f, fs, fg);
+    sA = fma(gk, (double)f, sA);
+    sB = fma(gk, (double)fs, sB);
+    sC = fma(gk, (double)fg, sC);
+  }
+}
+
+// Fast loop over r in [r0, r1], every lane inside its window and (Voigt) in
+// the far region of level NP-1.  FP32 partial sums are flushed to FP64 every
+// kFlush steps.
+constexpr int kFlush = 256;
+
+template <typename R, int PROF, int NP>
+__device__ __forceinline__ void fast_range(const AdjLine<R>& L, const double* __restrict__ gc, int r0, int r1,
+                                           double& sA, double& sB, double& sC) {
+  for (int rb = r0; rb <= r1; rb += kFlush) {
+    const int n = min(kFlush, r1 - rb + 1);
+    const double* gp = gc + (L.kc + rb);
+    R s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll 4
+    for (int j = 0; j < n; ++j) {
+      const R x = fma((R)(rb + j), L.a, L.nb);
+      const R u = x * x;
+      const R gk = (R)gp[j];
+      if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+        R e;
+        if constexpr (sizeof(R) == 4) e = __builtin_amdgcn_exp2f(-u);
+        else e = exp2(-u);
+        const R ge = gk * e;
+        s1 += ge;
+        s2 = fma(ge, u, s2);
+      } else if (PROF == XS_LORENTZ) {
+        const R iq = arcp(u + (R)1);
+        const R gi = gk * iq;
+        s1 += gi;
+        s2 = fma(gi, iq, s2);
+      } else {
+        R e, s, t;
+        pair_adj<R>(L.P[0], u, L.ty2, L.fy2, e, s, t);
+        if constexpr (NP >= 2) {
+          e *= L.P[0].K;
+          s *= L.P[0].K;
+          t *= L.P[0].K;
+#pragma unroll
+          for (int q = 1; q < NP; ++q) {
+            R e2, sq, t2;
+            pair_adj<R>(L.P[q], u, L.ty2, L.fy2, e2, sq, t2);
+            e = fma(L.P[q].K, e2, e);
+            s = fma(L.P[q].K, sq, s);
+            t = fma(L.P[q].K, t2, t);
+          }
+        }
+        s1 = fma(gk, e, s1);
+        s2 = fma(gk, t, s2);
+        s3 = fma(gk, s, s3);
+      }
+    }
+    // to the general-path convention
+    if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+      sA += (double)s1;
+      sB += 2.0 * kLN2 * (double)s2 - (double)s1;
+    } else if (PROF == XS_LORENTZ) {
+      sA += (double)s1;
+      sC += (double)s1 - 2.0 * (double)s2;
+    } else {
+      const double k = (NP == 1) ? (double)L.P[0].K : 1.0;
+      const double e = k * (double)s1, t = k * (double)s2, w = k * (double)s3;
+      sA += L.y * e;                      // Re w
+      sB += L.y * (e + 2.0 * t) + L.y * w; // Re w + x dRe w/dx + y dRe w/dy
+      sC -= w;                            // Im w' = -dRe w/dy
+    }
+  }
+}
+
+template <typename R, int PROF>
+__device__ __forceinline__ void fast_level(int level, const AdjLine<R>& L, const double* gc, int r0, int r1,
+                                           double& sA, double& sB, double& sC) {
+  if (PROF != XS_VOIGT || level == 0) fast_range<R, PROF, 1>(L, gc, r0, r1, sA, sB, sC);
+  else if (level == 1) fast_range<R, PROF, 2>(L, gc, r0, r1, sA, sB, sC);
+  else if constexpr (sizeof(R) == 8) fast_range<R, PROF, 3>(L, gc, r0, r1, sA, sB, sC);
+}
+
+// r-range of the bins where |x| < X (widened by one bin), clipped to
+// [lo - 1, hi + 1]; empty ranges are lo > hi.
+__device__ __forceinline__ void r_range(double X, double a, double b, int lo, int hi, int& rl, int& rh) {
+  if (!(X > 0.0)) {
+    rl = 0x7fffffff;
+    rh = -0x7fffffff;
+    return;
+  }
+  const double l = fmax(floor((b - X) / a) - 1.0, (double)lo - 1.0);
+  const double h = fmin(ceil((b + X) / a) + 1.0, (double)hi + 1.0);
+  if (l > h) {
+    rl = 0x7fffffff;
+    rh = -0x7fffffff;
+  } else {
+    rl = (int)l;
+    rh = (int)h;
+  }
+}
+
+// One wave owns 64 consecutive sorted lines (one per lane) and walks all of
+// their windows together in steps of r = k - k_c.  Lanes of a wave hold lines
+// of nearly equal wavenumber and width, so at a given r they need the same
+// formula: the r axis is cut into uniform runs (far-region levels, the
+// general core, masked window ends) decided once per wave.
 template <typename R, int PROF>
 __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
   __shared__ double sdt[4][kMaxCond];
   __shared__ double sdp[4][kMaxCond];
   const ModelDev& m = a.m;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int c = threadIdx.x; c < kMaxCond; c += 256)
     for (int w = 0; w < 4; ++w) sdt[w][c] = sdp[w][c] = 0.0;
   __syncthreads();
   const int64_t nk = a.off[m.n_buckets];
+  const int64_t nbatch = (nk + 63) >> 6;
   const double sqrt2ln2 = sqrt(2.0 * kLN2);
-  for (int64_t p = (int64_t)blockIdx.x * 4 + wave; p < nk; p += (int64_t)gridDim.x * 4) {
-    const double nu = a.rnu[p];
-    const double gref = (double)a.rgref[p], nexp = (double)a.rnexp[p];
-    const int32_t i = a.ridx[p];
-    const double Eu = a.st.E[a.ln.up[i]], El = a.st.E[a.ln.lo[i]];
+  for (int64_t bt = (int64_t)blockIdx.x * 4 + wave; bt < nbatch; bt += (int64_t)gridDim.x * 4) {
+    const int64_t p = bt * 64 + lane;
+    const bool have = p < nk;
+    double nu = 0.0, gref = 0.0, nexp = 0.0, Eu = 0.0, El = 0.0;
+    int32_t i = 0;
+    if (have) {
+      nu = a.rnu[p];
+      gref = (double)a.rgref[p];
+      nexp = (double)a.rnexp[p];
+      i = a.ridx[p];
+      Eu = a.st.E[a.ln.up[i]];
+      El = a.st.E[a.ln.lo[i]];
+    }
     double dls = 0.0, dgr = 0.0, dne = 0.0;
     for (int c = 0; c < m.n_cond; ++c) {
       const CondDev cd = a.cond[c];
-      int64_t klo, khi;
-      if (!line_window(nu, cd.cut, m.nu0, m.dnu, m.n_bins, klo, khi)) continue;
-      double S = (sizeof(R) == 4)
-                     ? (double)((const float*)a.rS)[(int64_t)cd.slot * a.max_lines + p] * exp(a.sb[cd.slot])
-                     : ((const double*)a.rS)[(int64_t)cd.slot * a.max_lines + p];
-      if (S == 0.0) continue;
+      int64_t klo = 0, khi = -1;
+      bool on = have && line_window(nu, cd.cut, m.nu0, m.dnu, m.n_bins, klo, khi);
+      double S = 0.0;
+      if (on) {
+        S = (sizeof(R) == 4)
+                ? (double)((const float*)a.rS)[(int64_t)cd.slot * a.max_lines + p] * exp(a.sb[cd.slot])
+                : ((const double*)a.rS)[(int64_t)cd.slot * a.max_lines + p];
+        on = S != 0.0;
+      }
+      if (__ballot(on) == 0) continue;
       const double alpha = (PROF == XS_GAUSSIAN) ? cd.hwhm : nu * cd.dop;
       const double sgm = alpha / sqrt2ln2;
       const double gpow = exp(nexp * cd.lnTr);
@@ -162,44 +407,114 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
         inv = sqrt(kLN2) / alpha;
         y = gam * inv;
       }
-      const int64_t kc = home_bin(nu, m.nu0, m.dnu);
-      const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
-      const R ra = (R)(m.dnu * inv), rb = (R)(delta * inv), ry = (R)y;
-      double sA = 0.0, sB = 0.0, sC = 0.0;
-      const double* gc = a.g + (int64_t)c * m.n_bins;
-      for (int64_t k0 = klo; k0 <= khi; k0 += 64) {
-        // row band from the end bins (uniform across the wave)
-        int band = 1;
-        if (PROF == XS_VOIGT) {
-          const double k1 = (double)(k0 + 63 < khi ? k0 + 63 : khi);
-          const double x0 = (double)(k0 - kc) * (double)ra - (double)rb;
-          const double x1 = (k1 - (double)kc) * (double)ra - (double)rb;
-          const double xm = (x0 <= 0.0 && x1 >= 0.0) ? 0.0 : fmin(fabs(x0), fabs(x1));
-          const double rho = xm * xm + y * y;
-          if (sizeof(R) == 4) band = rho >= 900.0 * 1.001 ? 1 : (rho >= 64.0 * 1.001 ? 2 : 0);
-          else band = rho >= 9.0e6 * 1.001 ? 1 : rho >= 6400.0 * 1.001 ? 2 : rho >= 400.0 * 1.001 ? 3
-                    : rho >= 144.0 * 1.001 ? 4 : rho >= 64.0 * 1.001 ? 6 : 0;
+      const int64_t kc64 = home_bin(nu, m.nu0, m.dnu);
+      const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc64);
+      AdjLine<R> L;
+      L.kc = (int)kc64;
+      L.rlo = on ? (int)(klo - kc64) : 0x7fffffff;
+      L.rhi = on ? (int)(khi - kc64) : -0x7fffffff;
+      L.ad = m.dnu * inv;
+      L.bd = delta * inv;
+      L.y = y;
+      L.a = (R)L.ad;
+      L.nb = (R)(-L.bd);
+      L.ty2 = (R)(2.0 * y * y);
+      L.fy2 = (R)(4.0 * y * y);
+      bool wide = false;
+      if (PROF == XS_VOIGT) {
+        L.P[0] = pair_d<R>(y, GH::t2[0], GH::w2[0]);
+        L.P[1] = pair_d<R>(y, GH::t4[0], GH::w4[0]);
+        L.P[2] = pair_d<R>(y, GH::t4[1], GH::w4[1]);
+        if (sizeof(R) == 8) {
+          // FP64 levels: 1, 2 and 3 node pairs; pairs of the 3-pair rule are
+          // set when that level is entered.
         }
-        const int64_t k = k0 + lane;
-        if (k <= khi) {
-          R x;
-          if constexpr (sizeof(R) == 4) {
-            x = fmaf((float)(k - kc), ra, -rb);
-          } else {
-#pragma clang fp contract(off)
-            x = (nu_of_bin(m.nu0, m.dnu, k) - nu) * inv;
-          }
-          R f, fs, fg;
-          prof_grad<R, PROF>(x, ry, sgm, gam, band, f, fs, fg);
-          const double gk = gc[k];
-          sA += gk * (double)f;
-          sB += gk * (double)fs;
-          sC += gk * (double)fg;
+        if (sizeof(R) == 4 && on) {
+          const double xmax = fmax(fabs((double)L.rlo * L.ad - L.bd), fabs((double)L.rhi * L.ad - L.bd));
+          wide = xmax > 1.0e9 || y > 1.0e9;
         }
       }
-      sA = wave_sum(sA);
-      sB = wave_sum(sB);
-      sC = wave_sum(sC);
+      // uniform runs along r
+      const int Rmin = wave_min(L.rlo), Rmax = wave_max(L.rhi);
+      const int Alo = wave_max(on ? L.rlo : -0x7fffffff), Ahi = wave_min(on ? L.rhi : 0x7fffffff);
+      const bool any_wide = __ballot(wide) != 0;
+      constexpr int NL = (PROF == XS_VOIGT) ? Levels<R>::n : 1;
+      int Hlo[NL], Hhi[NL];
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        int rl = 0x7fffffff, rh = -0x7fffffff;
+        if (on) {
+          double X;
+          if (PROF == XS_VOIGT) X = sqrt(fmax(Levels<R>::rho[l] * 1.001 - y * y, 0.0));
+          else if (PROF == XS_LORENTZ) X = 0.0;  // one level, no inner region
+          else X = (sizeof(R) == 4) ? sqrt(160.0) : sqrt(1100.0);  // Gaussian: nonzero range
+          r_range(X, L.ad, L.bd, L.rlo, L.rhi, rl, rh);
+        }
+        Hlo[l] = wave_min(rl);
+        Hhi[l] = wave_max(rh);
+      }
+      double sA = 0.0, sB = 0.0, sC = 0.0;
+      const double* gc = a.g + (int64_t)c * m.n_bins;
+      if (on) {
+        int r = Rmin;
+        while (r <= Rmax) {
+          int end, mode;  // mode: -2 skip, -1 general, l >= 0 fast level l
+          if (any_wide || r < Alo || r > Ahi) {
+            mode = -1;
+            end = (any_wide || r > Ahi) ? Rmax : Alo - 1;
+          } else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+            // outside the nonzero hull every lane's Gaussian is exactly 0
+            if (Hlo[0] > Hhi[0] || r > Hhi[0]) { mode = -2; end = Ahi; }
+            else if (r < Hlo[0]) { mode = -2; end = Hlo[0] - 1; }
+            else { mode = 0; end = min(Hhi[0], Ahi); }
+          } else if (PROF == XS_LORENTZ) {
+            mode = 0;
+            end = Ahi;
+          } else {
+            // deepest level whose hull holds r
+            int l = 0;
+#pragma unroll
+            for (int q = 0; q < NL; ++q)
+              if (l == q && Hlo[q] <= r && r <= Hhi[q]) l = q + 1;
+            if (l == NL) {
+              mode = -1;
+              end = min(Hhi[NL - 1], Ahi);
+            } else {
+              mode = l;
+              if (Hlo[l] <= Hhi[l] && r < Hlo[l]) end = Hlo[l] - 1;   // up to the next inner hull
+              else end = (l == 0) ? Ahi : Hhi[l - 1];                  // to the end of this hull
+              end = min(end, Ahi);
+            }
+          }
+          if (mode >= 0) {
+            if (PROF == XS_VOIGT && sizeof(R) == 8 && mode == 2) {
+              AdjLine<R> L3 = L;
+              L3.P[0] = pair_d<R>(y, GH::t6[0], GH::w6[0]);
+              L3.P[1] = pair_d<R>(y, GH::t6[1], GH::w6[1]);
+              L3.P[2] = pair_d<R>(y, GH::t6[2], GH::w6[2]);
+              fast_level<R, PROF>(2, L3, gc, r, end, sA, sB, sC);
+            } else if (PROF == XS_VOIGT && mode == 0) {
+              AdjLine<R> L1 = L;
+              fast_level<R, PROF>(0, L1, gc, r, end, sA, sB, sC);
+            } else if (PROF == XS_VOIGT && mode == 1) {
+              AdjLine<R> L2 = L;
+              L2.P[0] = L.P[1];
+              L2.P[1] = L.P[2];
+              fast_level<R, PROF>(1, L2, gc, r, end, sA, sB, sC);
+            } else {
+              fast_level<R, PROF>(0, L, gc, r, end, sA, sB, sC);
+            }
+          } else if (mode == -1) {
+            for (int rr = r; rr <= end; ++rr) {
+              if (rr >= L.rlo && rr <= L.rhi) {
+                const double gk = gc[L.kc + rr];
+                general_eval<R, PROF>(L, wide, rr, gk, sA, sB, sC);
+              }
+            }
+          }
+          r = end + 1;
+        }
+      }
       // scale to the unit-area profile and its derivatives
       double A, B, C;
       if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
@@ -217,22 +532,29 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
         C = -sC / (2.0 * sqrt(kPI) * sgm * sgm);          // -Im w' / (2 sqrt(pi) sg^2)
         B = -sB / (sgm * sgm * sqrt(2.0 * kPI));          // -Re G / (sg^2 sqrt(2 pi))
       }
-      const double T = cd.Tk;
-      double dlnS;
-      if (m.mode == XS_ABSORPTION)
-        dlnS = kC2 * El / (T * T) - (kC2 * nu / (T * T)) / expm1(kC2 * nu / T) - a.dQ[cd.slot] / a.Q[cd.slot];
-      else
-        dlnS = kC2 * Eu / (T * T) - a.dQ[cd.slot] / a.Q[cd.slot];
-      const double dsg_dT = (PROF == XS_GAUSSIAN) ? 0.0 : sgm / (2.0 * T);
-      dls += S * A;
-      dgr += S * C * gpow * cd.pfac;
-      dne += S * C * gam * cd.lnTr;
+      double vt = 0.0, vp = 0.0;
+      if (on) {
+        const double T = cd.Tk;
+        double dlnS;
+        if (m.mode == XS_ABSORPTION)
+          dlnS = kC2 * El / (T * T) - (kC2 * nu / (T * T)) / expm1(kC2 * nu / T) - a.dQ[cd.slot] / a.Q[cd.slot];
+        else
+          dlnS = kC2 * Eu / (T * T) - a.dQ[cd.slot] / a.Q[cd.slot];
+        const double dsg_dT = (PROF == XS_GAUSSIAN) ? 0.0 : sgm / (2.0 * T);
+        dls += S * A;
+        dgr += S * C * gpow * cd.pfac;
+        dne += S * C * gam * cd.lnTr;
+        vt = S * (A * dlnS + B * dsg_dT - C * nexp * gam / T);
+        vp = (cd.P > 0.0) ? S * C * gam / cd.P : 0.0;
+      }
+      vt = wave_sum(vt);
+      vp = wave_sum(vp);
       if (lane == 0) {
-        sdt[wave][c] += S * (A * dlnS + B * dsg_dT - C * nexp * gam / T);
-        sdp[wave][c] += (cd.P > 0.0) ? S * C * gam / cd.P : 0.0;
+        sdt[wave][c] += vt;
+        sdp[wave][c] += vp;
       }
     }
-    if (lane == 0) {
+    if (have) {
       a.dls[i] = dls;
       if (a.dgref) a.dgref[i] = dgr;
       if (a.dnexp) a.dnexp[i] = dne;
