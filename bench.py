@@ -31,24 +31,67 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per profile evaluation, counted on the far-wing formula
-# that covers > 95% of the window (one Gauss-Hermite node pair), FMA = 2:
-#   forward FP32:  x = fma(j,a,-b); u = x*x; n = u+p; a = u-p; qu = q*u;
-#                  d = fma(a,a,qu); r = rcp(d); t = n*r; acc = fma(c,t,acc)   -> 12 flops
-#   forward FP64 (2 pairs, 80 <= |z| < 3000): x = (nu_k - nu)*inv (2); u (1);
-#                  per pair p, n, a, d=fma, W*n*den, num=fma, den*d (10) -> 20;
-#                  division (1); acc fma (2)                                  -> 26 flops
-#   adjoint FP32:  x (2); u, zi, zi^2 (3); per pair A, A^2, d, rcp, id^2 (5);
-#                  Re w, R1, RG sums (14); scaling (3); 3 FP64 accumulations (6) -> 33 flops
-#   adjoint FP64 (2 pairs): x (2); u, zi, zi^2 (3); 2 x (5 + 14) -> 38; scaling (3);
-#                  3 FP64 accumulations (6)                                  -> 52 flops
-FLOPS_PER_EVAL = {("fwd", "f32"): 12, ("fwd", "f64"): 26, ("adj", "f32"): 33, ("adj", "f64"): 52}
+# Algorithmic work per profile evaluation: the flops of the formula the method
+# needs at that evaluation (FMA = 2; add, mul, reciprocal, division, exp2 = 1),
+# by the Voigt region rho = x^2 + y^2 of the evaluation (the same regions the
+# kernels use).  (rho threshold, flops) from the outermost region inward:
+#   forward FP32: 1 node pair: x = fma(r,a,-b) 2, u 1, u+q 1, d = fma 2, rcp 1,
+#                 numerator fma 2, accumulate fma 2 = 11; 2 pairs 19;
+#                 Taylor core (K = 16, complex Horner in FP64) 140.
+#   forward FP64: 1 pair 11; 2 pairs (one division) 19; 3/4/6 pairs 30/39/57;
+#                 core (K = 22) 188.
+#   adjoint FP32: 1 pair: x 2, u 1, pair terms 18 (u+q, d, rcp, e, s, t),
+#                 three accumulations 6 = 27; 2 pairs 54; core (w and w') 280.
+#   adjoint FP64: 1/2/3 pairs 27/54/78; 4/6 pairs (general form) 113/161;
+#                 core (K = 22) 372.
+FLOP_REGIONS = {
+    ("fwd", "f32"): [(900.0, 11), (64.0, 19), (0.0, 140)],
+    ("fwd", "f64"): [(9.0e6, 11), (6400.0, 19), (400.0, 30), (144.0, 39), (64.0, 57), (0.0, 188)],
+    ("adj", "f32"): [(900.0, 27), (64.0, 54), (0.0, 280)],
+    ("adj", "f64"): [(9.0e6, 27), (6400.0, 54), (400.0, 78), (144.0, 113), (64.0, 161), (0.0, 372)],
+}
 # MI355X vector peaks, no packed-FP32 (packed FP32 is disabled in this build):
 # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP32
 # and FP64 alike.  The published 157.3 TFLOP/s FP32 figure needs packed math.
 PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
 KERNEL_SOURCES = ["paper_2609_17273_amd/csrc/k_profile.hip", "paper_2609_17273_amd/csrc/k_adjoint.hip",
                   "paper_2609_17273_amd/csrc/k_common.h"]
+
+
+def region_fractions(wl, lines, cond):
+    """Fraction of the window evaluations in each Voigt region, from the closed
+    form of |x| < sqrt(rho - y^2) per line (grid clipping ignored)."""
+    import numpy as np
+    c, kb, amu = 2.99792458e10, 1.380649e-16, 1.66053906660e-24
+    E = wl.states.energy
+    nu = E[lines.upper] - E[lines.lower]
+    pos = nu > 0
+    nu = nu[pos]
+    alpha = nu / c * np.sqrt(2.0 * kb * cond.T * np.log(2.0) / (wl.mass_amu * amu))
+    s = alpha / np.sqrt(np.log(2.0))                 # sigma_G sqrt(2)
+    gref = lines.gamma_ref.astype(np.float64)[pos]
+    nexp = lines.n_exp.astype(np.float64)[pos]
+    y = gref * (296.0 / cond.T) ** nexp * cond.P / s
+    total = 2.0 * cond.cutoff * len(nu)
+
+    def inside(rho):
+        X = np.sqrt(np.maximum(rho - y * y, 0.0))
+        return float(np.sum(2.0 * np.minimum(X * s, cond.cutoff))) / total
+
+    out = {}
+    for kind in FLOP_REGIONS:
+        regs = FLOP_REGIONS[kind]
+        fr = []
+        for j, (rho, _) in enumerate(regs):
+            outer = inside(regs[j - 1][0]) if j > 0 else 1.0
+            inner = inside(rho) if rho > 0.0 else 0.0
+            fr.append(max(outer - inner, 0.0))
+        out[kind] = fr
+    return out
+
+
+def flops_per_eval(fracs, kind):
+    return sum(f * fl for f, (_, fl) in zip(fracs[kind], FLOP_REGIONS[kind]))
 
 
 def log(*a):
@@ -147,8 +190,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how it would shard); run with --gpus 1.", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(sharding is described in the design notes); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -223,15 +266,18 @@ def main():
         extras["gather_over_scatter_speedup_f32"] = round(extras["scatter_f32"]["profile_pass_ms"] / per32["forward"], 2)
 
     # roofline of the dominant kernel (events around each launch, same stream)
+    fracs = region_fractions(wl, lines, cond)
     rl = {}
     for kind, ms in (("fwd", per32["forward"]), ("adj", per32["adjoint"])):
-        flops = FLOPS_PER_EVAL[(kind, "f32")] * pairs
+        fpe = flops_per_eval(fracs, (kind, "f32"))
+        flops = fpe * pairs
         ach = flops / (ms / 1e3) / 1e12
         key = "gather_c2_f32" if kind == "fwd" else "adjoint_c2_f32"
         rl[kind] = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
                     "frac": round(ach / PEAK_TFLOPS["f32"], 4), "traffic": traffic_from_profiles(key),
                     "kernel": "k_gather<float,Voigt>" if kind == "fwd" else "k_adjoint<float,Voigt>",
-                    "avg_launch_ms": round(ms, 3), "flops_per_eval": FLOPS_PER_EVAL[(kind, "f32")],
+                    "avg_launch_ms": round(ms, 3), "flops_per_eval": round(fpe, 3),
+                    "region_fractions": [round(f, 5) for f in fracs[(kind, "f32")]],
                     "evals_per_launch": pairs}
     dom = "adj" if per32["adjoint"] >= per32["forward"] else "fwd"
     other = "fwd" if dom == "adj" else "adj"

@@ -127,20 +127,23 @@ typedef struct {
   double n_exp_scalar;
 } xs_lines;
 
-/* Kernel configuration.  A gather work item is one tile of
- * tile_bins = tile_waves x 64 lanes x (2, 4 or 8) grid points: each wave owns
- * 64 x per-lane points, each lane every 64th of them.  tile_waves: 1, 2 or 4;
- * tile_bins: 128 .. 2048 as above; bucket_bins: grid points per line bucket
- * (power of two, 64..4096); persistent: 1 = one persistent launch pulling
- * (condition, tile) items from a device queue, 0 = one workgroup per item;
- * waves_per_cu: size of the persistent grid in waves per compute unit
- * (4..64). */
+/* Kernel configuration.  The gather cuts the grid into tiles of tile_bins
+ * points (256, 512 or 1024; one wave of 64 lanes, each lane every 64th point).
+ * A work item is one (tile, condition) and a slice of at most chunk_lines of
+ * the tile's candidate lines; a tile split over several items is summed from
+ * their partial rows in item order, so results do not depend on scheduling.
+ * chunk_lines: 0 = automatic (about 64 items per compute unit when the
+ * tiles alone are too few), else a multiple of 64 (the automatic size wins
+ * when it is larger).  bucket_bins: grid points per line bucket (power of two,
+ * 64..4096); persistent: 1 = one persistent launch pulling items from a
+ * device queue, 0 = one workgroup per item; waves_per_cu: size of the
+ * persistent grid in waves per compute unit (4..64). */
 typedef struct {
   int32_t tile_bins;
   int32_t bucket_bins;
   int32_t persistent;
   int32_t waves_per_cu;
-  int32_t tile_waves;
+  int32_t chunk_lines;
 } xs_config;
 
 /* Counters of the last xs_cross_section / adjoint call (read after sync). */

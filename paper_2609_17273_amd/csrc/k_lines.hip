@@ -466,6 +466,8 @@ __global__ void k_reset_queue(int32_t* counter) {
   if (threadIdx.x < 64) counter[threadIdx.x] = 0;
 }
 
+void launch_scan_i32(int32_t* a, int64_t n, int32_t* sums, hipStream_t s) { scan_excl(a, n, sums, s); }
+
 void launch_reset_queue(const Work& w, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, w.counter);
 }

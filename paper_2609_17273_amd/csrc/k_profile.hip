@@ -101,37 +101,37 @@ __device__ __forceinline__ KRange x_range(double X, double a, double b, int64_t 
   return r;
 }
 
-// Row classes of a staged line, 2 bits per wave of the tile: 0 = the row
-// gets nothing (outside the window, or a Gaussian row where 2^{-x^2}
-// vanishes); 1 = the whole row is inside the window and takes the first
-// uniform formula (FP32: one node pair / Gaussian / Lorentzian; FP64: one
-// node pair / Gaussian / Lorentzian); 3 = inside the window, second uniform
-// formula (FP32: two node pairs; FP64: two node pairs); 2 = general per-chunk
-// path (window edges, the core, lines evaluated in FP64).
+// Class of a staged line for the tile: 0 = nothing to add (outside the
+// window, or a Gaussian whose 2^{-x^2} vanishes on every bin of the tile);
+// 1 = the whole tile is inside the window and takes the first uniform formula
+// (Voigt: one node pair; Gaussian, Lorentzian: the profile itself); 3 = inside
+// the window, second uniform formula (Voigt: two node pairs); 2 = general
+// per-chunk path (window edges, the core, lines evaluated in FP64).
 constexpr int kRowSkip = 0, kRowF1 = 1, kRowGeneral = 2, kRowF2 = 3;
 
-// FP32 form.  The fast-path fields come first (two 16-byte LDS reads).
+// FP32 form.  The first-formula fields come first (two 16-byte LDS reads);
+// the second formula reads a, nb, jfb and B1, B2.
 //   rB: bins that are not far-wing (one node pair) -- for the Gaussian, the
 //       bins where 2^{-x^2} is not zero in FP32; rC: bins near the core that
 //       need the per-lane choice (Taylor core or two node pairs).
-struct RecF {
-  int cls;
-  float a, nb, jfb;  // x = (jfb + offset of the bin in the tile) a + nb; jfb = tlo - k_c
-  Pair<float> A;
+struct __attribute__((aligned(16))) RecF {
+  float a, nb, jfb, c0;  // x = (jfb + offset of the bin in the tile) a + nb; jfb = tlo - k_c
+  Pair<float> A;         // one node pair
+  Pair<float> B1, B2;    // two node pairs
   int klo, khi, flag, kc;
   KRange rB, rC;
-  float c0, y, pad0, pad1;
-  Pair<float> B1, B2;
+  float y;
+  int pad0, pad1, pad2;
 };
 // FP64 form.  r[0..4]: bins with |z|^2 below 9e6, 6400, 400, 144, 64 (the
 // thresholds of the 1, 2, 3, 4 and 6 node-pair bands); for the Gaussian,
 // r[0] holds the bins where 2^{-x^2} is not zero in FP64.
-struct RecD {
-  int cls, klo, khi, flag;
-  KRange r[5];
-  int kc, pad2;
-  double nu, inv, y, c0;
+struct __attribute__((aligned(16))) RecD {
+  double nu, inv, c0, y;
   Pair<double> A, B1, B2;
+  int klo, khi, flag, kc;
+  KRange r[5];
+  int pad0, pad1;
 };
 
 struct GatherArgs {
@@ -144,34 +144,53 @@ struct GatherArgs {
   const float* rnexp;
   const void* rS;
   int64_t max_lines;
-  int32_t* counter;
+  int32_t* counter;         // [0]: work queue; [2..3]: candidate total; [4..5]: lines per item
+  const int32_t* ib;        // [n_ct + 1] first work item of each (tile, condition); ib[n_ct] = items
+  const int32_t* pb;        // [n_ct + 1] first partial row of each split (tile, condition)
+  double* part;             // partial rows of split tiles
   double* sigma;
   int32_t accumulate;
   int32_t n_tiles;
-  int64_t n_items;
+  int32_t n_ct;             // n_tiles * n_cond; ct = t * n_cond + c
   int32_t tile_bins;
   int32_t persistent;
+  int64_t chunk_cfg;        // requested lines per work item (0: automatic)
+  int64_t item_target;      // work items aimed at when tiles are split
 };
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ bool meets(int lo, int hi, const KRange& r) { return hi >= r.lo && lo <= r.hi; }
 
-// Staging: does line p touch bins [tlo, thi] under condition cd?  Fills rec,
-// including the class of each wave's row (rows of rowb bins from tlo).
-template <typename Rec, int PROF, int WAVES>
-__device__ bool stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int64_t tlo,
-                           int64_t thi, int rowb, Rec& r) {
+// Candidate lines of tile t under condition cd: the buckets within the
+// cut-off reach of the tile.
+__device__ __forceinline__ void tile_candidates(const GatherArgs& g, const CondDev& cd, int t, int64_t& tlo,
+                                                int64_t& thi, int64_t& plo, int64_t& phi) {
+  const ModelDev& m = g.m;
+  tlo = (int64_t)t * g.tile_bins;
+  thi = min(tlo + g.tile_bins, m.n_bins) - 1;
+  const int64_t lo = tlo - cd.wbins;
+  const int64_t blo = max<int64_t>(0, lo >= 0 ? lo / m.bucket_bins : -1);
+  const int64_t bhi = min<int64_t>(m.n_buckets - 1, (thi + cd.wbins) / m.bucket_bins);
+  plo = g.off[blo];
+  phi = g.off[bhi + 1];
+}
+
+// Staging: does line p touch bins [tlo, thi] under condition cd?  Fills the
+// record and returns its class for the tile row [tlo, tlo + rowb - 1].
+template <typename Rec, int PROF>
+__device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int64_t tlo,
+                          int64_t thi, int rowb, Rec& r) {
   const ModelDev& m = g.m;
   const double nu = g.rnu[p];
   int64_t klo, khi;
-  if (!line_window(nu, cd.cut, m.nu0, m.dnu, m.n_bins, klo, khi)) return false;
-  if (khi < tlo || klo > thi) return false;
+  if (!line_window(nu, cd.cut, m.nu0, m.dnu, m.n_bins, klo, khi)) return kRowSkip;
+  if (khi < tlo || klo > thi) return kRowSkip;
   double S;
   if constexpr (sizeof(Rec) == sizeof(RecF))
     S = (double)((const float*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
   else
     S = ((const double*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
-  if (S == 0.0) return false;
+  if (S == 0.0) return kRowSkip;
   const int64_t kc = home_bin(nu, m.nu0, m.dnu);
   const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
   const LineParams lp = line_params<PROF>(m, cd, nu, (double)g.rgref[p], (double)g.rnexp[p], S);
@@ -191,35 +210,24 @@ __device__ bool stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, in
   }
   auto xr = [&](double rho) { return x_range(sqrt(fmax(rho - y2, 0.0)), a, b, kc, klo, khi); };
   const KRange none = x_range(0.0, a, b, kc, klo, khi);
-  // class of the row [lo, hi] given the ranges of the first and second uniform formula
-  auto row_class = [&](int lo, int hi, KRange zero, KRange not1, KRange not2, bool can2) {
-    if (hi < klo || lo > khi) return kRowSkip;
-    if (!meets(lo, hi, zero)) return kRowSkip;
-    const bool inside = klo <= lo && khi >= hi;
-    if (!inside || r.flag) return kRowGeneral;
-    if (!meets(lo, hi, not1)) return kRowF1;
-    if (can2 && !meets(lo, hi, not2)) return kRowF2;
-    return kRowGeneral;
-  };
-  KRange zero, not1, not2;
-  bool can2;
+  const int lo = (int)tlo, hi = lo + rowb - 1;
+  const bool inside = klo <= lo && khi >= hi;
+  // Gaussian: the nonzero range nz; first formula when the row lies inside it.
+  // Voigt: first formula when the row avoids n1, second when it avoids n2.
+  KRange nz = KRange{(int)klo, (int)khi}, n1 = none, n2 = none;
+  bool can2 = false, gauss = false;
   if constexpr (sizeof(Rec) == sizeof(RecF)) {
     r.a = (float)a;
     r.nb = (float)(-b);
     r.jfb = (float)(tlo - kc);  // integer, exact in FP32 within a window
     r.c0 = (float)lp.c0;
     r.y = (float)lp.y;
+    r.rB = none;
+    r.rC = none;
     if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
       r.rB = x_range(sqrt(160.0), a, b, kc, klo, khi);
-      r.rC = none;
-      zero = r.rB;
-      // a row inside the nonzero range takes the Gaussian directly
-      not1 = KRange{-0x7fffffff, 0x7fffffff};
-      if (r.rB.lo <= r.rB.hi) {
-        not1 = KRange{(int)klo, r.rB.lo - 1};   // bins left of the nonzero range
-      }
-      not2 = KRange{r.rB.hi + 1, (int)khi};     // bins right of it
-      can2 = false;
+      nz = r.rB;
+      gauss = true;
     } else if (PROF == XS_VOIGT) {
       r.rB = xr(900.0 * 1.001);
       r.rC = xr(64.0 * 1.001);
@@ -227,17 +235,9 @@ __device__ bool stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, in
       // (nu of a few 1e-3 cm^-1 or less) are evaluated in FP64.
       const double xmax = fmax(fabs((double)(klo - kc) * a - b), fabs((double)(khi - kc) * a - b));
       if (xmax > 1.0e9 || lp.y > 1.0e9) r.flag = 1;
-      zero = KRange{(int)klo, (int)khi};
-      not1 = r.rB;
-      not2 = r.rC;
+      n1 = r.rB;
+      n2 = r.rC;
       can2 = true;
-    } else {
-      r.rB = none;
-      r.rC = none;
-      zero = KRange{(int)klo, (int)khi};
-      not1 = none;
-      not2 = none;
-      can2 = false;
     }
   } else {
     r.nu = nu;
@@ -246,45 +246,25 @@ __device__ bool stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, in
     r.c0 = lp.c0;
     if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
       r.r[0] = x_range(sqrt(1100.0), a, b, kc, klo, khi);
-      zero = r.r[0];
-      not1 = KRange{-0x7fffffff, 0x7fffffff};
-      if (r.r[0].lo <= r.r[0].hi) not1 = KRange{(int)klo, r.r[0].lo - 1};
-      not2 = KRange{r.r[0].hi + 1, (int)khi};
-      can2 = false;
+      nz = r.r[0];
+      gauss = true;
     } else if (PROF == XS_VOIGT) {
       r.r[0] = xr(9.0e6 * 1.001);
       r.r[1] = xr(6400.0 * 1.001);
       r.r[2] = xr(400.0 * 1.001);
       r.r[3] = xr(144.0 * 1.001);
       r.r[4] = xr(64.0 * 1.001);
-      zero = KRange{(int)klo, (int)khi};
-      not1 = r.r[0];
-      not2 = r.r[1];
+      n1 = r.r[0];
+      n2 = r.r[1];
       can2 = true;
-    } else {
-      zero = KRange{(int)klo, (int)khi};
-      not1 = none;
-      not2 = none;
-      can2 = false;
     }
   }
-  // For the Gaussian the "first formula" test is: row inside the nonzero range.
-  int cls = 0;
-#pragma unroll
-  for (int w = 0; w < WAVES; ++w) {
-    const int lo = (int)tlo + w * rowb, hi = lo + rowb - 1;
-    int c;
-    if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
-      if (hi < klo || lo > khi || !meets(lo, hi, zero)) c = kRowSkip;
-      else if (klo <= lo && khi >= hi && !meets(lo, hi, not1) && !meets(lo, hi, not2)) c = kRowF1;
-      else c = kRowGeneral;
-    } else {
-      c = row_class(lo, hi, zero, not1, not2, can2);
-    }
-    cls |= c << (2 * w);
-  }
-  r.cls = cls;
-  return cls != 0;
+  if (!meets(lo, hi, nz)) return kRowSkip;
+  if (!inside || r.flag) return kRowGeneral;
+  if (gauss) return (nz.lo <= lo && nz.hi >= hi) ? kRowF1 : kRowGeneral;
+  if (!meets(lo, hi, n1)) return kRowF1;
+  if (can2 && !meets(lo, hi, n2)) return kRowF2;
+  return kRowGeneral;
 }
 
 // ---- far-region evaluators ------------------------------------------------
@@ -334,45 +314,54 @@ __device__ __noinline__ float voigt_near_f32(float x, float y, float c0, Pair<fl
   return c0 * (float)wr;
 }
 
-// Tile layout: wave w owns the row [row_lo, row_lo + 64 M); lane l owns the
-// bins row_lo + 64 j + l, j = 0..M-1, so each "chunk" j is 64 consecutive
-// bins.  A line's narrow core region falls into one or two chunks, and every
-// per-chunk decision (window, band, zero skip) is a scalar compare of the
-// chunk's bin range with the line's precomputed ranges.
-template <typename Real, int PROF, int M, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_gather(GatherArgs g) {
+// Work item = (tile, condition, slice of the tile's candidate lines); one
+// wave per item.  Lane l owns the bins tlo + 64 j + l, j = 0..M-1, so each
+// "chunk" j is 64 consecutive bins and every per-chunk decision (window,
+// band, zero skip) is a scalar compare of the chunk's range with the line's
+// precomputed ranges.  Each batch of up to 64 candidates is staged one line
+// per lane, and the survivors are compacted into LDS grouped by class (a
+// ballot and mbcnt per class), so the first- and second-formula lines run in
+// tight loops with no per-line branch.  A tile split over several items
+// writes FP64 partial rows that k_reduce adds in item order.
+template <typename Real, int PROF, int M>
+__global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
   using Rec = typename std::conditional<sizeof(Real) == 4, RecF, RecD>::type;
   constexpr bool F32 = sizeof(Real) == 4;
-  constexpr int NT = 64 * WAVES;
-  constexpr int ROWB = 64 * M;  // bins per wave row
-  __shared__ Rec srec[NT];
-  __shared__ int s_wcnt[WAVES];
-  __shared__ long long s_item;
+  constexpr int ROWB = 64 * M;
+  __shared__ Rec srec[64];
 
-  // wave index made explicitly uniform so row and chunk bounds live in SGPRs
-  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = threadIdx.x;
   const ModelDev& m = g.m;
-  long long item = blockIdx.x;
+  const int n_items = uni(g.ib[g.n_ct]);
+  const int64_t chunk = *(const int64_t*)(g.counter + 4);
+  const float lane_off = (float)lane;
+  int item = blockIdx.x;
   for (;;) {
     if (g.persistent) {
-      if (tid == 0) s_item = atomicAdd((unsigned long long*)g.counter, 1ull);
-      __syncthreads();
-      item = s_item;
-      __syncthreads();
+      int v = 0;
+      if (lane == 0) v = atomicAdd(g.counter, 1);
+      item = __shfl(v, 0, 64);
     }
-    if (item >= g.n_items) return;
-    const int c = (int)(item % m.n_cond);
-    const int t = (int)(item / m.n_cond);
+    item = uni(item);
+    if (item >= n_items) return;
+    // (tile, condition) of the item: the last ct with ib[ct] <= item
+    int lo = 0, hi = g.n_ct - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (g.ib[mid] <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const int ct = uni(lo);
+    const int jpart = item - g.ib[ct];
+    const int nch = g.ib[ct + 1] - g.ib[ct];
+    const int c = ct % m.n_cond, t = ct / m.n_cond;
     const CondDev cd = g.cond[c];
-    const int64_t tlo = (int64_t)t * g.tile_bins;
-    const int64_t thi = min(tlo + g.tile_bins, m.n_bins) - 1;
-    const int64_t blo = max<int64_t>(0, (tlo - cd.wbins) / m.bucket_bins - ((tlo - cd.wbins) < 0 ? 1 : 0));
-    const int64_t bhi = min<int64_t>(m.n_buckets - 1, (thi + cd.wbins) / m.bucket_bins);
-    const int64_t plo = g.off[blo], phi = g.off[bhi + 1];
-    const int row_lo = (int)tlo + wave * ROWB;
-    const int row_hi = row_lo + ROWB - 1;
-    const int my0 = row_lo + lane;          // bin of chunk 0 of this lane
-    const float lane_off = (float)(wave * ROWB + lane);  // offset of that bin in the tile
+    int64_t tlo, thi, plo, phi;
+    tile_candidates(g, cd, t, tlo, thi, plo, phi);
+    const int64_t q0 = plo + (int64_t)jpart * chunk;
+    const int64_t q1 = min(phi, q0 + chunk);
+    const int row_lo = (int)tlo;
+    const int my0 = row_lo + lane;  // bin of chunk 0 of this lane
 
     double acc64[M];
     float acc32[M];
@@ -384,72 +373,75 @@ __global__ __launch_bounds__(64 * WAVES) void k_gather(GatherArgs g) {
       if (!F32) nuk[j] = nu_of_bin(m.nu0, m.dnu, my0 + 64 * j);
     }
 
-    for (int64_t p0 = plo; p0 < phi; p0 += NT) {
-      // ---- stage: exact window test, compaction into LDS ----
+    for (int64_t p0 = q0; p0 < q1; p0 += 64) {
+      // ---- stage: exact window test and class, compaction into LDS by class ----
       Rec r;
-      bool keep = false;
-      const int64_t p = p0 + tid;
-      if (p < phi) keep = stage_line<Rec, PROF, WAVES>(g, cd, p, tlo, thi, ROWB, r);
-      const unsigned long long bal = __ballot(keep);
-      const int before = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
-                                                   __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-      if (lane == 0) s_wcnt[wave] = __popcll(bal);
+      int cls = kRowSkip;
+      const int64_t p = p0 + lane;
+      if (p < q1) cls = stage_line<Rec, PROF>(g, cd, p, tlo, thi, ROWB, r);
+      const unsigned long long b1 = __ballot(cls == kRowF1);
+      const unsigned long long b2 = __ballot(cls == kRowF2);
+      const unsigned long long bg = __ballot(cls == kRowGeneral);
+      const int n1 = __popcll(b1), n2 = __popcll(b2), ng = __popcll(bg);
+      if (n1 + n2 + ng == 0) continue;
+      const unsigned long long mine = cls == kRowF1 ? b1 : (cls == kRowF2 ? b2 : bg);
+      const int base = cls == kRowF1 ? 0 : (cls == kRowF2 ? n1 : n1 + n2);
+      const int slot = base + __builtin_amdgcn_mbcnt_hi((unsigned)(mine >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((unsigned)mine, 0u));
       __syncthreads();
-      int base = 0, total = 0;
-#pragma unroll
-      for (int w2 = 0; w2 < WAVES; ++w2) {
-        int cnum = s_wcnt[w2];
-        base += (w2 < wave) ? cnum : 0;
-        total += cnum;
-      }
-      if (keep) srec[base + before] = r;
+      if (cls != kRowSkip) srec[slot] = r;
       __syncthreads();
 
-      // ---- evaluate every staged line over this wave's row ----
-      for (int l = 0; l < total; ++l) {
-        const Rec& rr = srec[l];
-        const int cls = (uni(rr.cls) >> (2 * wave)) & 3;
-        if (cls == kRowSkip) continue;
-        if constexpr (F32) {
-          // x = (k - k_c) a - b, with k - k_c = (tlo - k_c) + (offset in tile): integers,
-          // exact in FP32 within a window
-          const float a = rr.a, nb = rr.nb;
-          const float jf0 = rr.jfb + lane_off;
-          if (cls != kRowGeneral) {
-            if (PROF == XS_LORENTZ) {
-              const float c0 = rr.c0;
+      if constexpr (F32) {
+        // x = (k - k_c) a - b, with k - k_c = (tlo - k_c) + (offset in tile):
+        // integers, exact in FP32 within a window
+        // ---- first formula ----
+#pragma unroll 2
+        for (int l = 0; l < n1; ++l) {
+          const RecF& rr = srec[l];
+          const float a = rr.a, nb = rr.nb, jf0 = rr.jfb + lane_off;
+          if (PROF == XS_LORENTZ) {
+            const float c0 = rr.c0;
 #pragma unroll
-              for (int j = 0; j < M; ++j) {
-                const float x = fmaf(jf0 + (float)(64 * j), a, nb);
-                acc32[j] = fmaf(c0, rcp32(fmaf(x, x, 1.0f)), acc32[j]);
-              }
-            } else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
-              const float c0 = rr.c0;
-#pragma unroll
-              for (int j = 0; j < M; ++j) {
-                const float x = fmaf(jf0 + (float)(64 * j), a, nb);
-                acc32[j] = fmaf(c0, __builtin_amdgcn_exp2f(-(x * x)), acc32[j]);
-              }
-            } else if (cls == kRowF1) {
-              const float cw = rr.A.cw, cwp = rr.A.cwp, q = rr.A.q, p2 = rr.A.p2;
-#pragma unroll
-              for (int j = 0; j < M; ++j) {
-                const float x = fmaf(jf0 + (float)(64 * j), a, nb);
-                const float u = x * x;
-                acc32[j] = fmaf(fmaf(cw, u, cwp), rcp32(fmaf(u, u + q, p2)), acc32[j]);
-              }
-            } else {
-              const Pair<float> B1 = rr.B1, B2 = rr.B2;
-#pragma unroll
-              for (int j = 0; j < M; ++j) {
-                const float x = fmaf(jf0 + (float)(64 * j), a, nb);
-                const float u = x * x;
-                acc32[j] += pair_term<float>(B1, u) + pair_term<float>(B2, u);
-              }
+            for (int j = 0; j < M; ++j) {
+              const float x = fmaf(jf0 + (float)(64 * j), a, nb);
+              acc32[j] = fmaf(c0, rcp32(fmaf(x, x, 1.0f)), acc32[j]);
             }
-            continue;
+          } else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+            const float c0 = rr.c0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+              const float x = fmaf(jf0 + (float)(64 * j), a, nb);
+              acc32[j] = fmaf(c0, __builtin_amdgcn_exp2f(-(x * x)), acc32[j]);
+            }
+          } else {
+            const float cw = rr.A.cw, cwp = rr.A.cwp, q = rr.A.q, p2 = rr.A.p2;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+              const float x = fmaf(jf0 + (float)(64 * j), a, nb);
+              const float u = x * x;
+              acc32[j] = fmaf(fmaf(cw, u, cwp), rcp32(fmaf(u, u + q, p2)), acc32[j]);
+            }
           }
-          // general path: per-chunk decisions
+        }
+        // ---- second formula (Voigt: two node pairs) ----
+        if (PROF == XS_VOIGT) {
+          for (int l = n1; l < n1 + n2; ++l) {
+            const RecF& rr = srec[l];
+            const float a = rr.a, nb = rr.nb, jf0 = rr.jfb + lane_off;
+            const Pair<float> B1 = rr.B1, B2 = rr.B2;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+              const float x = fmaf(jf0 + (float)(64 * j), a, nb);
+              const float u = x * x;
+              acc32[j] += pair_term<float>(B1, u) + pair_term<float>(B2, u);
+            }
+          }
+        }
+        // ---- general path: per-chunk decisions ----
+        for (int l = n1 + n2; l < n1 + n2 + ng; ++l) {
+          const RecF& rr = srec[l];
+          const float a = rr.a, nb = rr.nb, jf0 = rr.jfb + lane_off;
           const int klo = uni(rr.klo), khi = uni(rr.khi);
           const KRange rB = {uni(rr.rB.lo), uni(rr.rB.hi)};
           const KRange rC = {uni(rr.rC.lo), uni(rr.rC.hi)};
@@ -482,8 +474,16 @@ __global__ __launch_bounds__(64 * WAVES) void k_gather(GatherArgs g) {
             }
             acc32[j] += (full || (k >= klo && k <= khi)) ? v : 0.0f;
           }
-        } else {
-          // FP64 form: x from the exact difference nu_k - nu_i
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          acc64[j] += (double)acc32[j];
+          acc32[j] = 0.0f;
+        }
+      } else {
+        // FP64 form: x from the exact difference nu_k - nu_i
+        for (int l = 0; l < n1 + n2; ++l) {
+          const RecD& rr = srec[l];
           const double nu = rr.nu, inv = rr.inv;
           double xs[M];
 #pragma unroll
@@ -491,26 +491,27 @@ __global__ __launch_bounds__(64 * WAVES) void k_gather(GatherArgs g) {
 #pragma clang fp contract(off)
             xs[j] = (nuk[j] - nu) * inv;
           }
-          if (cls != kRowGeneral) {
-            if (PROF == XS_LORENTZ) {
-              const double c0 = rr.c0;
+          if (PROF == XS_LORENTZ) {
+            const double c0 = rr.c0;
 #pragma unroll
-              for (int j = 0; j < M; ++j) acc64[j] = fma(c0, rcp64(fma(xs[j], xs[j], 1.0)), acc64[j]);
-            } else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
-              const double c0 = rr.c0;
+            for (int j = 0; j < M; ++j) acc64[j] = fma(c0, rcp64(fma(xs[j], xs[j], 1.0)), acc64[j]);
+          } else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+            const double c0 = rr.c0;
 #pragma unroll
-              for (int j = 0; j < M; ++j) acc64[j] = fma(c0, exp2(-(xs[j] * xs[j])), acc64[j]);
-            } else if (cls == kRowF1) {
-              const Pair<double> A = rr.A;
+            for (int j = 0; j < M; ++j) acc64[j] = fma(c0, exp2(-(xs[j] * xs[j])), acc64[j]);
+          } else if (l < n1) {
+            const Pair<double> A = rr.A;
 #pragma unroll
-              for (int j = 0; j < M; ++j) acc64[j] += pair_term<double>(A, xs[j] * xs[j]);
-            } else {
-              const Pair<double> B1 = rr.B1, B2 = rr.B2;
+            for (int j = 0; j < M; ++j) acc64[j] += pair_term<double>(A, xs[j] * xs[j]);
+          } else {
+            const Pair<double> B1 = rr.B1, B2 = rr.B2;
 #pragma unroll
-              for (int j = 0; j < M; ++j) acc64[j] += pair2_term(B1, B2, xs[j] * xs[j]);
-            }
-            continue;
+            for (int j = 0; j < M; ++j) acc64[j] += pair2_term(B1, B2, xs[j] * xs[j]);
           }
+        }
+        for (int l = n1 + n2; l < n1 + n2 + ng; ++l) {
+          const RecD& rr = srec[l];
+          const double nu = rr.nu, inv = rr.inv;
           const int klo = uni(rr.klo), khi = uni(rr.khi);
 #pragma unroll
           for (int j = 0; j < M; ++j) {
@@ -518,7 +519,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_gather(GatherArgs g) {
             if (ch < klo || cl > khi) continue;
             const bool full = cl >= klo && ch <= khi;
             const int k = my0 + 64 * j;
-            const double x = xs[j];
+            double x;
+            {
+#pragma clang fp contract(off)
+              x = (nuk[j] - nu) * inv;
+            }
             double v;
             if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
               if (!meets(cl, ch, KRange{uni(rr.r[0].lo), uni(rr.r[0].hi)})) continue;
@@ -547,40 +552,94 @@ __global__ __launch_bounds__(64 * WAVES) void k_gather(GatherArgs g) {
           }
         }
       }
-      if constexpr (F32) {
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-          acc64[j] += (double)acc32[j];
-          acc32[j] = 0.0f;
-        }
-      }
-      __syncthreads();
     }
 
-    // ---- write the tile ----
-    const double scale = F32 ? exp(g.sb[cd.slot]) : 1.0;
-    double* out = g.sigma + (int64_t)c * m.n_bins;
+    // ---- write the tile, or this item's partial row ----
+    if (nch == 1) {
+      const double scale = F32 ? exp(g.sb[cd.slot]) : 1.0;
+      double* out = g.sigma + (int64_t)c * m.n_bins;
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      const int64_t k = my0 + 64 * j;
-      if (k <= thi) {
-        const double v = scale * acc64[j];
-        out[k] = g.accumulate ? out[k] + v : v;
+      for (int j = 0; j < M; ++j) {
+        const int64_t k = my0 + 64 * j;
+        if (k <= thi) {
+          const double v = scale * acc64[j];
+          out[k] = g.accumulate ? out[k] + v : v;
+        }
       }
+    } else {
+      double* row = g.part + (int64_t)(g.pb[ct] + jpart) * ROWB;
+#pragma unroll
+      for (int j = 0; j < M; ++j) row[lane + 64 * j] = acc64[j];
     }
     if (!g.persistent) return;
   }
 }
 
-template <typename Real, int PROF>
-static void gather_dispatch(const GatherArgs& a, const Tiling& t, int blocks, hipStream_t s) {
-  const int w = t.waves, M = t.per_lane;
-#define XS_G(MM, WW)                                                                       \
-  if (M == MM && w == WW) {                                                                \
-    hipLaunchKernelGGL((k_gather<Real, PROF, MM, WW>), dim3(blocks), dim3(64 * WW), 0, s, a); \
-    return;                                                                                \
+// Candidate count of every (tile, condition) and their total.
+__global__ __launch_bounds__(256) void k_items_count(GatherArgs g, int32_t* cnt) {
+  unsigned long long local = 0;
+  for (int64_t ct = (int64_t)blockIdx.x * 256 + threadIdx.x; ct < g.n_ct; ct += (int64_t)gridDim.x * 256) {
+    const int c = (int)(ct % g.m.n_cond), t = (int)(ct / g.m.n_cond);
+    int64_t tlo, thi, plo, phi;
+    tile_candidates(g, g.cond[c], t, tlo, thi, plo, phi);
+    cnt[ct] = (int32_t)(phi - plo);
+    local += (unsigned long long)(phi - plo);
   }
-  XS_G(4, 1) XS_G(8, 1) XS_G(4, 2) XS_G(8, 2) XS_G(2, 4) XS_G(4, 4) XS_G(8, 4)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) local += __shfl_xor(local, o, 64);
+  if ((threadIdx.x & 63) == 0 && local) atomicAdd((unsigned long long*)(g.counter + 2), local);
+}
+
+// Lines per work item (at least the requested number, and large enough that
+// the items stay near the target count) and the items of every (tile,
+// condition); split tiles also get partial rows.
+__global__ __launch_bounds__(256) void k_items_split(GatherArgs g, const int32_t* cnt, int32_t* ib,
+                                                     int32_t* pb) {
+  const unsigned long long total = *(const unsigned long long*)(g.counter + 2);
+  int64_t chunk = (int64_t)((total + g.item_target - 1) / g.item_target);
+  chunk = max(chunk, g.chunk_cfg);
+  chunk = max<int64_t>(64, (chunk + 63) / 64 * 64);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *(int64_t*)(g.counter + 4) = chunk;
+    ib[g.n_ct] = 0;
+    pb[g.n_ct] = 0;
+  }
+  for (int64_t ct = (int64_t)blockIdx.x * 256 + threadIdx.x; ct < g.n_ct; ct += (int64_t)gridDim.x * 256) {
+    const int64_t n = cnt[ct];
+    const int nch = n == 0 ? 1 : (int)((n + chunk - 1) / chunk);
+    ib[ct] = nch;
+    pb[ct] = nch > 1 ? nch : 0;
+  }
+}
+
+// Sum of the partial rows of split tiles, in item order.
+__global__ __launch_bounds__(256) void k_reduce(GatherArgs g) {
+  for (int64_t ct = blockIdx.x; ct < g.n_ct; ct += gridDim.x) {
+    const int nch = g.ib[ct + 1] - g.ib[ct];
+    if (nch <= 1) continue;
+    const int c = (int)(ct % g.m.n_cond), t = (int)(ct / g.m.n_cond);
+    const double scale = g.m.prec == XS_FP32 ? exp(g.sb[g.cond[c].slot]) : 1.0;
+    const double* rows = g.part + (int64_t)g.pb[ct] * g.tile_bins;
+    double* out = g.sigma + (int64_t)c * g.m.n_bins;
+    for (int o = threadIdx.x; o < g.tile_bins; o += 256) {
+      const int64_t k = (int64_t)t * g.tile_bins + o;
+      if (k >= g.m.n_bins) break;
+      double s = 0.0;
+      for (int j = 0; j < nch; ++j) s += rows[(int64_t)j * g.tile_bins + o];
+      const double v = scale * s;
+      out[k] = g.accumulate ? out[k] + v : v;
+    }
+  }
+}
+
+template <typename Real, int PROF>
+static void gather_dispatch(const GatherArgs& a, int M, int blocks, hipStream_t s) {
+#define XS_G(MM)                                                                      \
+  if (M == MM) {                                                                      \
+    hipLaunchKernelGGL((k_gather<Real, PROF, MM>), dim3(blocks), dim3(64), 0, s, a); \
+    return;                                                                           \
+  }
+  XS_G(4) XS_G(8) XS_G(16)
 #undef XS_G
 }
 
@@ -597,24 +656,39 @@ void launch_gather(const ModelDev& m, const Work& w, const Tiling& t, double* si
   a.rS = w.rS;
   a.max_lines = w.max_lines;
   a.counter = w.counter;
+  a.ib = w.item_base;
+  a.pb = w.part_base;
+  a.part = w.part;
   a.sigma = sigma;
   a.accumulate = accumulate;
   a.tile_bins = t.tile_bins;
   a.n_tiles = (int)((m.n_bins + t.tile_bins - 1) / t.tile_bins);
-  a.n_items = (int64_t)a.n_tiles * m.n_cond;
+  a.n_ct = a.n_tiles * m.n_cond;
   a.persistent = t.persistent;
-  const int blocks = t.persistent ? t.grid_blocks : (int)a.n_items;
+  a.chunk_cfg = t.chunk_lines;
+  a.item_target = w.item_target;
+  // plan the work items
+  launch_reset_queue(w, s);
+  const int cb = (int)std::min<int64_t>(1024, (a.n_ct + 255) / 256);
+  hipLaunchKernelGGL(k_items_count, dim3(cb), dim3(256), 0, s, a, w.item_cnt);
+  hipLaunchKernelGGL(k_items_split, dim3(cb), dim3(256), 0, s, a, (const int32_t*)w.item_cnt,
+                     w.item_base, w.part_base);
+  launch_scan_i32(w.item_base, (int64_t)a.n_ct + 1, w.item_sums, s);
+  launch_scan_i32(w.part_base, (int64_t)a.n_ct + 1, w.item_sums, s);
+  // every item fits the bound n_ct + item_target (one per unsplit tile plus
+  // at most total / chunk extra)
+  const int blocks = t.persistent ? t.grid_blocks : (int)(a.n_ct + w.item_target);
+  const int M = t.tile_bins / 64;
 #define XS_P(R, P)                                   \
-  if (m.profile == P) {                              \
-    gather_dispatch<R, P>(a, t, blocks, s);          \
-    return;                                          \
-  }
+  if (m.profile == P) gather_dispatch<R, P>(a, M, blocks, s);
   if (m.prec == XS_FP32) {
     XS_P(float, XS_DOPPLER) XS_P(float, XS_GAUSSIAN) XS_P(float, XS_LORENTZ) XS_P(float, XS_VOIGT)
   } else {
     XS_P(double, XS_DOPPLER) XS_P(double, XS_GAUSSIAN) XS_P(double, XS_LORENTZ) XS_P(double, XS_VOIGT)
   }
 #undef XS_P
+  const int rb = (int)std::min<int64_t>(65536, a.n_ct);
+  hipLaunchKernelGGL(k_reduce, dim3(rb), dim3(256), 0, s, a);
 }
 
 // Evaluators of the scatter (one lane per bin, band per lane).

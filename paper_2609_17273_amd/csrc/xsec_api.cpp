@@ -145,11 +145,10 @@ int validate_lines(const xs_plan* p, const xs_lines* l) {
 
 int validate_config(const xs_config* c) {
   if (!c) return fail(XS_EINVAL, "config is NULL");
-  if (c->tile_waves != 1 && c->tile_waves != 2 && c->tile_waves != 4)
-    return fail(XS_EINVAL, "config.tile_waves must be 1, 2 or 4");
-  const int per_lane = c->tile_bins / (64 * c->tile_waves);
-  if (per_lane * 64 * c->tile_waves != c->tile_bins || (per_lane != 2 && per_lane != 4 && per_lane != 8))
-    return fail(XS_EINVAL, "config.tile_bins must be tile_waves x 64 x (2, 4 or 8)");
+  if (c->tile_bins != 256 && c->tile_bins != 512 && c->tile_bins != 1024)
+    return fail(XS_EINVAL, "config.tile_bins must be 256, 512 or 1024");
+  if (c->chunk_lines < 0 || c->chunk_lines > (1 << 30) || c->chunk_lines % 64)
+    return fail(XS_EINVAL, "config.chunk_lines must be 0 or a multiple of 64 up to 2^30");
   const int b = c->bucket_bins;
   if (b < 64 || b > 4096 || (b & (b - 1))) return fail(XS_EINVAL, "config.bucket_bins must be a power of two in [64, 4096]");
   if (c->persistent != 0 && c->persistent != 1) return fail(XS_EINVAL, "config.persistent must be 0 or 1");
@@ -182,14 +181,13 @@ LinesView view(const xs_lines* l) {
   return v;
 }
 
-// Tile shape: tile_waves waves x 64 lanes x per-lane bins.
-void tiling_for(xs_plan* p, int tile_bins, int persistent, int waves_per_cu, int tile_waves) {
+// Tile shape (64 lanes x tile_bins / 64 bins), launch mode and lines per work item.
+void tiling_for(xs_plan* p, int tile_bins, int persistent, int waves_per_cu, int chunk_lines) {
   Tiling t;
   t.tile_bins = tile_bins;
-  t.waves = tile_waves;
-  t.per_lane = tile_bins / (64 * tile_waves);
   t.persistent = persistent;
-  t.grid_blocks = std::max(1, p->n_cu * waves_per_cu / t.waves);
+  t.grid_blocks = std::max(1, p->n_cu * waves_per_cu);
+  t.chunk_lines = chunk_lines;
   p->tiling = t;
 }
 
@@ -299,6 +297,16 @@ size_t layout(xs_plan* p, char* base, Work* w) {
   x.ridx = (int32_t*)take(4 * L);
   x.rS = take((size_t)(d.prec == XS_FP32 ? 4 : 8) * d.n_slots * L);
   x.counter = (int32_t*)take(4 * 64);
+  {
+    // work items of the gather: sized for the smallest tile (256 bins)
+    const int64_t n_ct = (int64_t)d.n_cond * ((p->grid.n_bins + 255) / 256);
+    x.item_cnt = (int32_t*)take(4 * (size_t)n_ct);
+    x.item_base = (int32_t*)take(4 * (size_t)(n_ct + 1));
+    x.part_base = (int32_t*)take(4 * (size_t)(n_ct + 1));
+    x.item_sums = (int32_t*)take(4 * (size_t)((n_ct + 1) / 1024 + 2));
+    x.item_target = kItemsPerCU * (int64_t)std::max(1, p->n_cu);
+    x.part = (double*)take(sizeof(double) * 2 * (size_t)x.item_target * 1024);
+  }
   x.stats = (unsigned long long*)take(8 * 8);
   x.adjpart = (double*)take(sizeof(double) * d.n_cond * 2 * kAdjBlocks);
   x.cut_class = (double*)take(sizeof(double) * d.n_cut_classes);
@@ -403,7 +411,7 @@ int xs_plan_create(xs_plan** out, const xs_model* model, const xs_grid* grid, in
   p->n_cu = prop.multiProcessorCount;
   p->arch = prop.gcnArchName;
   derive(p);
-  tiling_for(p, 512, 0, 16, 1);
+  tiling_for(p, 512, 1, 16, 0);
   std::memset(&p->w, 0, sizeof(p->w));
   *out = p;
   g_err.clear();
@@ -485,7 +493,7 @@ int xs_plan_set_config(xs_plan* p, const xs_config* c) {
       if ((rc = upload(p))) return rc;
     }
   }
-  tiling_for(p, c->tile_bins, c->persistent, c->waves_per_cu, c->tile_waves);
+  tiling_for(p, c->tile_bins, c->persistent, c->waves_per_cu, c->chunk_lines);
   return XS_OK;
 }
 
@@ -494,8 +502,8 @@ int xs_plan_get_config(const xs_plan* p, xs_config* c) {
   c->tile_bins = p->tiling.tile_bins;
   c->bucket_bins = p->bucket_bins;
   c->persistent = p->tiling.persistent;
-  c->waves_per_cu = p->tiling.grid_blocks * p->tiling.waves / std::max(1, p->n_cu);
-  c->tile_waves = p->tiling.waves;
+  c->waves_per_cu = p->tiling.grid_blocks / std::max(1, p->n_cu);
+  c->chunk_lines = (int32_t)p->tiling.chunk_lines;
   return XS_OK;
 }
 
@@ -661,14 +669,14 @@ static bool cache_lookup(const char* path, const std::string& key, xs_config* c)
   bool found = false;
   while (std::fgets(line, sizeof(line), f)) {
     char k[256];
-    int t, b, per, wv, tw;
-    if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"tile_bins\": %d, \"bucket_bins\": %d, \"persistent\": %d, \"waves_per_cu\": %d, \"tile_waves\": %d",
-                    k, &t, &b, &per, &wv, &tw) == 6 && key == k) {
+    int t, b, per, wv, cl;
+    if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"tile_bins\": %d, \"bucket_bins\": %d, \"persistent\": %d, \"waves_per_cu\": %d, \"chunk_lines\": %d",
+                    k, &t, &b, &per, &wv, &cl) == 6 && key == k) {
       c->tile_bins = t;
       c->bucket_bins = b;
       c->persistent = per;
       c->waves_per_cu = wv;
-      c->tile_waves = tw;
+      c->chunk_lines = cl;
       found = true;
     }
   }
@@ -680,8 +688,8 @@ static void cache_store(const char* path, const std::string& key, const xs_confi
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "{\"key\": \"%s\", \"tile_bins\": %d, \"bucket_bins\": %d, \"persistent\": %d, \"waves_per_cu\": %d, \"tile_waves\": %d, \"ms\": %.4f}\n",
-               key.c_str(), c.tile_bins, c.bucket_bins, c.persistent, c.waves_per_cu, c.tile_waves, ms);
+  std::fprintf(f, "{\"key\": \"%s\", \"tile_bins\": %d, \"bucket_bins\": %d, \"persistent\": %d, \"waves_per_cu\": %d, \"chunk_lines\": %d, \"ms\": %.4f}\n",
+               key.c_str(), c.tile_bins, c.bucket_bins, c.persistent, c.waves_per_cu, c.chunk_lines, ms);
   std::fclose(f);
 }
 
@@ -701,18 +709,19 @@ int xs_plan_autotune(xs_plan* p, const xs_states* st, const xs_lines* ln, double
     (void)hipEventDestroy(e0);
     return rc;
   }
-  // candidates: (tile_waves, bins per lane) and persistent or not
-  const int shapes[7][2] = {{1, 4}, {1, 8}, {2, 4}, {2, 8}, {4, 2}, {4, 4}, {4, 8}};
+  // candidates: tile width x launch mode (persistent queue with two grid sizes, or one block per item)
+  const int tiles[3] = {256, 512, 1024};
+  const int modes[3][2] = {{0, 16}, {1, 16}, {1, 32}};
   double best_ms = 1e300;
   xs_config cur;
   cur.bucket_bins = p->bucket_bins;
-  for (int si = 0; si < 7 && !rc; ++si) {
-    for (int per = 0; per < 2 && !rc; ++per) {
-      cur.tile_waves = shapes[si][0];
-      cur.tile_bins = shapes[si][0] * 64 * shapes[si][1];
-      cur.persistent = per;
-      cur.waves_per_cu = per ? 32 : 16;
-      tiling_for(p, cur.tile_bins, cur.persistent, cur.waves_per_cu, cur.tile_waves);
+  cur.chunk_lines = 0;
+  for (int si = 0; si < 3 && !rc; ++si) {
+    for (int mi = 0; mi < 3 && !rc; ++mi) {
+      cur.tile_bins = tiles[si];
+      cur.persistent = modes[mi][0];
+      cur.waves_per_cu = modes[mi][1];
+      tiling_for(p, cur.tile_bins, cur.persistent, cur.waves_per_cu, cur.chunk_lines);
       float ms_best = 1e30f;
       for (int rep = 0; rep < 3 && !rc; ++rep) {
         launch_reset_queue(p->w, p->stream);
@@ -733,7 +742,7 @@ int xs_plan_autotune(xs_plan* p, const xs_states* st, const xs_lines* ln, double
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  tiling_for(p, best.tile_bins, best.persistent, best.waves_per_cu, best.tile_waves);
+  tiling_for(p, best.tile_bins, best.persistent, best.waves_per_cu, best.chunk_lines);
   cache_store(cache_path, key, best, best_ms);
   return XS_OK;
 }

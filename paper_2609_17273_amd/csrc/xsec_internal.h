@@ -20,6 +20,7 @@ constexpr double kLN2 = 0.69314718055994530942;
 
 constexpr int kMaxCond = 256;
 constexpr int kQBlocks = 256;     // partial sums per slot in the partition-function reduction
+constexpr int kItemsPerCU = 64;   // gather work items aimed at per compute unit when tiles are split
 constexpr int kAdjBlocks = 2048;  // persistent blocks of the adjoint (fixed: deterministic sums)
 constexpr int kSortItems = 16;    // keys per thread in the radix sort (4096 per block)
 constexpr int kSortBlock = 256 * kSortItems;
@@ -96,7 +97,13 @@ struct Work {
   float* rnexp;             //                 n_exp
   int32_t* ridx;            //                 original line index
   void* rS;                 //                 S (f64) or S~ (f32), [n_slots][max_lines]
-  int32_t* counter;         // [64] work queues
+  int32_t* counter;         // [64] work queue, candidate total, lines per item
+  int32_t* item_cnt;        // [n_ct_max] candidate lines of each (tile, condition)
+  int32_t* item_base;       // [n_ct_max + 1] work items of each (tile, condition), scanned
+  int32_t* part_base;       // [n_ct_max + 1] partial rows of split tiles, scanned
+  int32_t* item_sums;       // scan block sums
+  double* part;             // [2 item_target][1024] partial rows
+  int64_t item_target;      // work items aimed at when tiles are split
   unsigned long long* stats;// [8]
   double* adjpart;          // [n_cond][2][kAdjBlocks]
   double* cut_class;        // [n_cut_classes] distinct cut-offs
@@ -106,11 +113,10 @@ struct Work {
 };
 
 struct Tiling {
-  int32_t tile_bins;   // bins per gather work item
-  int32_t per_lane;    // consecutive bins per lane
-  int32_t waves;       // waves per workgroup
+  int32_t tile_bins;   // bins per gather tile: 64 lanes x tile_bins / 64 bins each
   int32_t persistent;
-  int32_t grid_blocks; // persistent grid size
+  int32_t grid_blocks; // persistent grid size (one wave per block)
+  int64_t chunk_lines; // requested candidate lines per work item (0: automatic)
 };
 
 // ---- launch wrappers (k_lines.hip) ----
@@ -127,6 +133,7 @@ void launch_intensity_out(const ModelDev& m, const Work& w, const StatesView& st
 void launch_q_out(const ModelDev& m, const Work& w, double* Q, double* dQ, hipStream_t s);
 void launch_reset(const Work& w, hipStream_t s);
 void launch_reset_queue(const Work& w, hipStream_t s);
+void launch_scan_i32(int32_t* a, int64_t n, int32_t* sums, hipStream_t s);  // exclusive, in place
 
 // ---- profile pass (k_profile.hip) ----
 void launch_gather(const ModelDev& m, const Work& w, const Tiling& t, double* sigma,

@@ -63,15 +63,14 @@ def test_all_configurations_agree(prec):
     ref = oracle.run_condition(wl, ln, wl.conditions[0]).sigma
     plan = make_plan(wl, prec, ln.n)
     ds, dl = gpu_inputs(wl, ln)
-    for tw, per_lane in ((1, 4), (1, 8), (2, 4), (2, 8), (4, 2), (4, 4), (4, 8)):
-        for bucket in (128, 256, 1024):
+    for tile in (256, 512, 1024):
+        for bucket, chunk in ((128, 0), (256, 64), (1024, 640), (256, 0)):
             for pers in (0, 1):
-                tile = tw * 64 * per_lane
                 plan.set_config(tile_bins=tile, bucket_bins=bucket, persistent=pers, waves_per_cu=8,
-                                tile_waves=tw)
+                                chunk_lines=chunk)
                 got = plan.cross_section(ds, dl)[0].cpu().numpy()
                 e, _, _ = rel_err(got, ref)
-                assert e <= (1e-10 if prec == FP64 else 1e-4), (tile, tw, bucket, pers, e)
+                assert e <= (1e-10 if prec == FP64 else 1e-4), (tile, bucket, chunk, pers, e)
     cfg = plan.autotune(ds, dl, torch.empty((1, wl.grid.n_bins), dtype=torch.float64, device="cuda"))
     got = plan.cross_section(ds, dl)[0].cpu().numpy()
     e, _, _ = rel_err(got, ref)
