@@ -207,12 +207,23 @@ __device__ __noinline__ void w_core(double x, double y, double& wr, double& wi) 
   const double hr = ax - XS_FT_STEP * i, hi = y - XS_FT_STEP * j;
   const double* c = xs_ft_coef + (size_t)((i * XS_FT_NA + j) * (XS_FT_KMAX + 1)) * 2;
   double pr = c[2 * K], pi = c[2 * K + 1];
+  if constexpr (K <= 16) {
+    // short series: every coefficient load is issued before the Horner chain
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k) {
+      double nr = fma(pr, hr, fma(-pi, hi, c[2 * k]));
+      double ni = fma(pr, hi, fma(pi, hr, c[2 * k + 1]));
+      pr = nr;
+      pi = ni;
+    }
+  } else {
 #pragma unroll 2
-  for (int k = K - 1; k >= 0; --k) {
-    double nr = fma(pr, hr, fma(-pi, hi, c[2 * k]));
-    double ni = fma(pr, hi, fma(pi, hr, c[2 * k + 1]));
-    pr = nr;
-    pi = ni;
+    for (int k = K - 1; k >= 0; --k) {
+      double nr = fma(pr, hr, fma(-pi, hi, c[2 * k]));
+      double ni = fma(pr, hi, fma(pi, hr, c[2 * k + 1]));
+      pr = nr;
+      pi = ni;
+    }
   }
   wr = pr;
   wi = x < 0.0 ? -pi : pi;

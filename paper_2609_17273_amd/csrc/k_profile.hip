@@ -103,25 +103,28 @@ __device__ __forceinline__ KRange x_range(double X, double a, double b, int64_t 
 
 // Class of a staged line for the tile: 0 = nothing to add (outside the
 // window, or a Gaussian whose 2^{-x^2} vanishes on every bin of the tile);
-// 1 = the whole tile is inside the window and takes the first uniform formula
-// (Voigt: one node pair; Gaussian, Lorentzian: the profile itself); 3 = inside
-// the window, second uniform formula (Voigt: two node pairs); 2 = general
-// per-chunk path (window edges, the core, lines evaluated in FP64).
-constexpr int kRowSkip = 0, kRowF1 = 1, kRowGeneral = 2, kRowF2 = 3;
+// 1 = every bin of the tile takes the first uniform formula (Voigt: one node
+// pair; Gaussian, Lorentzian: the profile itself); 3 = second uniform formula
+// (Voigt: two node pairs); 4, 5 = as 1, 3 where a window end falls inside the
+// tile (the same formula under a window mask); 2 = general per-chunk path
+// (the core, the Gaussian's zero chunks, lines evaluated in FP64).
+constexpr int kRowSkip = 0, kRowF1 = 1, kRowGeneral = 2, kRowF2 = 3, kRowF1M = 4, kRowF2M = 5;
 
 // FP32 form.  The first-formula fields come first (two 16-byte LDS reads);
 // the second formula reads a, nb, jfb and B1, B2.
 //   rB: bins that are not far-wing (one node pair) -- for the Gaussian, the
-//       bins where 2^{-x^2} is not zero in FP32; rC: bins near the core that
-//       need the per-lane choice (Taylor core or two node pairs).
+//       bins where 2^{-x^2} is not zero in FP32; rC, rD: bins with
+//       |z|^2 < 64 and < 36 (outside rC two node pairs suffice, outside rD
+//       three; inside rD the Taylor core).
 struct __attribute__((aligned(16))) RecF {
   float a, nb, jfb, c0;  // x = (jfb + offset of the bin in the tile) a + nb; jfb = tlo - k_c
   Pair<float> A;         // one node pair
   Pair<float> B1, B2;    // two node pairs
   int klo, khi, flag, kc;
   KRange rB, rC;
+  KRange rD;
   float y;
-  int pad0, pad1, pad2;
+  int pad0;
 };
 // FP64 form.  r[0..4]: bins with |z|^2 below 9e6, 6400, 400, 144, 64 (the
 // thresholds of the 1, 2, 3, 4 and 6 node-pair bands); for the Gaussian,
@@ -224,6 +227,7 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
     r.y = (float)lp.y;
     r.rB = none;
     r.rC = none;
+    r.rD = none;
     if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
       r.rB = x_range(sqrt(160.0), a, b, kc, klo, khi);
       nz = r.rB;
@@ -231,6 +235,7 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
     } else if (PROF == XS_VOIGT) {
       r.rB = xr(900.0 * 1.001);
       r.rC = xr(64.0 * 1.001);
+      r.rD = xr(36.0 * 1.001);
       // FP32 keeps u (u + q) + p^2 finite for |x|, y < ~1e9; lines beyond that
       // (nu of a few 1e-3 cm^-1 or less) are evaluated in FP64.
       const double xmax = fmax(fabs((double)(klo - kc) * a - b), fabs((double)(khi - kc) * a - b));
@@ -260,10 +265,10 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
     }
   }
   if (!meets(lo, hi, nz)) return kRowSkip;
-  if (!inside || r.flag) return kRowGeneral;
-  if (gauss) return (nz.lo <= lo && nz.hi >= hi) ? kRowF1 : kRowGeneral;
-  if (!meets(lo, hi, n1)) return kRowF1;
-  if (can2 && !meets(lo, hi, n2)) return kRowF2;
+  if (r.flag) return kRowGeneral;
+  if (gauss) return (inside && nz.lo <= lo && nz.hi >= hi) ? kRowF1 : kRowGeneral;
+  if (!meets(lo, hi, n1)) return inside ? kRowF1 : kRowF1M;
+  if (can2 && !meets(lo, hi, n2)) return inside ? kRowF2 : kRowF2M;
   return kRowGeneral;
 }
 
@@ -305,12 +310,28 @@ __device__ __noinline__ double gh_pairs_y(double c0, double y, double u) {
   return s;
 }
 
-// Per-lane evaluation of a chunk that reaches |z| < 8 (FP32 form).
-__device__ __noinline__ float voigt_near_f32(float x, float y, float c0, Pair<float> B1, Pair<float> B2) {
+// Three node pairs (|z|^2 >= 36, relative error below 2e-7) from c0 and y,
+// FP32 form.
+__device__ __forceinline__ float gh3_f32(float u, float y, float c0) {
+  const float y2 = y * y;
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const float tau = (float)GH::t6[j];
+    const float p = y2 + tau;
+    s = fmaf((float)GH::w6[j] * (u + p), rcp32(fmaf(u, u + (2.0f * y2 - 2.0f * tau), p * p)), s);
+  }
+  return c0 * (float)(2.0 / kPI) * y * s;
+}
+
+// Per-lane evaluation of a chunk that reaches |z| < 6 (FP32 form): three node
+// pairs, or the Taylor core with 13 terms (truncation below 1e-9 |w| for the
+// half-step anchors of the table).
+__device__ __noinline__ float voigt_near_f32(float x, float y, float c0) {
   const float u = x * x;
-  if (u + y * y >= 64.0f) return pair_term<float>(B1, u) + pair_term<float>(B2, u);
+  if (u + y * y >= 36.0f) return gh3_f32(u, y, c0);
   double wr, wi;
-  w_core<16>((double)x, (double)y, wr, wi);
+  w_core<13>((double)x, (double)y, wr, wi);
   return c0 * (float)wr;
 }
 
@@ -379,13 +400,21 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
       int cls = kRowSkip;
       const int64_t p = p0 + lane;
       if (p < q1) cls = stage_line<Rec, PROF>(g, cd, p, tlo, thi, ROWB, r);
+      // LDS order: F1 | F1M | F2 | F2M | general
       const unsigned long long b1 = __ballot(cls == kRowF1);
+      const unsigned long long b1m = __ballot(cls == kRowF1M);
       const unsigned long long b2 = __ballot(cls == kRowF2);
+      const unsigned long long b2m = __ballot(cls == kRowF2M);
       const unsigned long long bg = __ballot(cls == kRowGeneral);
-      const int n1 = __popcll(b1), n2 = __popcll(b2), ng = __popcll(bg);
-      if (n1 + n2 + ng == 0) continue;
-      const unsigned long long mine = cls == kRowF1 ? b1 : (cls == kRowF2 ? b2 : bg);
-      const int base = cls == kRowF1 ? 0 : (cls == kRowF2 ? n1 : n1 + n2);
+      const int e1 = __popcll(b1), e1m = e1 + __popcll(b1m), e2 = e1m + __popcll(b2);
+      const int e2m = e2 + __popcll(b2m), eg = e2m + __popcll(bg);
+      if (eg == 0) continue;
+      unsigned long long mine = bg;
+      int base = e2m;
+      if (cls == kRowF1) { mine = b1; base = 0; }
+      else if (cls == kRowF1M) { mine = b1m; base = e1; }
+      else if (cls == kRowF2) { mine = b2; base = e1m; }
+      else if (cls == kRowF2M) { mine = b2m; base = e2; }
       const int slot = base + __builtin_amdgcn_mbcnt_hi((unsigned)(mine >> 32),
                                                         __builtin_amdgcn_mbcnt_lo((unsigned)mine, 0u));
       __syncthreads();
@@ -395,56 +424,88 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
       if constexpr (F32) {
         // x = (k - k_c) a - b, with k - k_c = (tlo - k_c) + (offset in tile):
         // integers, exact in FP32 within a window
-        // ---- first formula ----
-#pragma unroll 2
-        for (int l = 0; l < n1; ++l) {
-          const RecF& rr = srec[l];
-          const float a = rr.a, nb = rr.nb, jf0 = rr.jfb + lane_off;
-          if (PROF == XS_LORENTZ) {
-            const float c0 = rr.c0;
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-              const float x = fmaf(jf0 + (float)(64 * j), a, nb);
-              acc32[j] = fmaf(c0, rcp32(fmaf(x, x, 1.0f)), acc32[j]);
-            }
-          } else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
-            const float c0 = rr.c0;
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-              const float x = fmaf(jf0 + (float)(64 * j), a, nb);
-              acc32[j] = fmaf(c0, __builtin_amdgcn_exp2f(-(x * x)), acc32[j]);
-            }
-          } else {
-            const float cw = rr.A.cw, cwp = rr.A.cwp, q = rr.A.q, p2 = rr.A.p2;
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-              const float x = fmaf(jf0 + (float)(64 * j), a, nb);
-              const float u = x * x;
-              acc32[j] = fmaf(fmaf(cw, u, cwp), rcp32(fmaf(u, u + q, p2)), acc32[j]);
-            }
-          }
-        }
-        // ---- second formula (Voigt: two node pairs) ----
-        if (PROF == XS_VOIGT) {
-          for (int l = n1; l < n1 + n2; ++l) {
+        // ---- first formula; then the same under the window mask ----
+        auto first = [&](int l0, int l1, auto masked) {
+          for (int l = l0; l < l1; ++l) {
             const RecF& rr = srec[l];
             const float a = rr.a, nb = rr.nb, jf0 = rr.jfb + lane_off;
-            const Pair<float> B1 = rr.B1, B2 = rr.B2;
+            int klo = 0, khi = 0;
+            if (masked) {
+              klo = uni(rr.klo);
+              khi = uni(rr.khi);
+            }
+            if (PROF == XS_LORENTZ) {
+              const float c0 = rr.c0;
 #pragma unroll
-            for (int j = 0; j < M; ++j) {
-              const float x = fmaf(jf0 + (float)(64 * j), a, nb);
-              const float u = x * x;
-              acc32[j] += pair_term<float>(B1, u) + pair_term<float>(B2, u);
+              for (int j = 0; j < M; ++j) {
+                const float x = fmaf(jf0 + (float)(64 * j), a, nb);
+                if (!masked) {
+                  acc32[j] = fmaf(c0, rcp32(fmaf(x, x, 1.0f)), acc32[j]);
+                } else {
+                  const int k = my0 + 64 * j;
+                  const float t = c0 * rcp32(fmaf(x, x, 1.0f));
+                  acc32[j] += (k >= klo && k <= khi) ? t : 0.0f;
+                }
+              }
+            } else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+              const float c0 = rr.c0;
+#pragma unroll
+              for (int j = 0; j < M; ++j) {
+                const float x = fmaf(jf0 + (float)(64 * j), a, nb);
+                acc32[j] = fmaf(c0, __builtin_amdgcn_exp2f(-(x * x)), acc32[j]);
+              }
+            } else {
+              const float cw = rr.A.cw, cwp = rr.A.cwp, q = rr.A.q, p2 = rr.A.p2;
+#pragma unroll
+              for (int j = 0; j < M; ++j) {
+                const float x = fmaf(jf0 + (float)(64 * j), a, nb);
+                const float u = x * x;
+                if (!masked) {
+                  acc32[j] = fmaf(fmaf(cw, u, cwp), rcp32(fmaf(u, u + q, p2)), acc32[j]);
+                } else {
+                  const int k = my0 + 64 * j;
+                  const float t = fmaf(cw, u, cwp) * rcp32(fmaf(u, u + q, p2));
+                  acc32[j] += (k >= klo && k <= khi) ? t : 0.0f;
+                }
+              }
             }
           }
+        };
+        first(0, e1, std::false_type());
+        first(e1, e1m, std::true_type());
+        // ---- second formula (Voigt: two node pairs), unmasked then masked ----
+        if (PROF == XS_VOIGT) {
+          auto second = [&](int l0, int l1, auto masked) {
+            for (int l = l0; l < l1; ++l) {
+              const RecF& rr = srec[l];
+              const float a = rr.a, nb = rr.nb, jf0 = rr.jfb + lane_off;
+              const Pair<float> B1 = rr.B1, B2 = rr.B2;
+              int klo = 0, khi = 0;
+              if (masked) {
+                klo = uni(rr.klo);
+                khi = uni(rr.khi);
+              }
+#pragma unroll
+              for (int j = 0; j < M; ++j) {
+                const float x = fmaf(jf0 + (float)(64 * j), a, nb);
+                const float u = x * x;
+                const float t = pair_term<float>(B1, u) + pair_term<float>(B2, u);
+                const int k = my0 + 64 * j;
+                acc32[j] += (!masked || (k >= klo && k <= khi)) ? t : 0.0f;
+              }
+            }
+          };
+          second(e1m, e2, std::false_type());
+          second(e2, e2m, std::true_type());
         }
         // ---- general path: per-chunk decisions ----
-        for (int l = n1 + n2; l < n1 + n2 + ng; ++l) {
+        for (int l = e2m; l < eg; ++l) {
           const RecF& rr = srec[l];
           const float a = rr.a, nb = rr.nb, jf0 = rr.jfb + lane_off;
           const int klo = uni(rr.klo), khi = uni(rr.khi);
           const KRange rB = {uni(rr.rB.lo), uni(rr.rB.hi)};
           const KRange rC = {uni(rr.rC.lo), uni(rr.rC.hi)};
+          const KRange rD = {uni(rr.rD.lo), uni(rr.rD.hi)};
           const bool flag = PROF == XS_VOIGT && uni(rr.flag);
 #pragma unroll
           for (int j = 0; j < M; ++j) {
@@ -469,8 +530,10 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
             } else if (!meets(cl, ch, rC)) {
               const float u = x * x;
               v = pair_term<float>(rr.B1, u) + pair_term<float>(rr.B2, u);
+            } else if (!meets(cl, ch, rD)) {
+              v = gh3_f32(x * x, rr.y, rr.c0);
             } else {
-              v = voigt_near_f32(x, rr.y, rr.c0, rr.B1, rr.B2);
+              v = voigt_near_f32(x, rr.y, rr.c0);
             }
             acc32[j] += (full || (k >= klo && k <= khi)) ? v : 0.0f;
           }
@@ -482,34 +545,40 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
         }
       } else {
         // FP64 form: x from the exact difference nu_k - nu_i
-        for (int l = 0; l < n1 + n2; ++l) {
-          const RecD& rr = srec[l];
-          const double nu = rr.nu, inv = rr.inv;
-          double xs[M];
+        auto uniform = [&](int l0, int l1, auto masked, auto two) {
+          for (int l = l0; l < l1; ++l) {
+            const RecD& rr = srec[l];
+            const double nu = rr.nu, inv = rr.inv;
+            int klo = 0, khi = 0;
+            if (masked) {
+              klo = uni(rr.klo);
+              khi = uni(rr.khi);
+            }
+            double xs[M];
 #pragma unroll
-          for (int j = 0; j < M; ++j) {
+            for (int j = 0; j < M; ++j) {
 #pragma clang fp contract(off)
-            xs[j] = (nuk[j] - nu) * inv;
+              xs[j] = (nuk[j] - nu) * inv;
+            }
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+              double t;
+              if (PROF == XS_LORENTZ) t = rr.c0 * rcp64(fma(xs[j], xs[j], 1.0));
+              else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) t = rr.c0 * exp2(-(xs[j] * xs[j]));
+              else if (!two) t = pair_term<double>(rr.A, xs[j] * xs[j]);
+              else t = pair2_term(rr.B1, rr.B2, xs[j] * xs[j]);
+              const int k = my0 + 64 * j;
+              if (!masked || (k >= klo && k <= khi)) acc64[j] += t;
+            }
           }
-          if (PROF == XS_LORENTZ) {
-            const double c0 = rr.c0;
-#pragma unroll
-            for (int j = 0; j < M; ++j) acc64[j] = fma(c0, rcp64(fma(xs[j], xs[j], 1.0)), acc64[j]);
-          } else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
-            const double c0 = rr.c0;
-#pragma unroll
-            for (int j = 0; j < M; ++j) acc64[j] = fma(c0, exp2(-(xs[j] * xs[j])), acc64[j]);
-          } else if (l < n1) {
-            const Pair<double> A = rr.A;
-#pragma unroll
-            for (int j = 0; j < M; ++j) acc64[j] += pair_term<double>(A, xs[j] * xs[j]);
-          } else {
-            const Pair<double> B1 = rr.B1, B2 = rr.B2;
-#pragma unroll
-            for (int j = 0; j < M; ++j) acc64[j] += pair2_term(B1, B2, xs[j] * xs[j]);
-          }
+        };
+        uniform(0, e1, std::false_type(), std::false_type());
+        uniform(e1, e1m, std::true_type(), std::false_type());
+        if (PROF == XS_VOIGT) {
+          uniform(e1m, e2, std::false_type(), std::true_type());
+          uniform(e2, e2m, std::true_type(), std::true_type());
         }
-        for (int l = n1 + n2; l < n1 + n2 + ng; ++l) {
+        for (int l = e2m; l < eg; ++l) {
           const RecD& rr = srec[l];
           const double nu = rr.nu, inv = rr.inv;
           const int klo = uni(rr.klo), khi = uni(rr.khi);
