@@ -90,9 +90,13 @@ __device__ __forceinline__ void prof_grad(R x, R y, double sgm, double gam, int 
       fs = rg;
       return;
     }
-    double wr, wi, dr, di;
-    if constexpr (sizeof(R) == 4) w_core_d<16>((double)x, (double)y, wr, wi, dr, di);
-    else w_core_d<22>((double)x, (double)y, wr, wi, dr, di);
+    // near region: w by the rational approximation, w' = -2 z w + 2i/sqrt(pi)
+    double wr, wi;
+    if constexpr (sizeof(R) == 4) w_weideman<24>((double)x, (double)y, wr, wi);
+    else w_weideman<40>((double)x, (double)y, wr, wi);
+    const double xd = (double)x, yd = (double)y;
+    const double dr = -2.0 * (xd * wr - yd * wi);
+    const double di = -2.0 * (xd * wi + yd * wr) + 2.0 / sqrt(kPI);
     f = (R)wr;
     fg = (R)di;                                           // Im w'
     fs = (R)(wr + ((double)x * dr - (double)y * di));     // Re G = Re w + Re(z w')

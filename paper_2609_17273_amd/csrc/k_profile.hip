@@ -324,17 +324,6 @@ __device__ __forceinline__ float gh3_f32(float u, float y, float c0) {
   return c0 * (float)(2.0 / kPI) * y * s;
 }
 
-// Per-lane evaluation of a chunk that reaches |z| < 6 (FP32 form): three node
-// pairs, or the Taylor core with 13 terms (truncation below 1e-9 |w| for the
-// half-step anchors of the table).
-__device__ __noinline__ float voigt_near_f32(float x, float y, float c0) {
-  const float u = x * x;
-  if (u + y * y >= 36.0f) return gh3_f32(u, y, c0);
-  double wr, wi;
-  w_core<13>((double)x, (double)y, wr, wi);
-  return c0 * (float)wr;
-}
-
 // Work item = (tile, condition, slice of the tile's candidate lines); one
 // wave per item.  Lane l owns the bins tlo + 64 j + l, j = 0..M-1, so each
 // "chunk" j is 64 consecutive bins and every per-chunk decision (window,
@@ -533,7 +522,9 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
             } else if (!meets(cl, ch, rD)) {
               v = gh3_f32(x * x, rr.y, rr.c0);
             } else {
-              v = voigt_near_f32(x, rr.y, rr.c0);
+              // a chunk that reaches |z| < 6: every lane takes the rational
+              // approximation (valid everywhere, so no divergence)
+              v = (float)((double)rr.c0 * re_w_core<24>((double)x, (double)rr.y));
             }
             acc32[j] += (full || (k >= klo && k <= khi)) ? v : 0.0f;
           }
@@ -612,9 +603,7 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
               } else if (!meets(cl, ch, KRange{uni(rr.r[4].lo), uni(rr.r[4].hi)}) || u + rr.y * rr.y >= 64.0) {
                 v = gh_pairs_y<6>(rr.c0, rr.y, u);
               } else {
-                double wr, wi;
-                w_core<22>(x, rr.y, wr, wi);
-                v = rr.c0 * wr;
+                v = rr.c0 * re_w_core<40>(x, rr.y);
               }
             }
             if (full || (k >= klo && k <= khi)) acc64[j] += v;
@@ -778,9 +767,7 @@ __device__ __forceinline__ float eval_f32(const ScatF& r, float x) {
     const float u = x * x;
     if (u + r.y2 >= 900.0f) return r.cy * gh_re_sum<1, float>(u, r.y2, r.q);
     if (u + r.y2 >= 64.0f) return r.cy * gh_re_sum<2, float>(u, r.y2, r.q);
-    double wr, wi;
-    w_core<16>((double)x, (double)r.y, wr, wi);
-    return r.c0 * (float)wr;
+    return r.c0 * (float)re_w_core<24>((double)x, (double)r.y);
   }
 }
 

@@ -1,0 +1,108 @@
+"""Host checks of the constants the device Faddeeva function is built from
+(paper_2609_17273_amd/csrc/faddeeva_table.h), against library routines: the
+Gauss-Hermite nodes and weights against numpy's rule, and the error bounds
+the kernels' region thresholds rely on against scipy.special.wofz and
+mpmath.  The formulas are evaluated here in numpy FP64 exactly as the kernels
+write them."""
+import os
+import re
+
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy.special import wofz
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                   "paper_2609_17273_amd", "csrc", "faddeeva_table.h")
+
+
+def _defs():
+    text = open(HDR).read()
+    out = {}
+    for name, body in re.findall(r"#define (XS_\w+) (.+)", text):
+        body = body.strip()
+        if body.startswith("{"):
+            out[name] = np.array([float.fromhex(v.strip()) for v in body.strip("{} ").split(",")])
+        else:
+            out[name] = float.fromhex(body)
+    return out
+
+
+D = _defs()
+
+
+def gh_re(n, x, y):
+    """Re w by the n-point Gauss-Hermite rule in node-pair form."""
+    tau, W = D[f"XS_GH{n}_TAU"], D[f"XS_GH{n}_W"]
+    u = x * x
+    s = 0.0
+    for t, w in zip(tau, W):
+        p = y * y + t
+        s = s + w * (u + p) / ((u - p) ** 2 + 4 * y * y * u)
+    return 2 * y / np.pi * s
+
+
+def weideman(n, z):
+    L, a = D[f"XS_WM{n}_L"], D[f"XS_WM{n}_A"]
+    q = 1.0 / (L - 1j * z)
+    Z = (L + 1j * z) * q
+    p = np.zeros_like(z)
+    for c in a[::-1]:
+        p = p * Z + c
+    return 2 * p * q * q + q / np.sqrt(np.pi)
+
+
+@pytest.mark.parametrize("n", [2, 4, 6, 8, 12])
+def test_gauss_hermite_nodes_match_numpy(n):
+    t, w = np.polynomial.hermite.hermgauss(n)
+    pos = t > 0
+    assert np.allclose(np.sort(t[pos] ** 2), D[f"XS_GH{n}_TAU"], rtol=1e-14, atol=0)
+    assert np.allclose(w[pos][np.argsort(t[pos])], D[f"XS_GH{n}_W"], rtol=1e-12, atol=0)
+    # the pairs carry half the total weight sqrt(pi)
+    assert abs(2 * D[f"XS_GH{n}_W"].sum() - np.sqrt(np.pi)) < 1e-14
+
+
+def _grid(xmax, ymax, nx=1201, ny=301):
+    xs = np.linspace(-xmax, xmax, nx)
+    ys = np.concatenate([[0.0, 1e-6, 1e-3], np.linspace(0.01, ymax, ny)])
+    X, Y = np.meshgrid(xs, ys)
+    return X + 1j * Y
+
+
+@pytest.mark.parametrize("n,bound", [(24, 5e-10), (40, 3e-14)])
+def test_weideman_relative_error(n, bound):
+    Z = _grid(25.0, 12.0)
+    err = np.abs(weideman(n, Z) - wofz(Z)) / np.abs(wofz(Z))
+    assert err.max() < bound, err.max()
+
+
+def test_weideman_against_mpmath():
+    rng = np.random.default_rng(7)
+    for _ in range(40):
+        z = complex(rng.uniform(-9, 9), rng.uniform(0, 9))
+        ref = complex(mp.exp(-mp.mpc(z) ** 2) * mp.erfc(-1j * mp.mpc(z)))
+        assert abs(complex(weideman(40, np.array([z]))[0]) - ref) <= 3e-14 * abs(ref)
+        assert abs(complex(weideman(24, np.array([z]))[0]) - ref) <= 5e-10 * abs(ref)
+
+
+# (rule, rho threshold, bound on the relative error of Re w where Re w > 1e-9)
+FP32_BANDS = [(2, 900.0, 4e-6), (4, 64.0, 1.1e-6), (6, 36.0, 2e-7)]
+FP64_BANDS = [(2, 9.0e6, 1e-13), (4, 6400.0, 1e-13), (6, 400.0, 1e-13), (8, 144.0, 1e-13),
+              (12, 64.0, 1e-13)]
+
+
+@pytest.mark.parametrize("n,rho,bound", FP32_BANDS + FP64_BANDS)
+def test_gauss_hermite_band_error(n, rho, bound):
+    r = np.sqrt(rho)
+    # points on and just outside the band edge, plus a far sample
+    th = np.linspace(0.0, np.pi / 2, 721)
+    pts = []
+    for scale in (1.0, 1.01, 1.1, 2.0, 10.0):
+        pts.append(scale * r * (np.cos(th) + 1j * np.sin(th)))
+    Z = np.concatenate(pts)
+    Z = Z[Z.imag >= 0]
+    ex = wofz(Z).real
+    keep = ex > 1e-9
+    got = gh_re(n, Z.real, Z.imag)
+    err = np.abs(got[keep] - ex[keep]) / ex[keep]
+    assert err.max() < bound, (n, rho, err.max())
