@@ -370,7 +370,9 @@ __global__ __launch_bounds__(256) void k_records(ModelDev m, const SlotDev* slot
                                                  const double* sb, StatesView st, LinesView ln,
                                                  const int32_t* svals, const int32_t* off,
                                                  int64_t max_lines, double* rnu, float* rgref,
-                                                 float* rnexp, int32_t* ridx, void* rS) {
+                                                 float* rnexp, int32_t* ridx, void* rS,
+                                                 const double* cut_class, int32_t* rkc, float* rdel,
+                                                 int32_t* rwin) {
   const int64_t nk = off[m.n_buckets];
   for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < nk;
        p += (int64_t)gridDim.x * 256) {
@@ -381,6 +383,19 @@ __global__ __launch_bounds__(256) void k_records(ModelDev m, const SlotDev* slot
     rgref[p] = ln.gref ? ln.gref[i] : (float)ln.gref_scalar;
     rnexp[p] = ln.nexp ? ln.nexp[i] : (float)ln.nexp_scalar;
     ridx[p] = i;
+    // home bin, offset from it, and the exact window of every cut-off class
+    const int64_t kc = home_bin(nu, m.nu0, m.dnu);
+    rkc[p] = (int32_t)kc;
+    rdel[p] = (float)(nu - nu_of_bin(m.nu0, m.dnu, kc));
+    for (int q = 0; q < m.n_cut_classes; ++q) {
+      int64_t klo, khi;
+      if (!line_window(nu, cut_class[q], m.nu0, m.dnu, m.n_bins, klo, khi)) {
+        klo = 1;
+        khi = 0;
+      }
+      rwin[((int64_t)q * max_lines + p) * 2] = (int32_t)klo;
+      rwin[((int64_t)q * max_lines + p) * 2 + 1] = (int32_t)khi;
+    }
     const LineState ls = line_state(st, u, l, m.pop);
     const double A = (double)ln.A[i];
     const double sc = ln.lscale ? (double)ln.lscale[i] : 0.0;
@@ -404,7 +419,8 @@ void launch_offsets_records(const ModelDev& m, const Work& w, const StatesView& 
   hipLaunchKernelGGL(k_offsets, dim3((unsigned)blocks), dim3(256), 0, s, skeys, n, m.n_buckets,
                      w.off);
   hipLaunchKernelGGL(k_records, dim3((unsigned)blocks), dim3(256), 0, s, m, w.slot, w.Q, w.sb, st,
-                     ln, svals, w.off, w.max_lines, w.rnu, w.rgref, w.rnexp, w.ridx, w.rS);
+                     ln, svals, w.off, w.max_lines, w.rnu, w.rgref, w.rnexp, w.ridx, w.rS,
+                     w.cut_class, w.rkc, w.rdel, w.rwin);
 }
 
 // ---------------------------------------------------------------------------

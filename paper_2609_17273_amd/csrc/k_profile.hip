@@ -146,6 +146,9 @@ struct GatherArgs {
   const float* rgref;
   const float* rnexp;
   const void* rS;
+  const int32_t* rkc;       // home bin of every sorted line
+  const float* rdel;        // nu - nu_{k_c}
+  const int32_t* rwin;      // exact windows per cut-off class
   int64_t max_lines;
   int32_t* counter;         // [0]: work queue; [2..3]: candidate total; [4..5]: lines per item
   const int32_t* ib;        // [n_ct + 1] first work item of each (tile, condition); ib[n_ct] = items
@@ -178,82 +181,125 @@ __device__ __forceinline__ void tile_candidates(const GatherArgs& g, const CondD
   phi = g.off[bhi + 1];
 }
 
+__device__ __forceinline__ float rcp32(float d) { return __builtin_amdgcn_rcpf(d); }
+
+// Bin range where |x| < X, relative to k_c, in FP32 (the one-bin margin
+// covers the rounding of a, b and of the quotient), clipped to the window.
+__device__ __forceinline__ KRange x_range_f(float X, float a, float b, int kc, int klo, int khi) {
+  KRange r;
+  r.lo = 0x7fffffff;
+  r.hi = -0x7fffffff;
+  if (!(X > 0.0f)) return r;
+  const float ra = 1.0f / a;
+  const float lo = fminf(fmaxf(floorf((b - X) * ra) - 1.0f, -1.0e9f), 1.0e9f);
+  const float hi = fminf(fmaxf(ceilf((b + X) * ra) + 1.0f, -1.0e9f), 1.0e9f);
+  const int l = max((int)lo + kc, klo - 1), h = min((int)hi + kc, khi + 1);
+  if (l <= h) {
+    r.lo = l;
+    r.hi = h;
+  }
+  return r;
+}
+
 // Staging: does line p touch bins [tlo, thi] under condition cd?  Fills the
-// record and returns its class for the tile row [tlo, tlo + rowb - 1].
+// record and returns its class for the tile row [tlo, tlo + rowb - 1].  The
+// line's home bin and exact window come from the record pass; the FP32 form
+// derives its constants in FP32 (relative error a few units of 1e-7, far
+// inside its tolerance), the FP64 form in FP64.
 template <typename Rec, int PROF>
 __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int64_t tlo,
                           int64_t thi, int rowb, Rec& r) {
   const ModelDev& m = g.m;
-  const double nu = g.rnu[p];
-  int64_t klo, khi;
-  if (!line_window(nu, cd.cut, m.nu0, m.dnu, m.n_bins, klo, khi)) return kRowSkip;
-  if (khi < tlo || klo > thi) return kRowSkip;
-  double S;
-  if constexpr (sizeof(Rec) == sizeof(RecF))
-    S = (double)((const float*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
-  else
-    S = ((const double*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
-  if (S == 0.0) return kRowSkip;
-  const int64_t kc = home_bin(nu, m.nu0, m.dnu);
-  const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
-  const LineParams lp = line_params<PROF>(m, cd, nu, (double)g.rgref[p], (double)g.rnexp[p], S);
-  klo = klo > tlo ? klo : tlo;
-  khi = khi < thi ? khi : thi;
-  r.klo = (int)klo;
-  r.khi = (int)khi;
+  const int2 win = ((const int2*)g.rwin)[(int64_t)cd.cclass * g.max_lines + p];
+  if (win.x > win.y || win.y < tlo || win.x > thi) return kRowSkip;
+  const int kc = g.rkc[p];
+  const int klo = max(win.x, (int)tlo), khi = min(win.y, (int)thi);
+  r.klo = klo;
+  r.khi = khi;
   r.flag = 0;
-  r.kc = (int)kc;
-  const double a = m.dnu * lp.inv, b = delta * lp.inv;
-  const double y2 = lp.y * lp.y;
-  using R = decltype(r.A.cw);
-  if (PROF == XS_VOIGT) {
-    r.A = make_pair<R>(lp.c0, lp.y, GH::t2[0], GH::w2[0]);
-    r.B1 = make_pair<R>(lp.c0, lp.y, GH::t4[0], GH::w4[0]);
-    r.B2 = make_pair<R>(lp.c0, lp.y, GH::t4[1], GH::w4[1]);
-  }
-  auto xr = [&](double rho) { return x_range(sqrt(fmax(rho - y2, 0.0)), a, b, kc, klo, khi); };
-  const KRange none = x_range(0.0, a, b, kc, klo, khi);
+  r.kc = kc;
   const int lo = (int)tlo, hi = lo + rowb - 1;
   const bool inside = klo <= lo && khi >= hi;
   // Gaussian: the nonzero range nz; first formula when the row lies inside it.
   // Voigt: first formula when the row avoids n1, second when it avoids n2.
-  KRange nz = KRange{(int)klo, (int)khi}, n1 = none, n2 = none;
+  KRange nz = KRange{klo, khi}, n1 = KRange{0x7fffffff, -0x7fffffff}, n2 = n1;
   bool can2 = false, gauss = false;
   if constexpr (sizeof(Rec) == sizeof(RecF)) {
-    r.a = (float)a;
-    r.nb = (float)(-b);
-    r.jfb = (float)(tlo - kc);  // integer, exact in FP32 within a window
-    r.c0 = (float)lp.c0;
-    r.y = (float)lp.y;
+    const float S = ((const float*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
+    if (S == 0.0f) return kRowSkip;
+    const float nu = (float)g.rnu[p];
+    float inv, y = 0.0f, c0;
+    if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+      const float alpha = PROF == XS_GAUSSIAN ? (float)cd.hwhm : nu * (float)cd.dop;
+      inv = rcp32(alpha);
+      c0 = S * (float)0.46971863934982566 * inv;           // sqrt(ln2/pi)/alpha
+    } else {
+      const float gamma = g.rgref[p] * __builtin_amdgcn_exp2f(g.rnexp[p] * (float)(cd.lnTr / kLN2)) *
+                          (float)cd.pfac;
+      if (PROF == XS_LORENTZ) {
+        inv = rcp32(gamma);
+        c0 = S * (float)(1.0 / kPI) * inv;
+      } else {
+        inv = (float)0.83255461115769776 * rcp32(nu * (float)cd.dop);  // sqrt(ln2)/alpha
+        y = gamma * inv;
+        c0 = S * (float)0.56418958354775628 * inv;         // 1/(sg sqrt(2 pi))
+      }
+    }
+    const float a = (float)m.dnu * inv, b = g.rdel[p] * inv;
+    r.a = a;
+    r.nb = -b;
+    r.jfb = (float)(lo - kc);  // integer, exact in FP32 within a window
+    r.c0 = c0;
+    r.y = y;
+    const KRange none = KRange{0x7fffffff, -0x7fffffff};
     r.rB = none;
     r.rC = none;
     r.rD = none;
     if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
-      r.rB = x_range(sqrt(160.0), a, b, kc, klo, khi);
+      r.rB = x_range_f(12.649110640673518f, a, b, kc, klo, khi);  // 2^{-x^2} = 0 beyond sqrt(160)
       nz = r.rB;
       gauss = true;
     } else if (PROF == XS_VOIGT) {
-      r.rB = xr(900.0 * 1.001);
-      r.rC = xr(64.0 * 1.001);
-      r.rD = xr(36.0 * 1.001);
+      const float y2 = y * y;
+      auto make = [&](double tau, double W) {
+        const float p2 = y2 + (float)tau, cw = c0 * (float)(2.0 / kPI) * y * (float)W;
+        return Pair<float>{cw, cw * p2, 2.0f * y2 - 2.0f * (float)tau, p2 * p2};
+      };
+      r.A = make(GH::t2[0], GH::w2[0]);
+      r.B1 = make(GH::t4[0], GH::w4[0]);
+      r.B2 = make(GH::t4[1], GH::w4[1]);
+      r.rB = x_range_f(sqrtf(fmaxf(900.9f - y2, 0.0f)), a, b, kc, klo, khi);
+      r.rC = x_range_f(sqrtf(fmaxf(64.064f - y2, 0.0f)), a, b, kc, klo, khi);
+      r.rD = x_range_f(sqrtf(fmaxf(36.036f - y2, 0.0f)), a, b, kc, klo, khi);
       // FP32 keeps u (u + q) + p^2 finite for |x|, y < ~1e9; lines beyond that
       // (nu of a few 1e-3 cm^-1 or less) are evaluated in FP64.
-      const double xmax = fmax(fabs((double)(klo - kc) * a - b), fabs((double)(khi - kc) * a - b));
-      if (xmax > 1.0e9 || lp.y > 1.0e9) r.flag = 1;
+      const float xmax = fmaxf(fabsf((float)(klo - kc) * a - b), fabsf((float)(khi - kc) * a - b));
+      if (!(xmax <= 1.0e9f) || !(y <= 1.0e9f)) r.flag = 1;
       n1 = r.rB;
       n2 = r.rC;
       can2 = true;
     }
   } else {
+    const double S = ((const double*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
+    if (S == 0.0) return kRowSkip;
+    const double nu = g.rnu[p];
+    const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
+    const LineParams lp = line_params<PROF>(m, cd, nu, (double)g.rgref[p], (double)g.rnexp[p], S);
+    const double a = m.dnu * lp.inv, b = delta * lp.inv;
+    const double y2 = lp.y * lp.y;
     r.nu = nu;
     r.inv = lp.inv;
     r.y = lp.y;
     r.c0 = lp.c0;
+    auto xr = [&](double rho) { return x_range(sqrt(fmax(rho - y2, 0.0)), a, b, kc, klo, khi); };
     if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
       r.r[0] = x_range(sqrt(1100.0), a, b, kc, klo, khi);
       nz = r.r[0];
       gauss = true;
     } else if (PROF == XS_VOIGT) {
+      r.A = make_pair<double>(lp.c0, lp.y, GH::t2[0], GH::w2[0]);
+      r.B1 = make_pair<double>(lp.c0, lp.y, GH::t4[0], GH::w4[0]);
+      r.B2 = make_pair<double>(lp.c0, lp.y, GH::t4[1], GH::w4[1]);
       r.r[0] = xr(9.0e6 * 1.001);
       r.r[1] = xr(6400.0 * 1.001);
       r.r[2] = xr(400.0 * 1.001);
@@ -280,7 +326,6 @@ __device__ __forceinline__ double rcp64(double d) {
   e = fma(-d, r, 1.0);
   return fma(r, e, r);
 }
-__device__ __forceinline__ float rcp32(float d) { return __builtin_amdgcn_rcpf(d); }
 
 template <typename R>
 __device__ __forceinline__ R pair_term(const Pair<R>& P, R u) {
@@ -524,7 +569,9 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
             } else {
               // a chunk that reaches |z| < 6: every lane takes the rational
               // approximation (valid everywhere, so no divergence)
-              v = (float)((double)rr.c0 * re_w_core<24>((double)x, (double)rr.y));
+              double wr, wi;
+              w_weideman<24>((double)x, (double)rr.y, wr, wi);
+              v = (float)((double)rr.c0 * wr);
             }
             acc32[j] += (full || (k >= klo && k <= khi)) ? v : 0.0f;
           }
@@ -712,6 +759,9 @@ void launch_gather(const ModelDev& m, const Work& w, const Tiling& t, double* si
   a.rgref = w.rgref;
   a.rnexp = w.rnexp;
   a.rS = w.rS;
+  a.rkc = w.rkc;
+  a.rdel = w.rdel;
+  a.rwin = w.rwin;
   a.max_lines = w.max_lines;
   a.counter = w.counter;
   a.ib = w.item_base;

@@ -247,17 +247,20 @@ void derive(xs_plan* p) {
     cd.pfac = c.P / m.P_ref;
     cd.slot = slot;
     cd.wbins = (int32_t)std::ceil(c.cutoff / p->grid.dnu) + 2;
-    p->cdev.push_back(cd);
     maxcut = std::max(maxcut, c.cutoff);
     int cc = -1;
     for (size_t q = 0; q < p->cut_class.size(); ++q)
       if (p->cut_class[q] == c.cutoff) cc = (int)q;
     if (cc < 0) {
+      cc = (int)p->cut_class.size();
       p->cut_class.push_back(c.cutoff);
       p->cut_mult.push_back(1);
     } else {
       p->cut_mult[cc] += 1;
     }
+    cd.cclass = cc;
+    cd.pad = 0;
+    p->cdev.push_back(cd);
   }
   d.n_slots = (int32_t)p->sdev.size();
   d.n_cut_classes = (int32_t)p->cut_class.size();
@@ -295,6 +298,9 @@ size_t layout(xs_plan* p, char* base, Work* w) {
   x.rgref = (float*)take(4 * L);
   x.rnexp = (float*)take(4 * L);
   x.ridx = (int32_t*)take(4 * L);
+  x.rkc = (int32_t*)take(4 * L);
+  x.rdel = (float*)take(4 * L);
+  x.rwin = (int32_t*)take(8 * (size_t)d.n_cut_classes * L);
   x.rS = take((size_t)(d.prec == XS_FP32 ? 4 : 8) * d.n_slots * L);
   x.counter = (int32_t*)take(4 * 64);
   {

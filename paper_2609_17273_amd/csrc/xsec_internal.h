@@ -35,6 +35,8 @@ struct CondDev {
   double pfac;    // P / P_ref
   int32_t slot;   // intensity slot (distinct T or (T_vib, T_rot))
   int32_t wbins;  // ceil(cut / dnu) + 2: bound on |k - k_c| inside the window
+  int32_t cclass; // cut-off class (index of the distinct cut-off)
+  int32_t pad;
 };
 
 // Per intensity slot: the temperatures of the populations.
@@ -96,6 +98,9 @@ struct Work {
   float* rgref;             //                 gamma_ref
   float* rnexp;             //                 n_exp
   int32_t* ridx;            //                 original line index
+  int32_t* rkc;             //                 home bin k_c = rint((nu - nu0)/dnu)
+  float* rdel;              //                 nu - nu_{k_c}
+  int32_t* rwin;            //                 [n_cut_classes][max_lines][2] window (klo, khi), klo > khi if empty
   void* rS;                 //                 S (f64) or S~ (f32), [n_slots][max_lines]
   int32_t* counter;         // [64] work queue, candidate total, lines per item
   int32_t* item_cnt;        // [n_ct_max] candidate lines of each (tile, condition)
