@@ -19,7 +19,8 @@ namespace xs {
 
 // Voigt far region with NP Gauss-Hermite pairs: returns Re w, and
 //   R1 = Re sum_j W_j (Z + tau_j)/(Z - tau_j)^2       (Im w' = -(2/pi) R1)
-//   RG = (4y/pi) sum_j W_j tau_j Im[z/(Z - tau_j)^2] = Re G,  G = w + z w'
+//   RG = (4/pi) sum_j W_j tau_j Im[z/(Z - tau_j)^2] = Re G,  G = w + z w'
+// (each pair's term 2z/(Z - tau) of w gives f + z f' = -4 z tau/(Z - tau)^2),
 // written without differences of nearly equal terms:
 //   Re (Z+tau)/(Z-tau)^2 = A/d + 2 tau (A^2 - Zi^2)/d^2,
 //   Im z/(Z-tau)^2       = y (A^2 - Zi^2 - 4 x^2 A)/d^2,
@@ -46,7 +47,7 @@ __device__ __forceinline__ void gh_adj(R x, R y, R& rew, R& r1, R& rg) {
   }
   rew = (R)(2.0 / kPI) * y * sw;
   r1 = s1;
-  rg = (R)(4.0 / kPI) * y * y * sg;
+  rg = (R)(4.0 / kPI) * y * sg;
 }
 
 // f, df/dsg, df/dgamma of the unit-area profile at x (its own scaling per
@@ -267,18 +268,31 @@ __device__ __forceinline__ void general_eval(const AdjLine<R>& L, bool wide, int
 // kFlush steps.
 constexpr int kFlush = 256;
 
+// Where a lane reads its cotangent g_k: straight from memory, or -- when the
+// wave's home bins lie within kFlush of each other -- from the wave's LDS
+// slice, refilled with one coalesced pass per block of kFlush steps.
+template <typename R>
+struct GSrc {
+  const double* gc;  // g of this condition
+  int64_t nb;        // grid points
+  int kcmin;         // smallest home bin of the wave's active lanes
+  bool lds;
+  R* buf;            // [2 kFlush] LDS slice of the wave
+};
+
 template <typename R, int PROF, int NP>
-__device__ __forceinline__ void fast_range(const AdjLine<R>& L, const double* __restrict__ gc, int r0, int r1,
+__device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G, int r0, int r1,
                                            double& sA, double& sB, double& sC) {
+  // the lanes running this loop (the wave's active lines) share the refills
+  const unsigned long long act = __ballot(1);
+  const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(act >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)act, 0u));
+  const int nact = __popcll(act);
   for (int rb = r0; rb <= r1; rb += kFlush) {
     const int n = min(kFlush, r1 - rb + 1);
-    const double* gp = gc + (L.kc + rb);
     R s1 = 0, s2 = 0, s3 = 0;
-#pragma unroll 4
-    for (int j = 0; j < n; ++j) {
+    auto body = [&](int j, R gk) {
       const R x = fma((R)(rb + j), L.a, L.nb);
       const R u = x * x;
-      const R gk = (R)gp[j];
       if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
         R e;
         if constexpr (sizeof(R) == 4) e = __builtin_amdgcn_exp2f(-u);
@@ -311,6 +325,26 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const double* __
         s2 = fma(gk, t, s2);
         s3 = fma(gk, s, s3);
       }
+    };
+    if (G.lds) {
+      // refill the wave's slice with g[kcmin + rb + t], t < 2 kFlush
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const int64_t kb = (int64_t)G.kcmin + rb;
+      for (int t = rank; t < 2 * kFlush; t += nact) {
+        const int64_t k = kb + t;
+        G.buf[t] = (k >= 0 && k < G.nb) ? (R)G.gc[k] : (R)0;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const R* gl = G.buf + (L.kc - G.kcmin);
+#pragma unroll 4
+      for (int j = 0; j < n; ++j) body(j, gl[j]);
+    } else {
+      const double* gp = G.gc + (L.kc + rb);
+#pragma unroll 4
+      for (int j = 0; j < n; ++j) body(j, (R)gp[j]);
     }
     // to the general-path convention
     if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
@@ -330,11 +364,11 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const double* __
 }
 
 template <typename R, int PROF>
-__device__ __forceinline__ void fast_level(int level, const AdjLine<R>& L, const double* gc, int r0, int r1,
+__device__ __forceinline__ void fast_level(int level, const AdjLine<R>& L, const GSrc<R>& G, int r0, int r1,
                                            double& sA, double& sB, double& sC) {
-  if (PROF != XS_VOIGT || level == 0) fast_range<R, PROF, 1>(L, gc, r0, r1, sA, sB, sC);
-  else if (level == 1) fast_range<R, PROF, 2>(L, gc, r0, r1, sA, sB, sC);
-  else if constexpr (sizeof(R) == 8) fast_range<R, PROF, 3>(L, gc, r0, r1, sA, sB, sC);
+  if (PROF != XS_VOIGT || level == 0) fast_range<R, PROF, 1>(L, G, r0, r1, sA, sB, sC);
+  else if (level == 1) fast_range<R, PROF, 2>(L, G, r0, r1, sA, sB, sC);
+  else if constexpr (sizeof(R) == 8) fast_range<R, PROF, 3>(L, G, r0, r1, sA, sB, sC);
 }
 
 // r-range of the bins where |x| < X (widened by one bin), clipped to
@@ -356,6 +390,131 @@ __device__ __forceinline__ void r_range(double X, double a, double b, int lo, in
   }
 }
 
+// Window sums of the lane's line (general-path convention: Re w, Re G, Im w'
+// for the Voigt profile).
+struct Sums3 {
+  double A, B, C;
+};
+
+template <typename R, int PROF>
+__device__ __forceinline__ Sums3 window_sums(bool on, int64_t klo, int64_t khi, double nu, double inv, double y,
+                                             const double* gc, double nu0, double dnu, int64_t nbins, R* gbuf) {
+  const int64_t kc64 = home_bin(nu, nu0, dnu);
+  const double delta = nu - nu_of_bin(nu0, dnu, kc64);
+  AdjLine<R> L;
+  L.kc = (int)kc64;
+  L.rlo = on ? (int)(klo - kc64) : 0x7fffffff;
+  L.rhi = on ? (int)(khi - kc64) : -0x7fffffff;
+  L.ad = dnu * inv;
+  L.bd = delta * inv;
+  L.y = y;
+  L.a = (R)L.ad;
+  L.nb = (R)(-L.bd);
+  L.ty2 = (R)(2.0 * y * y);
+  L.fy2 = (R)(4.0 * y * y);
+  bool wide = false;
+  if (PROF == XS_VOIGT) {
+    L.P[0] = pair_d<R>(y, GH::t2[0], GH::w2[0]);
+    L.P[1] = pair_d<R>(y, GH::t4[0], GH::w4[0]);
+    L.P[2] = pair_d<R>(y, GH::t4[1], GH::w4[1]);
+    if (sizeof(R) == 8) {
+      // FP64 levels: 1, 2 and 3 node pairs; pairs of the 3-pair rule are
+      // set when that level is entered.
+    }
+    if (sizeof(R) == 4 && on) {
+      const double xmax = fmax(fabs((double)L.rlo * L.ad - L.bd), fabs((double)L.rhi * L.ad - L.bd));
+      wide = xmax > 1.0e9 || y > 1.0e9;
+    }
+  }
+  // uniform runs along r
+  const int Rmin = wave_min(L.rlo), Rmax = wave_max(L.rhi);
+  const int Alo = wave_max(on ? L.rlo : -0x7fffffff), Ahi = wave_min(on ? L.rhi : 0x7fffffff);
+  const bool any_wide = __ballot(wide) != 0;
+  constexpr int NL = (PROF == XS_VOIGT) ? Levels<R>::n : 1;
+  int Hlo[NL], Hhi[NL];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    int rl = 0x7fffffff, rh = -0x7fffffff;
+    if (on) {
+      double X;
+      if (PROF == XS_VOIGT) X = sqrt(fmax(Levels<R>::rho[l] * 1.001 - y * y, 0.0));
+      else if (PROF == XS_LORENTZ) X = 0.0;  // one level, no inner region
+      else X = (sizeof(R) == 4) ? sqrt(160.0) : sqrt(1100.0);  // Gaussian: nonzero range
+      r_range(X, L.ad, L.bd, L.rlo, L.rhi, rl, rh);
+    }
+    Hlo[l] = wave_min(rl);
+    Hhi[l] = wave_max(rh);
+  }
+  double sA = 0.0, sB = 0.0, sC = 0.0;
+  GSrc<R> G;
+  G.gc = gc;
+  G.nb = nbins;
+  G.kcmin = wave_min(on ? L.kc : 0x7fffffff);
+  G.lds = (int64_t)wave_max(on ? L.kc : -0x7fffffff) - G.kcmin <= kFlush;
+  G.buf = gbuf;
+  if (on) {
+    int r = Rmin;
+    while (r <= Rmax) {
+      int end, mode;  // mode: -2 skip, -1 general, l >= 0 fast level l
+      if (any_wide || r < Alo || r > Ahi) {
+        mode = -1;
+        end = (any_wide || r > Ahi) ? Rmax : Alo - 1;
+      } else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
+        // outside the nonzero hull every lane's Gaussian is exactly 0
+        if (Hlo[0] > Hhi[0] || r > Hhi[0]) { mode = -2; end = Ahi; }
+        else if (r < Hlo[0]) { mode = -2; end = Hlo[0] - 1; }
+        else { mode = 0; end = min(Hhi[0], Ahi); }
+      } else if (PROF == XS_LORENTZ) {
+        mode = 0;
+        end = Ahi;
+      } else {
+        // deepest level whose hull holds r
+        int l = 0;
+#pragma unroll
+        for (int q = 0; q < NL; ++q)
+          if (l == q && Hlo[q] <= r && r <= Hhi[q]) l = q + 1;
+        if (l == NL) {
+          mode = -1;
+          end = min(Hhi[NL - 1], Ahi);
+        } else {
+          mode = l;
+          if (Hlo[l] <= Hhi[l] && r < Hlo[l]) end = Hlo[l] - 1;   // up to the next inner hull
+          else end = (l == 0) ? Ahi : Hhi[l - 1];                  // to the end of this hull
+          end = min(end, Ahi);
+        }
+      }
+      if (mode >= 0) {
+        if (PROF == XS_VOIGT && sizeof(R) == 8 && mode == 2) {
+          AdjLine<R> L3 = L;
+          L3.P[0] = pair_d<R>(y, GH::t6[0], GH::w6[0]);
+          L3.P[1] = pair_d<R>(y, GH::t6[1], GH::w6[1]);
+          L3.P[2] = pair_d<R>(y, GH::t6[2], GH::w6[2]);
+          fast_level<R, PROF>(2, L3, G, r, end, sA, sB, sC);
+        } else if (PROF == XS_VOIGT && mode == 0) {
+          AdjLine<R> L1 = L;
+          fast_level<R, PROF>(0, L1, G, r, end, sA, sB, sC);
+        } else if (PROF == XS_VOIGT && mode == 1) {
+          AdjLine<R> L2 = L;
+          L2.P[0] = L.P[1];
+          L2.P[1] = L.P[2];
+          fast_level<R, PROF>(1, L2, G, r, end, sA, sB, sC);
+        } else {
+          fast_level<R, PROF>(0, L, G, r, end, sA, sB, sC);
+        }
+      } else if (mode == -1) {
+        for (int rr = r; rr <= end; ++rr) {
+          if (rr >= L.rlo && rr <= L.rhi) {
+            const double gk = gc[L.kc + rr];
+            general_eval<R, PROF>(L, wide, rr, gk, sA, sB, sC);
+          }
+        }
+      }
+      r = end + 1;
+    }
+  }
+  return Sums3{sA, sB, sC};
+}
+
 // One wave owns 64 consecutive sorted lines (one per lane) and walks all of
 // their windows together in steps of r = k - k_c.  Lanes of a wave hold lines
 // of nearly equal wavenumber and width, so at a given r they need the same
@@ -365,6 +524,7 @@ template <typename R, int PROF>
 __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
   __shared__ double sdt[4][kMaxCond];
   __shared__ double sdp[4][kMaxCond];
+  __shared__ R s_g[4][2 * kFlush];  // per-wave cotangent slices
   const ModelDev& m = a.m;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -411,114 +571,9 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
         inv = sqrt(kLN2) / alpha;
         y = gam * inv;
       }
-      const int64_t kc64 = home_bin(nu, m.nu0, m.dnu);
-      const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc64);
-      AdjLine<R> L;
-      L.kc = (int)kc64;
-      L.rlo = on ? (int)(klo - kc64) : 0x7fffffff;
-      L.rhi = on ? (int)(khi - kc64) : -0x7fffffff;
-      L.ad = m.dnu * inv;
-      L.bd = delta * inv;
-      L.y = y;
-      L.a = (R)L.ad;
-      L.nb = (R)(-L.bd);
-      L.ty2 = (R)(2.0 * y * y);
-      L.fy2 = (R)(4.0 * y * y);
-      bool wide = false;
-      if (PROF == XS_VOIGT) {
-        L.P[0] = pair_d<R>(y, GH::t2[0], GH::w2[0]);
-        L.P[1] = pair_d<R>(y, GH::t4[0], GH::w4[0]);
-        L.P[2] = pair_d<R>(y, GH::t4[1], GH::w4[1]);
-        if (sizeof(R) == 8) {
-          // FP64 levels: 1, 2 and 3 node pairs; pairs of the 3-pair rule are
-          // set when that level is entered.
-        }
-        if (sizeof(R) == 4 && on) {
-          const double xmax = fmax(fabs((double)L.rlo * L.ad - L.bd), fabs((double)L.rhi * L.ad - L.bd));
-          wide = xmax > 1.0e9 || y > 1.0e9;
-        }
-      }
-      // uniform runs along r
-      const int Rmin = wave_min(L.rlo), Rmax = wave_max(L.rhi);
-      const int Alo = wave_max(on ? L.rlo : -0x7fffffff), Ahi = wave_min(on ? L.rhi : 0x7fffffff);
-      const bool any_wide = __ballot(wide) != 0;
-      constexpr int NL = (PROF == XS_VOIGT) ? Levels<R>::n : 1;
-      int Hlo[NL], Hhi[NL];
-#pragma unroll
-      for (int l = 0; l < NL; ++l) {
-        int rl = 0x7fffffff, rh = -0x7fffffff;
-        if (on) {
-          double X;
-          if (PROF == XS_VOIGT) X = sqrt(fmax(Levels<R>::rho[l] * 1.001 - y * y, 0.0));
-          else if (PROF == XS_LORENTZ) X = 0.0;  // one level, no inner region
-          else X = (sizeof(R) == 4) ? sqrt(160.0) : sqrt(1100.0);  // Gaussian: nonzero range
-          r_range(X, L.ad, L.bd, L.rlo, L.rhi, rl, rh);
-        }
-        Hlo[l] = wave_min(rl);
-        Hhi[l] = wave_max(rh);
-      }
-      double sA = 0.0, sB = 0.0, sC = 0.0;
-      const double* gc = a.g + (int64_t)c * m.n_bins;
-      if (on) {
-        int r = Rmin;
-        while (r <= Rmax) {
-          int end, mode;  // mode: -2 skip, -1 general, l >= 0 fast level l
-          if (any_wide || r < Alo || r > Ahi) {
-            mode = -1;
-            end = (any_wide || r > Ahi) ? Rmax : Alo - 1;
-          } else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
-            // outside the nonzero hull every lane's Gaussian is exactly 0
-            if (Hlo[0] > Hhi[0] || r > Hhi[0]) { mode = -2; end = Ahi; }
-            else if (r < Hlo[0]) { mode = -2; end = Hlo[0] - 1; }
-            else { mode = 0; end = min(Hhi[0], Ahi); }
-          } else if (PROF == XS_LORENTZ) {
-            mode = 0;
-            end = Ahi;
-          } else {
-            // deepest level whose hull holds r
-            int l = 0;
-#pragma unroll
-            for (int q = 0; q < NL; ++q)
-              if (l == q && Hlo[q] <= r && r <= Hhi[q]) l = q + 1;
-            if (l == NL) {
-              mode = -1;
-              end = min(Hhi[NL - 1], Ahi);
-            } else {
-              mode = l;
-              if (Hlo[l] <= Hhi[l] && r < Hlo[l]) end = Hlo[l] - 1;   // up to the next inner hull
-              else end = (l == 0) ? Ahi : Hhi[l - 1];                  // to the end of this hull
-              end = min(end, Ahi);
-            }
-          }
-          if (mode >= 0) {
-            if (PROF == XS_VOIGT && sizeof(R) == 8 && mode == 2) {
-              AdjLine<R> L3 = L;
-              L3.P[0] = pair_d<R>(y, GH::t6[0], GH::w6[0]);
-              L3.P[1] = pair_d<R>(y, GH::t6[1], GH::w6[1]);
-              L3.P[2] = pair_d<R>(y, GH::t6[2], GH::w6[2]);
-              fast_level<R, PROF>(2, L3, gc, r, end, sA, sB, sC);
-            } else if (PROF == XS_VOIGT && mode == 0) {
-              AdjLine<R> L1 = L;
-              fast_level<R, PROF>(0, L1, gc, r, end, sA, sB, sC);
-            } else if (PROF == XS_VOIGT && mode == 1) {
-              AdjLine<R> L2 = L;
-              L2.P[0] = L.P[1];
-              L2.P[1] = L.P[2];
-              fast_level<R, PROF>(1, L2, gc, r, end, sA, sB, sC);
-            } else {
-              fast_level<R, PROF>(0, L, gc, r, end, sA, sB, sC);
-            }
-          } else if (mode == -1) {
-            for (int rr = r; rr <= end; ++rr) {
-              if (rr >= L.rlo && rr <= L.rhi) {
-                const double gk = gc[L.kc + rr];
-                general_eval<R, PROF>(L, wide, rr, gk, sA, sB, sC);
-              }
-            }
-          }
-          r = end + 1;
-        }
-      }
+      const Sums3 ws = window_sums<R, PROF>(on, klo, khi, nu, inv, y, a.g + (int64_t)c * m.n_bins, m.nu0, m.dnu,
+                                            m.n_bins, s_g[wave]);
+      const double sA = ws.A, sB = ws.B, sC = ws.C;
       // scale to the unit-area profile and its derivatives
       double A, B, C;
       if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {

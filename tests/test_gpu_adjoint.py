@@ -63,7 +63,7 @@ def test_adjoint_vs_oracle_gradient(prof, prec):
                 assert gv == 0.0 and ov == 0.0
                 continue
             log(f"[adj] prof={prof} prec={prec} cond{c} {name}: gpu={gv:.10e} oracle={ov:.10e}")
-            assert gv == pytest.approx(ov, rel=stol)
+            assert gv == pytest.approx(ov, rel=stol, abs=0)
     vtol = 1e-9 if prec == FP64 else 1e-4
     for k in ref:
         if prof == synth.DOPPLER and k != "d_log_scale":
@@ -107,8 +107,8 @@ def test_adjoint_scalars_by_central_differences():
         r = plan.adjoint(ds, dl, g)
         dT, dP = float(r["dT"][0].item()), float(r["dP"][0].item())
         log(f"[fd] prec={prec} dT adj={dT:.8e} fd={fd_T:.8e}; dP adj={dP:.8e} fd={fd_P:.8e}")
-        assert dT == pytest.approx(fd_T, rel=2e-4)
-        assert dP == pytest.approx(fd_P, rel=2e-4)
+        assert dT == pytest.approx(fd_T, rel=2e-4, abs=0)
+        assert dP == pytest.approx(fd_P, rel=2e-4, abs=0)
         plan.close()
 
 
@@ -128,8 +128,10 @@ def test_autograd_function_backward_is_adjoint():
     g = (2.0 * w * (sigma[0].detach() - target)).reshape(1, -1)
     r = plan.adjoint(ds, P.DeviceLines(dl.upper, dl.lower, dl.einstein_a, gref.detach(), nexp.detach(),
                                        ls.detach()), g)
-    assert torch.allclose(T.grad, r["dT"]) and torch.allclose(Pr.grad, r["dP"])
-    assert torch.allclose(gref.grad, r["d_gamma_ref"].float())
-    assert torch.allclose(ls.grad, r["d_log_scale"].float())
+    # same kernels on both routes: relative agreement only (the gradients are ~1e-30)
+    assert torch.allclose(T.grad, r["dT"], rtol=1e-12, atol=0) and torch.allclose(Pr.grad, r["dP"], rtol=1e-12, atol=0)
+    assert torch.allclose(gref.grad, r["d_gamma_ref"].float(), rtol=1e-6, atol=0)
+    assert torch.allclose(ls.grad, r["d_log_scale"].float(), rtol=1e-6, atol=0)
+    assert T.grad.abs().item() > 0 and gref.grad.abs().max().item() > 0
     log(f"[autograd] dL/dT={T.grad.item():.6e} dL/dP={Pr.grad.item():.6e}")
     plan.close()

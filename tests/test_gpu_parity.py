@@ -42,9 +42,9 @@ def test_partition_functions(prec):
         Q, dQ = Q.cpu().numpy(), dQ.cpu().numpy()
         for c, cond in enumerate(wl.conditions):
             q, dq = oracle.partition(wl.states, wl.population, cond.T, cond.T_vib, cond.T_rot)
-            assert Q[c] == pytest.approx(q, rel=1e-12)
+            assert Q[c] == pytest.approx(q, rel=1e-12, abs=0)
             if wl.population == 0:
-                assert dQ[c] == pytest.approx(dq, rel=1e-12)
+                assert dQ[c] == pytest.approx(dq, rel=1e-12, abs=0)
             else:
                 assert np.isnan(dQ[c])
         log(f"[Q] config{k} Q={Q}")

@@ -55,11 +55,11 @@ def test_Q_geometric_ladder(orc):
     for T in [100.0, 700.0, 3000.0, 20000.0]:
         q = math.exp(-c2 * w / T)
         Q, dQ = orc.partition(st, orc.LTE, T)
-        assert Q == pytest.approx((1 - q ** N) / (1 - q), rel=1e-14)
+        assert Q == pytest.approx((1 - q ** N) / (1 - q), rel=1e-14, abs=0)
         # dQ/dT of the closed form
         dq = q * c2 * w / T ** 2
         dref = (-(N) * q ** (N - 1) * dq * (1 - q) + (1 - q ** N) * dq) / (1 - q) ** 2
-        assert dQ == pytest.approx(dref, rel=1e-12)
+        assert dQ == pytest.approx(dref, rel=1e-12, abs=0)
 
 
 def test_Q_rigid_rotor_high_T(orc):
@@ -72,7 +72,7 @@ def test_Q_rigid_rotor_high_T(orc):
         Q, _ = orc.partition(st, orc.LTE, T)
         t = T / (c2 * B)
         approx = t + 1.0 / 3.0 + 1.0 / (15.0 * t) + 4.0 / (315.0 * t * t)
-        assert Q == pytest.approx(approx, rel=1e-9)
+        assert Q == pytest.approx(approx, rel=1e-9, abs=0)
 
 
 def test_Q_limits(orc):
@@ -81,9 +81,9 @@ def test_Q_limits(orc):
     g = np.concatenate([[3.0], rng.integers(1, 20, 9).astype(float)])
     st = _states(E, g)
     Q0, _ = orc.partition(st, orc.LTE, 1.0)         # T -> 0: ground state only
-    assert Q0 == pytest.approx(3.0, rel=1e-15)
+    assert Q0 == pytest.approx(3.0, rel=1e-15, abs=0)
     Qinf, _ = orc.partition(st, orc.LTE, 1e12)     # T -> inf: total degeneracy
-    assert Qinf == pytest.approx(g.sum(), rel=1e-8)
+    assert Qinf == pytest.approx(g.sum(), rel=1e-8, abs=0)
 
 
 def test_Q_two_temperature_factorises(orc):
@@ -102,11 +102,11 @@ def test_Q_two_temperature_factorises(orc):
         Q, _ = orc.partition(st, orc.NLTE_2T, 0.0, Tv, Tr)
         qv = np.exp(-c2 * evib / Tv).sum()
         qr = ((2 * J + 1.0) * np.exp(-c2 * erot / Tr)).sum()
-        assert Q == pytest.approx(qv * qr, rel=1e-13)
+        assert Q == pytest.approx(qv * qr, rel=1e-13, abs=0)
     # equal temperatures reduce to LTE
     Q2, _ = orc.partition(st, orc.NLTE_2T, 0.0, 1700.0, 1700.0)
     Q1, _ = orc.partition(st, orc.LTE, 1700.0)
-    assert Q2 == pytest.approx(Q1, rel=1e-13)
+    assert Q2 == pytest.approx(Q1, rel=1e-13, abs=0)
 
 
 def test_dQdT_finite_difference(orc):
@@ -115,7 +115,7 @@ def test_dQdT_finite_difference(orc):
         Q, dQ = orc.partition(wl.states, orc.LTE, T)
         h = 1e-4 * T
         fd = (orc.partition(wl.states, orc.LTE, T + h)[0] - orc.partition(wl.states, orc.LTE, T - h)[0]) / (2 * h)
-        assert dQ == pytest.approx(fd, rel=1e-7)
+        assert dQ == pytest.approx(fd, rel=1e-7, abs=0)
 
 
 def _few_lines(n_states=300, n_lines=400, seed=5):
@@ -191,7 +191,7 @@ def test_ground_state_absorption_low_T_limit(orc):
     T = 20.0
     Q, _ = orc.partition(st, orc.LTE, T)
     _, S, _ = orc.intensities(st, ln, orc.ABSORPTION, orc.LTE, T, Q)
-    assert S[0] == pytest.approx(5.0 * 3.0 / (8 * math.pi * c * 2000.0 ** 2), rel=1e-14)
+    assert S[0] == pytest.approx(5.0 * 3.0 / (8 * math.pi * c * 2000.0 ** 2), rel=1e-14, abs=0)
 
 
 def test_log_scale_multiplies(orc):

@@ -27,37 +27,37 @@ def test_voigt_matches_scipy_voigt_profile(orc):
         ref = special.voigt_profile(d, sg, gamma)
         v = orc.profile(orc.VOIGT, d, alpha, gamma)
         if ref > 1e-300:
-            assert v == pytest.approx(ref, rel=2e-12), (d, alpha, gamma)
+            assert v == pytest.approx(ref, rel=2e-12, abs=0), (d, alpha, gamma)
 
 
 def test_gaussian_half_maximum_and_scipy(orc):
     for alpha in [1e-4, 0.013, 0.2]:
         g0 = orc.profile(orc.DOPPLER, 0.0, alpha, 0.0)
-        assert orc.profile(orc.DOPPLER, alpha, alpha, 0.0) == pytest.approx(g0 / 2, rel=1e-14)
-        assert orc.profile(orc.DOPPLER, -alpha, alpha, 0.0) == pytest.approx(g0 / 2, rel=1e-14)
+        assert orc.profile(orc.DOPPLER, alpha, alpha, 0.0) == pytest.approx(g0 / 2, rel=1e-14, abs=0)
+        assert orc.profile(orc.DOPPLER, -alpha, alpha, 0.0) == pytest.approx(g0 / 2, rel=1e-14, abs=0)
         sg = alpha / math.sqrt(2 * LN2)
         for d in [0.0, 0.3 * alpha, 2.7 * alpha]:
             ref = math.exp(-d * d / (2 * sg * sg)) / (sg * math.sqrt(2 * math.pi))
-            assert orc.profile(orc.DOPPLER, d, alpha, 0.0) == pytest.approx(ref, rel=1e-14)
+            assert orc.profile(orc.DOPPLER, d, alpha, 0.0) == pytest.approx(ref, rel=1e-14, abs=0)
 
 
 def test_lorentz_half_maximum_and_cauchy(orc):
     for gamma in [1e-3, 0.05, 2.0]:
         l0 = orc.profile(orc.LORENTZ, 0.0, 0.0, gamma)
-        assert l0 == pytest.approx(1.0 / (math.pi * gamma), rel=1e-15)
-        assert orc.profile(orc.LORENTZ, gamma, 0.0, gamma) == pytest.approx(l0 / 2, rel=1e-15)
+        assert l0 == pytest.approx(1.0 / (math.pi * gamma), rel=1e-15, abs=0)
+        assert orc.profile(orc.LORENTZ, gamma, 0.0, gamma) == pytest.approx(l0 / 2, rel=1e-15, abs=0)
 
 
 def test_voigt_limits(orc):
     alpha, d = 0.02, 0.013
     g = orc.profile(orc.DOPPLER, d, alpha, 0.0)
-    assert orc.profile(orc.VOIGT, d, alpha, 0.0) == pytest.approx(g, rel=1e-13)
-    assert orc.profile(orc.VOIGT, d, alpha, 1e-12) == pytest.approx(g, rel=1e-8)
+    assert orc.profile(orc.VOIGT, d, alpha, 0.0) == pytest.approx(g, rel=1e-13, abs=0)
+    assert orc.profile(orc.VOIGT, d, alpha, 1e-12) == pytest.approx(g, rel=1e-8, abs=0)
     gamma = 0.03
     lor = orc.profile(orc.LORENTZ, d, 0.0, gamma)
-    assert orc.profile(orc.VOIGT, d, 1e-9, gamma) == pytest.approx(lor, rel=1e-10)
+    assert orc.profile(orc.VOIGT, d, 1e-9, gamma) == pytest.approx(lor, rel=1e-10, abs=0)
     # far wing: V -> gamma / (pi d^2)
-    assert orc.profile(orc.VOIGT, 40.0, alpha, gamma) == pytest.approx(gamma / (math.pi * 1600.0), rel=1e-5)
+    assert orc.profile(orc.VOIGT, 40.0, alpha, gamma) == pytest.approx(gamma / (math.pi * 1600.0), rel=1e-5, abs=0)
 
 
 def _quad(orc, prof, alpha, gamma, cut):
@@ -79,16 +79,16 @@ def test_unit_area_with_exact_tails(orc):
     # by the same adaptive quadrature.
     for alpha, cut in [(0.05, 0.12), (0.01, 0.004)]:
         ref = 1.0 - special.erfc(cut * math.sqrt(LN2) / alpha)
-        assert _quad(orc, orc.DOPPLER, alpha, 0.0, cut) == pytest.approx(ref, rel=1e-11)
+        assert _quad(orc, orc.DOPPLER, alpha, 0.0, cut) == pytest.approx(ref, rel=1e-11, abs=0)
     for gamma, cut in [(0.05, 3.0), (0.2, 25.0)]:
         ref = 2 / math.pi * math.atan(cut / gamma)
-        assert _quad(orc, orc.LORENTZ, 0.0, gamma, cut) == pytest.approx(ref, rel=1e-11)
+        assert _quad(orc, orc.LORENTZ, 0.0, gamma, cut) == pytest.approx(ref, rel=1e-11, abs=0)
     from scipy import integrate
     for alpha, gamma, cut in [(0.04, 0.03, 1.0), (0.01, 0.002, 25.0)]:
         sg = alpha / math.sqrt(2 * LN2)
         ref, _ = integrate.quad(lambda x: special.voigt_profile(x, sg, gamma), -cut, cut,
                                 points=[0.0], limit=500, epsabs=1e-14, epsrel=1e-13)
-        assert _quad(orc, orc.VOIGT, alpha, gamma, cut) == pytest.approx(ref, rel=1e-10)
+        assert _quad(orc, orc.VOIGT, alpha, gamma, cut) == pytest.approx(ref, rel=1e-10, abs=0)
 
 
 def test_widths_laws(orc):
@@ -127,7 +127,7 @@ def test_profile_derivatives_finite_difference(orc, prof):
         A, B, C = orc.adjoint_sums(np.array([nu]), np.array([alpha]), np.array([gamma]), prof, grid, 25.0, g)
         d = k * 0.01 - nu
         f = orc.profile(prof, d, alpha, gamma)
-        assert A[0] == pytest.approx(f, rel=1e-14)
+        assert A[0] == pytest.approx(f, rel=1e-14, abs=0)
         sg = alpha / math.sqrt(2 * LN2)
         hs = 1e-5 * sg
         fs = (orc.profile(prof, d, (sg + hs) * math.sqrt(2 * LN2), gamma)

@@ -85,10 +85,10 @@ def test_integral_equals_sum_minus_cutoff_loss(orc):
         # the per-line sampled sums instead where the end effects matter.
         per = [math.fsum(orc.sigma(nu[i:i + 1], S[i:i + 1], alpha[i:i + 1], gamma[i:i + 1], 0, grid, cut)) * grid.dnu
                for i in range(n)]
-        assert lhs == pytest.approx(math.fsum(per), rel=1e-14)
+        assert lhs == pytest.approx(math.fsum(per), rel=1e-14, abs=0)
         if cut >= 1.0:
             ref = math.fsum(S * (1.0 - special.erfc(cut * math.sqrt(LN2) / alpha)))
-            assert lhs == pytest.approx(ref, rel=1e-12)
+            assert lhs == pytest.approx(ref, rel=1e-12, abs=0)
 
 
 def test_lorentz_integral_cutoff_loss(orc):
@@ -101,7 +101,7 @@ def test_lorentz_integral_cutoff_loss(orc):
         sig = orc.sigma(nu, np.array([1.0]), np.array([0.0]), np.array([gamma]), 2, grid, cut)
         s = math.fsum(sig) * grid.dnu
         end = gamma / math.pi / (cut * cut + gamma * gamma) * grid.dnu  # two half-weights
-        assert s - end == pytest.approx(2 / math.pi * math.atan(cut / gamma), rel=1e-8)
+        assert s - end == pytest.approx(2 / math.pi * math.atan(cut / gamma), rel=1e-8, abs=0)
 
 
 def test_superposition_and_permutation(orc):
