@@ -154,7 +154,7 @@ def time_steps(plan, ds, dl, sig, w, target, steps, warmup):
     return (t1 - t0) * 1e3 / max(steps, 1), per
 
 
-def cpu_baseline(wl, lines, cond, n_sample=16000):
+def cpu_baseline(wl, lines, cond, n_sample=40000):
     """The oracle (FP64, OpenMP) on this host: sigma at a random sample of grid
     points of the same workload, all lines; evaluations counted exactly as
     the (line, bin) pairs inside the cut-off."""
