@@ -212,6 +212,45 @@ def batched_48(X, wl, ds, dl, n_lines):
     return out
 
 
+def stream_2t(X, n_lines=50_000_000, n_chunks=5):
+    """Chunk streaming of the two-temperature emission workload (4 (T_vib,
+    T_rot) pairs, Doppler at T_rot, grid 0-30000 cm^-1 step 0.05): chunks held
+    in host memory are uploaded on a copy stream while the previous chunk
+    runs (FP32 form).  Reported with the uploads (PCIe-inclusive) and, for
+    comparison, with the same chunks already resident on the device."""
+    import torch
+    import synth
+    wl = synth.config(5, n_lines=n_lines, n_chunks=n_chunks)
+    sizes = wl.chunk_sizes()
+    chunks = [wl.chunk(j) for j in range(n_chunks)]
+    ds = X.DeviceStates.from_numpy(wl.states)
+    plan = X.Plan(wl.profile, wl.mode, wl.population, X.XS_FP32, wl.grid, wl.conditions, max(sizes),
+                  mass_amu=wl.mass_amu)
+    sig = torch.zeros((len(wl.conditions), wl.grid.n_bins), dtype=torch.float64, device="cuda")
+    st = X.ChunkStreamer(plan, max(sizes))
+    st.run(ds, chunks[:2], sig)
+    t0 = time.perf_counter()
+    n = st.run(ds, chunks, sig)
+    ms_stream = (time.perf_counter() - t0) * 1e3
+    dls = [X.DeviceLines.from_numpy(c) for c in chunks]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j, dl in enumerate(dls):
+        plan.cross_section(ds, dl, out=sig, accumulate=j > 0)
+    torch.cuda.synchronize()
+    ms_res = (time.perf_counter() - t0) * 1e3
+    nbytes = sum(4 * 2 + 4 + (4 if c.gamma_ref is not None else 0) + (4 if c.n_exp is not None else 0)
+                 for c in chunks[:1]) * n
+    out = {"lines": n, "chunks": n_chunks, "conditions": len(wl.conditions),
+           "ms_streamed": round(ms_stream, 2), "ms_resident": round(ms_res, 2),
+           "line_conditions_per_s_streamed": n * len(wl.conditions) / (ms_stream / 1e3),
+           "line_conditions_per_s_resident": n * len(wl.conditions) / (ms_res / 1e3),
+           "upload_bytes": nbytes}
+    log(f"stream 2T: {n} lines, streamed {ms_stream:.1f} ms, resident {ms_res:.1f} ms")
+    plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +338,7 @@ def main():
             ps.close()
         extras["gather_over_scatter_speedup_f32"] = round(extras["scatter_f32"]["profile_pass_ms"] / per32["forward"], 2)
         extras["batched_48"] = batched_48(X, wl, ds, dl, lines.n)
+        extras["stream_2t"] = stream_2t(X)
 
     # roofline of the dominant kernel (events around each launch, same stream)
     fracs = region_fractions(wl, lines, cond)
@@ -341,6 +381,14 @@ def main():
         "forward_evals_per_s": pairs / (per32["forward"] / 1e3),
         "lines_per_s": lines.n / (ms32 / 1e3),
         "adj_over_fwd": round(per32["adjoint"] / per32["forward"], 3),
+        # intensity pass and bucketing (HBM-bound): algorithmic bytes per line =
+        # reads u, l, A, gamma_ref, n_exp (20) + key write (4) + two radix
+        # passes (2 x 16) + sorted records written (nu 8, gamma_ref 4, n_exp 4,
+        # index 4, home bin 4, offset 4, window 8, S~ 4 = 40) = 96 B
+        "prepare_hbm": {"bound": "hbm", "bytes_per_line": 96,
+                        "achieved": round(96 * lines.n / (per32["prepare"] / 1e3) / 1e9, 1),
+                        "peak": 8000.0, "unit": "GB/s",
+                        "frac": round(96 * lines.n / (per32["prepare"] / 1e3) / 8e12, 4)},
         "roofline": rl[dom],
         "roofline_other": rl[other],
         **extras,

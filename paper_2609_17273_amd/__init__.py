@@ -4,4 +4,4 @@ The computation runs in libxsec.so (hand-written HIP kernels behind the C-ABI
 of include/xsec.h); this package is its Python binding.  See ``xsec``.
 """
 from .xsec import *  # noqa: F401,F403
-from .xsec import Plan, DeviceStates, DeviceLines, XsecFunction, XsecError, lib  # noqa: F401
+from .xsec import Plan, DeviceStates, DeviceLines, ChunkStreamer, XsecFunction, XsecError, lib  # noqa: F401

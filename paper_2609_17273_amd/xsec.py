@@ -408,6 +408,82 @@ class Plan:
         xs_plan_sync(self.h)
 
 
+class ChunkStreamer:
+    """Line chunks streamed from host memory into one sigma.
+
+    Chunk j+1 is copied from host memory into a pinned staging buffer and then
+    to the device on a copy stream, while the plan's stream runs chunk j
+    (double buffering); sigma accumulates over the chunks in chunk order, so
+    the result equals that of the chunks resident on the device.  Chunks are
+    objects with numpy arrays upper, lower (int32), einstein_a, gamma_ref,
+    n_exp (float32; gamma_ref / n_exp may be None) and scalars
+    gamma_ref_scalar, n_exp_scalar, as produced by the synthetic generator.
+    The copies are plumbing: every computation runs in the library's kernels.
+    """
+
+    def __init__(self, plan: "Plan", max_chunk_lines: int):
+        import torch
+        self.torch, self.plan, self.cap = torch, plan, int(max_chunk_lines)
+        n = self.cap
+        self.copy_stream = torch.cuda.Stream()  # default priority
+        self.host = [self._buffers(n, pinned=True) for _ in range(2)]
+        self.dev = [self._buffers(n, pinned=False) for _ in range(2)]
+        self.ready = [torch.cuda.Event() for _ in range(2)]      # upload j done
+        self.done = [torch.cuda.Event() for _ in range(2)]       # compute on buffer done
+        self.copied = [torch.cuda.Event() for _ in range(2)]     # pinned buffer free again
+
+    def _buffers(self, n, pinned):
+        t = self.torch
+        kw = dict(pin_memory=True) if pinned else dict(device="cuda")
+        return dict(upper=t.empty(n, dtype=t.int32, **kw), lower=t.empty(n, dtype=t.int32, **kw),
+                    einstein_a=t.empty(n, dtype=t.float32, **kw), gamma_ref=t.empty(n, dtype=t.float32, **kw),
+                    n_exp=t.empty(n, dtype=t.float32, **kw))
+
+    def run(self, states: "DeviceStates", chunks, out, accumulate: bool = False):
+        """Streams every chunk of the iterable through xs_cross_section into
+        out ([n_cond, n_bins] float64); returns the number of lines."""
+        t = self.torch
+        compute = self.plan.stream
+        total = 0
+        for j, ch in enumerate(chunks):
+            b = j & 1
+            n = int(len(ch.upper))
+            if n > self.cap:
+                raise ValueError(f"chunk of {n} lines exceeds the streamer's {self.cap}")
+            h, d = self.host[b], self.dev[b]
+            if j >= 2:
+                self.copied[b].synchronize()          # the pinned buffer's last upload has left it
+            for k in ("upper", "lower", "einstein_a"):
+                h[k][:n].numpy()[:] = getattr(ch, k)
+            has_g = ch.gamma_ref is not None
+            has_n = ch.n_exp is not None
+            if has_g:
+                h["gamma_ref"][:n].numpy()[:] = ch.gamma_ref
+            if has_n:
+                h["n_exp"][:n].numpy()[:] = ch.n_exp
+            with t.cuda.stream(self.copy_stream):
+                if j >= 2:
+                    self.copy_stream.wait_event(self.done[b])  # chunk j-2 no longer reads this buffer
+                for k in ("upper", "lower", "einstein_a"):
+                    d[k][:n].copy_(h[k][:n], non_blocking=True)
+                if has_g:
+                    d["gamma_ref"][:n].copy_(h["gamma_ref"][:n], non_blocking=True)
+                if has_n:
+                    d["n_exp"][:n].copy_(h["n_exp"][:n], non_blocking=True)
+                self.copied[b].record(self.copy_stream)
+                self.ready[b].record(self.copy_stream)
+            compute.wait_event(self.ready[b])
+            dl = DeviceLines(d["upper"][:n], d["lower"][:n], d["einstein_a"][:n],
+                             d["gamma_ref"][:n] if has_g else None, d["n_exp"][:n] if has_n else None,
+                             None, float(ch.gamma_ref_scalar), float(ch.n_exp_scalar))
+            with t.cuda.stream(compute):
+                self.plan.cross_section(states, dl, out=out, accumulate=accumulate or j > 0)
+                self.done[b].record(compute)
+            total += n
+        compute.synchronize()
+        return total
+
+
 def _make_xsec_function():
     import torch
 
