@@ -109,6 +109,8 @@ __device__ __forceinline__ KRange x_range(double X, double a, double b, int64_t 
 // tile (the same formula under a window mask); 2 = general per-chunk path
 // (the core, the Gaussian's zero chunks, lines evaluated in FP64).
 constexpr int kRowSkip = 0, kRowF1 = 1, kRowGeneral = 2, kRowF2 = 3, kRowF1M = 4, kRowF2M = 5;
+// FP64 form only: third uniform formula (three node pairs), plain and masked.
+constexpr int kRowF3 = 6, kRowF3M = 7;
 
 // FP32 form.  The first-formula fields come first (two 16-byte LDS reads);
 // the second formula reads a, nb, jfb and B1, B2.
@@ -291,7 +293,9 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
     r.inv = lp.inv;
     r.y = lp.y;
     r.c0 = lp.c0;
-    auto xr = [&](double rho) { return x_range(sqrt(fmax(rho - y2, 0.0)), a, b, kc, klo, khi); };
+    // the ranges only pick formulas; FP32 with the one-bin margin suffices
+    const float af = (float)a, bf = (float)b, y2f = (float)y2;
+    auto xr = [&](double rho) { return x_range_f(sqrtf(fmaxf((float)rho - y2f, 0.0f)), af, bf, kc, klo, khi); };
     if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
       r.r[0] = x_range(sqrt(1100.0), a, b, kc, klo, khi);
       nz = r.r[0];
@@ -315,6 +319,9 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
   if (gauss) return (inside && nz.lo <= lo && nz.hi >= hi) ? kRowF1 : kRowGeneral;
   if (!meets(lo, hi, n1)) return inside ? kRowF1 : kRowF1M;
   if (can2 && !meets(lo, hi, n2)) return inside ? kRowF2 : kRowF2M;
+  if constexpr (sizeof(Rec) == sizeof(RecD)) {
+    if (PROF == XS_VOIGT && !meets(lo, hi, r.r[2])) return inside ? kRowF3 : kRowF3M;
+  }
   return kRowGeneral;
 }
 
@@ -434,21 +441,26 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
       int cls = kRowSkip;
       const int64_t p = p0 + lane;
       if (p < q1) cls = stage_line<Rec, PROF>(g, cd, p, tlo, thi, ROWB, r);
-      // LDS order: F1 | F1M | F2 | F2M | general
+      // LDS order: F1 | F1M | F2 | F2M | F3 | F3M (FP64) | general
       const unsigned long long b1 = __ballot(cls == kRowF1);
       const unsigned long long b1m = __ballot(cls == kRowF1M);
       const unsigned long long b2 = __ballot(cls == kRowF2);
       const unsigned long long b2m = __ballot(cls == kRowF2M);
+      const unsigned long long b3 = F32 ? 0ull : __ballot(cls == kRowF3);
+      const unsigned long long b3m = F32 ? 0ull : __ballot(cls == kRowF3M);
       const unsigned long long bg = __ballot(cls == kRowGeneral);
       const int e1 = __popcll(b1), e1m = e1 + __popcll(b1m), e2 = e1m + __popcll(b2);
-      const int e2m = e2 + __popcll(b2m), eg = e2m + __popcll(bg);
+      const int e2m = e2 + __popcll(b2m), e3 = e2m + __popcll(b3), e3m = e3 + __popcll(b3m);
+      const int eg = e3m + __popcll(bg);
       if (eg == 0) continue;
       unsigned long long mine = bg;
-      int base = e2m;
+      int base = e3m;
       if (cls == kRowF1) { mine = b1; base = 0; }
       else if (cls == kRowF1M) { mine = b1m; base = e1; }
       else if (cls == kRowF2) { mine = b2; base = e1m; }
       else if (cls == kRowF2M) { mine = b2m; base = e2; }
+      else if (cls == kRowF3) { mine = b3; base = e2m; }
+      else if (cls == kRowF3M) { mine = b3m; base = e3; }
       const int slot = base + __builtin_amdgcn_mbcnt_hi((unsigned)(mine >> 32),
                                                         __builtin_amdgcn_mbcnt_lo((unsigned)mine, 0u));
       __syncthreads();
@@ -533,7 +545,7 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
           second(e2, e2m, std::true_type());
         }
         // ---- general path: per-chunk decisions ----
-        for (int l = e2m; l < eg; ++l) {
+        for (int l = e3m; l < eg; ++l) {
           const RecF& rr = srec[l];
           const float a = rr.a, nb = rr.nb, jf0 = rr.jfb + lane_off;
           const int klo = uni(rr.klo), khi = uni(rr.khi);
@@ -583,7 +595,8 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
         }
       } else {
         // FP64 form: x from the exact difference nu_k - nu_i
-        auto uniform = [&](int l0, int l1, auto masked, auto two) {
+        auto uniform = [&](int l0, int l1, auto masked, auto npairs) {
+          constexpr int NP = decltype(npairs)::value;
           for (int l = l0; l < l1; ++l) {
             const RecD& rr = srec[l];
             const double nu = rr.nu, inv = rr.inv;
@@ -598,25 +611,37 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
 #pragma clang fp contract(off)
               xs[j] = (nuk[j] - nu) * inv;
             }
+            Pair<double> C[3];
+            if (PROF == XS_VOIGT && NP == 3) {
+#pragma unroll
+              for (int q = 0; q < 3; ++q) C[q] = make_pair<double>(rr.c0, rr.y, GH::t6[q], GH::w6[q]);
+            }
 #pragma unroll
             for (int j = 0; j < M; ++j) {
               double t;
+              const double u = xs[j] * xs[j];
               if (PROF == XS_LORENTZ) t = rr.c0 * rcp64(fma(xs[j], xs[j], 1.0));
-              else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) t = rr.c0 * exp2(-(xs[j] * xs[j]));
-              else if (!two) t = pair_term<double>(rr.A, xs[j] * xs[j]);
-              else t = pair2_term(rr.B1, rr.B2, xs[j] * xs[j]);
+              else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) t = rr.c0 * exp2(-u);
+              else if (NP == 1) t = pair_term<double>(rr.A, u);
+              else if (NP == 2) t = pair2_term(rr.B1, rr.B2, u);
+              else t = pair_term<double>(C[0], u) + pair2_term(C[1], C[2], u);
               const int k = my0 + 64 * j;
               if (!masked || (k >= klo && k <= khi)) acc64[j] += t;
             }
           }
         };
-        uniform(0, e1, std::false_type(), std::false_type());
-        uniform(e1, e1m, std::true_type(), std::false_type());
+        using P1 = std::integral_constant<int, 1>;
+        using P2 = std::integral_constant<int, 2>;
+        using P3 = std::integral_constant<int, 3>;
+        uniform(0, e1, std::false_type(), P1());
+        uniform(e1, e1m, std::true_type(), P1());
         if (PROF == XS_VOIGT) {
-          uniform(e1m, e2, std::false_type(), std::true_type());
-          uniform(e2, e2m, std::true_type(), std::true_type());
+          uniform(e1m, e2, std::false_type(), P2());
+          uniform(e2, e2m, std::true_type(), P2());
+          uniform(e2m, e3, std::false_type(), P3());
+          uniform(e3, e3m, std::true_type(), P3());
         }
-        for (int l = e2m; l < eg; ++l) {
+        for (int l = e3m; l < eg; ++l) {
           const RecD& rr = srec[l];
           const double nu = rr.nu, inv = rr.inv;
           const int klo = uni(rr.klo), khi = uni(rr.khi);
