@@ -197,7 +197,7 @@ struct AdjLine {
 
 // Far-region levels of the Voigt adjoint: level l uses the rule with l+1 node
 // pairs where rho = x^2 + y^2 >= kLev[l]; inside the last level the general
-// per-lane path picks more pairs or the Taylor core.
+// per-lane path picks more pairs or the rational approximation.
 template <typename R>
 struct Levels;
 template <>
@@ -211,7 +211,7 @@ struct Levels<double> {
   static constexpr double rho[3] = {9.0e6, 6400.0, 400.0};
 };
 
-// Voigt values for the general path, out of line (Taylor core and up to six
+// Voigt values for the general path, out of line (rational core and up to six
 // node pairs): Re w, Re G and Im w' at (x, y) with the given band.
 template <typename R>
 struct Grad3 {

@@ -1,16 +1,18 @@
 // Profile pass: sigma_k = sum_i S_i f_i(nu_k - nu_i) over each line's cut-off
 // window (Eq. xsec with the cut-off rule of section "Spectral synthesis").
 //
-// k_gather: grid-tile-parallel.  A work item is (condition c, tile t of
-//   tile_bins grid points).  Its candidate lines are the buckets within the
-//   cut-off reach of the tile (lines were counting-sorted by home bin).  Each
-//   pass stages up to 256 candidates: every thread tests one line's exact
-//   window against the tile, the survivors are compacted into LDS with a
-//   wave-level prefix (ballot + mbcnt) and a 4-entry cross-wave scan, and then
-//   every wave evaluates every staged line over its own 64*M consecutive bins
-//   (M consecutive bins per lane), reading the line from LDS as a broadcast.
-//   Accumulation: FP64, or FP32 partial sums flushed to FP64 after each pass.
-//   Persistent mode: a fixed grid pulls items from a device counter.
+// k_gather: grid-tile-parallel.  A work item is one wave on (tile t of
+//   tile_bins grid points, condition c, slice of the tile's candidate lines);
+//   the candidates are the buckets within cut-off reach of the tile (lines
+//   were sorted by home bin).  Each batch of up to 64 candidates is staged one
+//   line per lane (exact window test against the tile, per-line constants,
+//   class of the line for the tile), compacted into LDS grouped by class with
+//   a ballot and mbcnt per class, and evaluated over the tile's bins, lane l
+//   owning bins tlo + 64 j + l.  Lines whose formula is uniform over the tile
+//   run in branch-free loops; the rest take per-chunk decisions.  FP32 partial
+//   sums are flushed to FP64 after each batch.  Tiles split over several items
+//   write FP64 partial rows that k_reduce adds in item order; a persistent
+//   grid pulls items from a device counter.
 // k_scatter: line-parallel comparison: one wave per (line, condition) walks
 //   the window and adds each term into sigma with hardware FP64 atomics.
 #include "k_common.h"
@@ -117,7 +119,7 @@ constexpr int kRowF3 = 6, kRowF3M = 7;
 //   rB: bins that are not far-wing (one node pair) -- for the Gaussian, the
 //       bins where 2^{-x^2} is not zero in FP32; rC, rD: bins with
 //       |z|^2 < 64 and < 36 (outside rC two node pairs suffice, outside rD
-//       three; inside rD the Taylor core).
+//       three; a chunk that meets rD takes the rational approximation).
 struct __attribute__((aligned(16))) RecF {
   float a, nb, jfb, c0;  // x = (jfb + offset of the bin in the tile) a + nb; jfb = tlo - k_c
   Pair<float> A;         // one node pair
