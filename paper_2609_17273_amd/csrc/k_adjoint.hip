@@ -242,7 +242,8 @@ __device__ __forceinline__ void general_eval(const AdjLine<R>& L, bool wide, int
       const R y = (R)L.y;
       const R rho = x * x + y * y;
       int band;
-      if (sizeof(R) == 4) band = rho >= (R)(900.0 * 1.001) ? 1 : (rho >= (R)(64.0 * 1.001) ? 2 : 0);
+      if (sizeof(R) == 4) band = rho >= (R)(900.0 * 1.001) ? 1 : rho >= (R)(64.0 * 1.001) ? 2
+                               : rho >= (R)(36.0 * 1.001) ? 3 : 0;
       else band = rho >= (R)(9.0e6 * 1.001) ? 1 : rho >= (R)(6400.0 * 1.001) ? 2 : rho >= (R)(400.0 * 1.001) ? 3
                 : rho >= (R)(144.0 * 1.001) ? 4 : rho >= (R)(64.0 * 1.001) ? 6 : 0;
       const Grad3<R> v = voigt_grad<R>(x, y, band);
@@ -521,7 +522,7 @@ __device__ __forceinline__ Sums3 window_sums(bool on, int64_t klo, int64_t khi, 
 // formula: the r axis is cut into uniform runs (far-region levels, the
 // general core, masked window ends) decided once per wave.
 template <typename R, int PROF>
-__global__ __launch_bounds__(256) void k_adjoint(AdjArgs a) {
+__global__ __launch_bounds__(256, sizeof(R) == 4 ? 4 : 3) void k_adjoint(AdjArgs a) {
   __shared__ double sdt[4][kMaxCond];
   __shared__ double sdp[4][kMaxCond];
   __shared__ R s_g[4][2 * kFlush];  // per-wave cotangent slices
