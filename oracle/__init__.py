@@ -28,6 +28,8 @@ _CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-shared", 
            "-std=gnu11"]
 
 DOPPLER, GAUSSIAN, LORENTZ, VOIGT = 0, 1, 2, 3
+# bin-integrated forms: the mean of the profile over the bin centred on the point
+BIN_DOPPLER, BIN_GAUSSIAN, BIN_LORENTZ, BIN_VOIGT = 4, 5, 6, 7
 ABSORPTION, EMISSION = 0, 1
 LTE, NLTE_2T = 0, 1
 
@@ -60,6 +62,9 @@ def lib():
         L.or_faddeeva_deriv.argtypes = [d, d, p, p, p, p]
         L.or_profile.argtypes = [i32, d, d, d]
         L.or_profile.restype = d
+        L.or_binned.argtypes = [i32, d, d, d, d]
+        L.or_binned.restype = d
+        L.or_gl_rule.argtypes = [p, p]
         L.or_window_counts.argtypes = [i64, p, d, d, d, i64, p]
         L.or_window_counts.restype = i64
         L.or_sigma.argtypes = [i64, p, p, p, p, i32, d, d, i64, d, i64, p, p]
@@ -106,6 +111,18 @@ def faddeeva_deriv(x: float, y: float):
 
 def profile(kind: int, d: float, alpha: float, gamma: float) -> float:
     return lib().or_profile(int(kind), float(d), float(alpha), float(gamma))
+
+
+def binned(kind: int, d: float, dnu: float, alpha: float, gamma: float) -> float:
+    """Mean of the profile over [d - dnu/2, d + dnu/2] (kind: BIN_* or the sampled kind)."""
+    return lib().or_binned(int(kind), float(d), float(dnu), float(alpha), float(gamma))
+
+
+def gl_rule():
+    """(nodes, weights) of the oracle's 16-point Gauss-Legendre rule on [-1, 1]."""
+    x, w = np.empty(16), np.empty(16)
+    lib().or_gl_rule(_p(x), _p(w))
+    return x, w
 
 
 def partition(states, pop: int, T: float, T_vib: float = 0.0, T_rot: float = 0.0):
@@ -254,6 +271,8 @@ def adjoint(wl, lines, cond, g: np.ndarray, log_scale: Optional[np.ndarray] = No
     """
     if wl.population != LTE:
         raise ValueError("oracle adjoint: LTE only")
+    if wl.profile >= BIN_DOPPLER:
+        raise ValueError("oracle adjoint: sampled profiles only")
     T, P = cond.T, cond.P
     r = run_condition(wl, lines, cond, log_scale=log_scale, with_sigma=False)
     A, B, Cs = adjoint_sums(r.nu, r.alpha, r.gamma, wl.profile, wl.grid, cond.cutoff, g)

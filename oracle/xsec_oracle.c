@@ -16,7 +16,8 @@
  *     points with |nu - nu_fi| <= cutoff (section "Spectral synthesis"), lines
  *     with nu_fi <= 0 discarded;
  *   - profiles of Table (tab:profile): Doppler / Gaussian, Lorentzian, and the
- *     SciPy-convention Voigt (Re of the Faddeeva function);
+ *     SciPy-convention Voigt (Re of the Faddeeva function), sampled at the
+ *     grid points or averaged over the bins centred on them ("binned");
  *   - per-line adjoint sums of sigma against a cotangent dL/dsigma.
  *
  * Everything is the plain definition: sigma_k = sum_i S_i f_i(nu_k - nu_i),
@@ -42,6 +43,11 @@
 #define OR_LN2 0.69314718055994530942
 
 enum { OR_DOPPLER = 0, OR_GAUSSIAN = 1, OR_LORENTZ = 2, OR_VOIGT = 3 };
+/* Bin-integrated forms of the same four profiles (Table tab:profile, "binned"
+ * methods): the mean of the profile over the bin [nu_k - dnu/2, nu_k + dnu/2]
+ * centred on the grid point. */
+enum { OR_BIN_DOPPLER = 4, OR_BIN_GAUSSIAN = 5, OR_BIN_LORENTZ = 6, OR_BIN_VOIGT = 7 };
+static int or_base(int profile) { return profile >= 4 ? profile - 4 : profile; }
 enum { OR_ABSORPTION = 0, OR_EMISSION = 1 };
 enum { OR_LTE = 0, OR_NLTE_2T = 1 };
 
@@ -169,7 +175,7 @@ int or_widths(int64_t nl, const double* nu, const float* gref, const float* nexp
   const double dfac = sqrt(2.0 * OR_KB * T * OR_LN2 / (mass_amu * OR_AMU));
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < nl; ++i) {
-    alpha[i] = (profile == OR_GAUSSIAN) ? hwhm_fixed : (nu[i] / OR_C) * dfac;
+    alpha[i] = (or_base(profile) == OR_GAUSSIAN) ? hwhm_fixed : (nu[i] / OR_C) * dfac;
     double gr = gref ? (double)gref[i] : gref_scalar;
     double ne = nexp ? (double)nexp[i] : nexp_scalar;
     gamma[i] = gr * pow(T_ref / T, ne) * (P / P_ref);
@@ -321,6 +327,119 @@ double or_profile(int profile, double d, double alpha, double gamma) {
   return or_profile1(profile, d, alpha, gamma);
 }
 
+/* ---- Bin-integrated profiles --------------------------------------------- */
+/* fbar = (1/dnu) int_{d - dnu/2}^{d + dnu/2} f(s) ds, d = nu_k - nu_i.
+ * Gaussian (HWHM alpha), with X = sqrt(ln 2) / alpha:
+ *   fbar = (erf(X d_b) - erf(X d_a)) / (2 dnu),
+ *   taken as erfc(X d_a) - erfc(X d_b) when both edges lie right of the line
+ *   centre (and mirrored on the left), so the far wing is no difference of
+ *   numbers near 1.
+ * Lorentzian (HWHM gamma):
+ *   fbar = (atan(d_b/gamma) - atan(d_a/gamma)) / (pi dnu)
+ *        = atan2(gamma dnu, gamma^2 + d_a d_b) / (pi dnu),
+ *   the difference of the two angles written as the argument of
+ *   (gamma + i d_b)(gamma - i d_a), exact and free of cancellation.
+ * Voigt: with z = (s + i gamma)/(sg sqrt 2), ds = sg sqrt 2 dx,
+ *   fbar = (1 / (dnu sqrt pi)) int_{x_a}^{x_b} Re w(x + i y) dx,
+ *   integrated by composite 16-point Gauss-Legendre over pieces no longer than
+ *   a quarter of max(1, |z|) on the piece (w is entire; its scale of
+ *   variation near a point z is about max(1, |z|)), so each piece's rule
+ *   converges far below the FP64 rounding level. */
+#define OR_GL_N 16
+static double or_gl_x[OR_GL_N], or_gl_w[OR_GL_N];
+static int or_gl_ready = 0;
+/* Nodes and weights of the Gauss-Legendre rule on [-1, 1]: the roots of P_16
+ * by Newton's method from the Chebyshev-like start cos(pi (i + 3/4)/(n + 1/2)),
+ * P_n by the three-term recurrence (n P_n = (2n-1) x P_{n-1} - (n-1) P_{n-2}),
+ * w_i = 2 / ((1 - x_i^2) P_n'(x_i)^2). */
+static void or_gl_init(void) {
+  if (or_gl_ready) return;
+#pragma omp critical(or_gl_init)
+  {
+    if (!or_gl_ready) {
+      const int n = OR_GL_N;
+      for (int i = 0; i < n; ++i) {
+        double x = cos(OR_PI * (i + 0.75) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+          double p0 = 1.0, p1 = x;
+          for (int k = 2; k <= n; ++k) {
+            double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+          }
+          dp = n * (x * p1 - p0) / (x * x - 1.0);
+          double dx = p1 / dp;
+          x -= dx;
+          if (fabs(dx) < 1e-17) break;
+        }
+        {
+          double p0 = 1.0, p1 = x;
+          for (int k = 2; k <= n; ++k) {
+            double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+          }
+          dp = n * (x * p1 - p0) / (x * x - 1.0);
+        }
+        or_gl_x[i] = x;
+        or_gl_w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+      }
+      __atomic_store_n(&or_gl_ready, 1, __ATOMIC_RELEASE);
+    }
+  }
+}
+
+void or_gl_rule(double* x, double* w) {
+  or_gl_init();
+  memcpy(x, or_gl_x, sizeof(or_gl_x));
+  memcpy(w, or_gl_w, sizeof(or_gl_w));
+}
+
+/* int_a^b Re w(x + i y) dx, accumulated into acc piece by piece. */
+static void or_re_w_integral(double a, double b, double y, or_sum* acc) {
+  double xn = (a <= 0.0 && b >= 0.0) ? 0.0 : fmin(fabs(a), fabs(b));
+  double scale = fmax(1.0, sqrt(xn * xn + y * y));
+  if (b - a > 0.25 * scale) {
+    double mid = (a < 0.0 && b > 0.0) ? 0.0 : 0.5 * (a + b);
+    or_re_w_integral(a, mid, y, acc);
+    or_re_w_integral(mid, b, y, acc);
+    return;
+  }
+  double c = 0.5 * (a + b), h = 0.5 * (b - a);
+  or_sum s = {0, 0};
+  for (int i = 0; i < OR_GL_N; ++i) {
+    double complex w;
+    or_faddeeva_full(c + h * or_gl_x[i], y, 1, &w, NULL, NULL);
+    or_add(&s, or_gl_w[i] * creal(w));
+  }
+  or_add(acc, h * or_total(&s));
+}
+
+static double or_binned1(int profile, double d, double dnu, double alpha, double gamma) {
+  const double da = d - 0.5 * dnu, db = d + 0.5 * dnu;
+  const int base = or_base(profile);
+  if (base == OR_DOPPLER || base == OR_GAUSSIAN) {
+    const double X = sqrt(OR_LN2) / alpha;
+    const double xa = X * da, xb = X * db;
+    double v;
+    if (xa >= 0.0) v = erfc(xa) - erfc(xb);
+    else if (xb <= 0.0) v = erfc(-xb) - erfc(-xa);
+    else v = erf(xb) - erf(xa);
+    return v / (2.0 * dnu);
+  }
+  if (base == OR_LORENTZ) return atan2(gamma * dnu, gamma * gamma + da * db) / (OR_PI * dnu);
+  const double s2 = alpha / sqrt(2.0 * OR_LN2) * sqrt(2.0);
+  or_sum acc = {0, 0};
+  or_re_w_integral(da / s2, db / s2, gamma / s2, &acc);
+  return or_total(&acc) / (dnu * sqrt(OR_PI));
+}
+
+double or_binned(int profile, double d, double dnu, double alpha, double gamma) {
+  or_mr_init();
+  or_gl_init();
+  return or_binned1(profile, d, dnu, alpha, gamma);
+}
+
 /* Profile value and its derivatives with respect to the Gaussian standard
  * deviation sg = alpha / sqrt(2 ln 2) and to gamma:
  *   Gaussian: dG/dsg = G (d^2/sg^2 - 1) / sg;   dG/dgamma = 0
@@ -400,6 +519,8 @@ static int or_key_cmp(const void* a, const void* b) {
 
 /* sigma_k = sum_i S_i f_i(nu_k - nu_i) over lines with nu_i > 0 and
  * |nu_k - nu_i| <= cut (Eq. xsec, cut-off rule), at the requested bins
+ * (binned profiles: f_i is the bin mean, and the cut-off still tests the bin
+ * centre nu_k)
  * (bins == NULL: all n_bins).  Lines are sorted by nu (library sort) so each
  * bin's candidates are found by binary search; each candidate is then tested
  * with the exact predicate.  Bins are independent: OpenMP over bins. */
@@ -407,6 +528,7 @@ int or_sigma(int64_t nl, const double* nu, const double* S, const double* alpha,
              const double* gamma, int profile, double nu0, double dnu, int64_t n_bins,
              double cut, int64_t n_out, const int64_t* bins, double* out) {
   or_mr_init();
+  or_gl_init();
   or_key* keys = (or_key*)malloc(sizeof(or_key) * (size_t)(nl > 0 ? nl : 1));
   if (!keys) return -2;
   int64_t m = 0;
@@ -430,7 +552,9 @@ int or_sigma(int64_t nl, const double* nu, const double* S, const double* alpha,
       int64_t i = keys[j].i;
       if (!or_in_window(nuk, nu[i], cut)) continue;
       double d = nuk - nu[i];
-      or_add(&acc, S[i] * or_profile1(profile, d, alpha[i], gamma[i]));
+      double f = profile >= 4 ? or_binned1(profile, d, dnu, alpha[i], gamma[i])
+                              : or_profile1(profile, d, alpha[i], gamma[i]);
+      or_add(&acc, S[i] * f);
     }
     out[q] = or_total(&acc);
   }
