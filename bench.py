@@ -212,6 +212,39 @@ def batched_48(X, wl, ds, dl, n_lines):
     return out
 
 
+def binned_voigt(X, wl, ds, dl, n_lines, cfg, sampled_ms):
+    """The binned Voigt profile (bin means, Table tab:profile) on the same 1e7
+    lines and condition: the profile pass alone (after one prepare), FP32 and
+    FP64 forms, in the kernel configuration of the main step, and its cost
+    relative to the sampled Voigt profile pass of the main step."""
+    import torch
+    out = {"lines": n_lines}
+    for prec, name in ((X.XS_FP32, "f32"), (X.XS_FP64, "f64")):
+        p = X.Plan(X.XS_BIN_VOIGT, X.XS_ABSORPTION, X.XS_LTE, prec, wl.grid, wl.conditions, n_lines,
+                   mass_amu=wl.mass_amu)
+        p.set_config(**cfg)
+        sig = torch.empty((1, wl.grid.n_bins), dtype=torch.float64, device="cuda")
+        p.prepare(ds, dl)
+        p.profile(out=sig)
+        pairs = p.stats()["window_pairs"]
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        e0.record()
+        for _ in range(reps):
+            p.profile(out=sig)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"profile_pass_ms": round(ms, 3), "evals_per_s": pairs / (ms / 1e3), "window_pairs": pairs}
+        log(f"binned voigt {name}: {ms:.2f} ms")
+        p.close()
+        del sig
+    out["f32_over_sampled_f32"] = round(out["f32"]["profile_pass_ms"] / sampled_ms, 3)
+    out["fp32_over_fp64_speedup"] = round(out["f64"]["profile_pass_ms"] / out["f32"]["profile_pass_ms"], 3)
+    return out
+
+
 def stream_2t(X, n_lines=50_000_000, n_chunks=5):
     """Chunk streaming of the two-temperature emission workload (4 (T_vib,
     T_rot) pairs, Doppler at T_rot, grid 0-30000 cm^-1 step 0.05): chunks held
@@ -337,6 +370,7 @@ def main():
             log(f"scatter {name}: {ms:.2f} ms")
             ps.close()
         extras["gather_over_scatter_speedup_f32"] = round(extras["scatter_f32"]["profile_pass_ms"] / per32["forward"], 2)
+        extras["binned_voigt"] = binned_voigt(X, wl, ds, dl, lines.n, cfg, per32["forward"])
         extras["batched_48"] = batched_48(X, wl, ds, dl, lines.n)
         extras["stream_2t"] = stream_2t(X)
 

@@ -51,8 +51,17 @@ typedef enum {
 /* Line profile (Table tab:profile): Doppler (width from T, nu, mass); Gaussian
  * with a user HWHM; Lorentzian (pressure); Voigt in the scipy.special
  * voigt_profile convention (Gaussian standard deviation sg = alpha/sqrt(2 ln2),
- * Lorentzian HWHM gamma), i.e. Re w(z)/(sg sqrt(2 pi)), z = (d + i gamma)/(sg sqrt 2). */
-typedef enum { XS_DOPPLER = 0, XS_GAUSSIAN = 1, XS_LORENTZ = 2, XS_VOIGT = 3 } xs_profile;
+ * Lorentzian HWHM gamma), i.e. Re w(z)/(sg sqrt(2 pi)), z = (d + i gamma)/(sg sqrt 2).
+ * XS_BIN_*: the binned (bin-integrated) methods of the same table: the mean of
+ * the profile over the bin [nu_k - dnu/2, nu_k + dnu/2] centred on each grid
+ * point, i.e. (F(d + dnu/2) - F(d - dnu/2)) / dnu with F the profile's
+ * cumulative distribution; the cut-off still tests the bin centre.  Widths and
+ * parameters as for the sampled kind (XS_BIN_x = XS_x + 4).  Forward only:
+ * the adjoint returns XS_EUNSUPPORTED for them. */
+typedef enum {
+  XS_DOPPLER = 0, XS_GAUSSIAN = 1, XS_LORENTZ = 2, XS_VOIGT = 3,
+  XS_BIN_DOPPLER = 4, XS_BIN_GAUSSIAN = 5, XS_BIN_LORENTZ = 6, XS_BIN_VOIGT = 7
+} xs_profile;
 /* Absorption (Eq. abs intensity lte, Eq. nlte ab 2T) or emission
  * (Eq. ems intensity lte, Eq. nlte em 2T) intensities. */
 typedef enum { XS_ABSORPTION = 0, XS_EMISSION = 1 } xs_mode;
@@ -77,7 +86,7 @@ typedef struct {
   double mass_amu;     /* molecular mass for the Doppler width (> 0 for Doppler/Voigt) */
   double T_ref;        /* reference temperature of gamma_ref, K (> 0; ExoMol: 296) */
   double P_ref;        /* reference pressure of gamma_ref, bar (> 0; 1) */
-  double hwhm_fixed;   /* Gaussian HWHM in cm^-1 for XS_GAUSSIAN (> 0), else ignored */
+  double hwhm_fixed;   /* Gaussian HWHM in cm^-1 for XS_GAUSSIAN, XS_BIN_GAUSSIAN (> 0), else ignored */
 } xs_model;
 
 /* Grid points nu_k = nu0 + k * dnu, k = 0 .. n_bins-1 (cm^-1), the user
@@ -213,7 +222,7 @@ int xs_line_intensities(xs_plan* plan, const xs_states* states, const xs_lines* 
 int xs_cross_section(xs_plan* plan, const xs_states* states, const xs_lines* lines,
                      double* sigma, int32_t accumulate);
 
-/* Adjoint of xs_cross_section (LTE only; XS_EUNSUPPORTED otherwise): given
+/* Adjoint of xs_cross_section (LTE, sampled profiles; XS_EUNSUPPORTED otherwise): given
  * dL_dsigma[n_cond][n_bins] (double, device), writes
  *   dL_dT[n_cond], dL_dP[n_cond]                              (double, device)
  *   dL_dgamma_ref[n], dL_dn_exp[n], dL_dlog_scale[n]           (double, device,

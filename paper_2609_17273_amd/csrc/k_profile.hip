@@ -327,6 +327,155 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
   return kRowGeneral;
 }
 
+// Staging for the binned profiles (as stage_line).  Record fields: a = h, the
+// bin width in the profile's unit x; nb, jfb as above; c0 = S / dnu times the
+// profile's normalisation (Gaussian 1/2, Lorentzian 1/pi, Voigt 1/sqrt(pi));
+// y (Voigt).  Ranges, all by the bin's nearest point to the line centre:
+//   Gaussian: rB / r[0] = bins whose mean is not zero in the precision;
+//   Lorentzian: rB / r[0] = bins where the atan series does not hold;
+//   Voigt: FP32 rB, rC, rD = |z|^2 below 900, 64, 36 (1, 2, 3 node pairs
+//   outside them, the rational antiderivative inside rD); FP64 r[0..4] =
+//   below 9e6, 6400, 400, 144, 64.
+// A Voigt line takes a uniform class only where every node term's atan
+// argument is positive and small enough for the series on every bin of that
+// band: with the band's nearest |x| = sqrt(rho - y^2), the denominators
+// y^2 + (x_a -+ s)(x_b -+ s) are at least dmin below.
+template <typename Rec, int PROF>
+__device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, int64_t p, int64_t tlo,
+                              int64_t thi, int rowb, Rec& r) {
+  constexpr int BASE = PROF - 4;
+  const ModelDev& m = g.m;
+  const int2 win = ((const int2*)g.rwin)[(int64_t)cd.cclass * g.max_lines + p];
+  if (win.x > win.y || win.y < tlo || win.x > thi) return kRowSkip;
+  const int kc = g.rkc[p];
+  const int klo = max(win.x, (int)tlo), khi = min(win.y, (int)thi);
+  r.klo = klo;
+  r.khi = khi;
+  r.flag = 0;
+  r.kc = kc;
+  const int lo = (int)tlo, hi = lo + rowb - 1;
+  const bool inside = klo <= lo && khi >= hi;
+  const KRange none = KRange{0x7fffffff, -0x7fffffff}, all = KRange{klo, khi};
+  KRange nz = all, n1 = none, n2 = none, n3 = all;
+  bool can2 = false, gauss = false;
+  // series condition of a band with threshold rho and largest node s
+  auto series_ok = [](double rho, double s, double y, double h, double T) {
+    const double y2 = y * y, xn = sqrt(fmax(rho - y2, 0.0));
+    const double dmin = xn > s ? y2 + (xn - s) * (xn - s) : y2 - 0.25 * h * h;
+    return dmin > 0.0 && y * h <= T * dmin;
+  };
+  if constexpr (sizeof(Rec) == sizeof(RecF)) {
+    const float S = ((const float*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
+    if (S == 0.0f) return kRowSkip;
+    const float nu = (float)g.rnu[p];
+    float inv, y = 0.0f, c0;
+    if (BASE == XS_DOPPLER || BASE == XS_GAUSSIAN) {
+      const float alpha = BASE == XS_GAUSSIAN ? (float)cd.hwhm : nu * (float)cd.dop;
+      inv = (float)0.83255461115769776 * rcp32(alpha);  // sqrt(ln2)/alpha
+      c0 = S * (float)(0.5 / m.dnu);
+    } else {
+      const float gamma = g.rgref[p] * __builtin_amdgcn_exp2f(g.rnexp[p] * (float)(cd.lnTr / kLN2)) *
+                          (float)cd.pfac;
+      if (BASE == XS_LORENTZ) {
+        inv = rcp32(gamma);
+        c0 = S * (float)(1.0 / (kPI * m.dnu));
+      } else {
+        inv = (float)0.83255461115769776 * rcp32(nu * (float)cd.dop);
+        y = gamma * inv;
+        c0 = S * (float)(0.56418958354775628 / m.dnu);  // 1/(sqrt(pi) dnu)
+      }
+    }
+    const float a = (float)m.dnu * inv, b = g.rdel[p] * inv, hh = 0.5f * a;
+    r.a = a;
+    r.nb = -b;
+    r.jfb = (float)(lo - kc);
+    r.c0 = c0;
+    r.y = y;
+    r.rB = none;
+    r.rC = none;
+    r.rD = none;
+    if (BASE == XS_DOPPLER || BASE == XS_GAUSSIAN) {
+      r.rB = x_range_f(10.1f + hh, a, b, kc, klo, khi);  // erfc(10.1) < 1e-45
+      nz = r.rB;
+      gauss = true;
+    } else if (BASE == XS_LORENTZ) {
+      // series where 1 + x_a x_b >= h / 0.1, i.e. |x| >= sqrt(10 h - 1 + hh^2)
+      r.rB = x_range_f(sqrtf(fmaxf(10.0f * a - 1.0f + hh * hh, 0.0f)) * 1.001f, a, b, kc, klo, khi);
+      n1 = r.rB;
+    } else {
+      const float y2 = y * y;
+      auto X = [&](float rho) { return rho > y2 ? sqrtf(rho - y2) + hh : 0.0f; };
+      r.rB = x_range_f(X(900.9f), a, b, kc, klo, khi);
+      r.rC = x_range_f(X(64.064f), a, b, kc, klo, khi);
+      r.rD = x_range_f(X(36.036f), a, b, kc, klo, khi);
+      const float xmax = fmaxf(fabsf((float)(klo - kc) * a - b), fabsf((float)(khi - kc) * a - b)) + hh;
+      if (!(xmax <= 1.0e9f) || !(y <= 1.0e9f)) r.flag = 1;
+      n1 = series_ok(900.0, GH::s2[0], y, a, 0.1) ? r.rB : all;
+      n2 = series_ok(64.0, GH::s4[1], y, a, 0.1) ? r.rC : all;
+      can2 = true;
+    }
+  } else {
+    const double S = ((const double*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
+    if (S == 0.0) return kRowSkip;
+    const double nu = g.rnu[p];
+    const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
+    double inv, y = 0.0, c0;
+    const double gamma = (BASE == XS_LORENTZ || BASE == XS_VOIGT)
+                             ? (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac
+                             : 0.0;
+    if (BASE == XS_DOPPLER || BASE == XS_GAUSSIAN) {
+      const double alpha = BASE == XS_GAUSSIAN ? cd.hwhm : nu * cd.dop;
+      inv = sqrt(kLN2) / alpha;
+      c0 = S * 0.5 / m.dnu;
+    } else if (BASE == XS_LORENTZ) {
+      inv = 1.0 / gamma;
+      c0 = S / (kPI * m.dnu);
+    } else {
+      inv = sqrt(kLN2) / (nu * cd.dop);
+      y = gamma * inv;
+      c0 = S / (sqrt(kPI) * m.dnu);
+    }
+    const double a = m.dnu * inv, b = delta * inv, hh = 0.5 * a;
+    r.nu = nu;
+    r.inv = inv;
+    r.y = y;
+    r.c0 = c0;
+    const float af = (float)a, bf = (float)b;
+    if (BASE == XS_DOPPLER || BASE == XS_GAUSSIAN) {
+      r.r[0] = x_range(27.3 + hh, a, b, kc, klo, khi);  // erfc(27.3) underflows FP64
+      nz = r.r[0];
+      gauss = true;
+    } else if (BASE == XS_LORENTZ) {
+      // series where 1 + x_a x_b >= h / 0.02
+      r.r[0] = x_range(sqrt(fmax(50.0 * a - 1.0 + hh * hh, 0.0)) * 1.001, a, b, kc, klo, khi);
+      n1 = r.r[0];
+    } else {
+      const double y2 = y * y;
+      auto xr = [&](double rho) {
+        return x_range_f(rho > y2 ? (float)(sqrt(rho - y2) + hh) : 0.0f, af, bf, kc, klo, khi);
+      };
+      r.r[0] = xr(9.0e6 * 1.001);
+      r.r[1] = xr(6400.0 * 1.001);
+      r.r[2] = xr(400.0 * 1.001);
+      r.r[3] = xr(144.0 * 1.001);
+      r.r[4] = xr(64.0 * 1.001);
+      n1 = series_ok(9.0e6, GH::s2[0], y, a, 0.02) ? r.r[0] : all;
+      n2 = series_ok(6400.0, GH::s4[1], y, a, 0.02) ? r.r[1] : all;
+      n3 = series_ok(400.0, GH::s6[2], y, a, 0.02) ? r.r[2] : all;
+      can2 = true;
+    }
+  }
+  if (!meets(lo, hi, nz)) return kRowSkip;
+  if (r.flag) return kRowGeneral;
+  if (gauss) return (inside && nz.lo <= lo && nz.hi >= hi) ? kRowF1 : kRowGeneral;
+  if (!meets(lo, hi, n1)) return inside ? kRowF1 : kRowF1M;
+  if (can2 && !meets(lo, hi, n2)) return inside ? kRowF2 : kRowF2M;
+  if constexpr (sizeof(Rec) == sizeof(RecD)) {
+    if (BASE == XS_VOIGT && !meets(lo, hi, n3)) return inside ? kRowF3 : kRowF3M;
+  }
+  return kRowGeneral;
+}
+
 // ---- far-region evaluators ------------------------------------------------
 // The hardware FP64 reciprocal has a relative error below 5e-8 on gfx950
 // (measured over 1e6 arguments spanning 1e-30..1e30); one Newton step
@@ -442,7 +591,10 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
       Rec r;
       int cls = kRowSkip;
       const int64_t p = p0 + lane;
-      if (p < q1) cls = stage_line<Rec, PROF>(g, cd, p, tlo, thi, ROWB, r);
+      if (p < q1) {
+        if constexpr (PROF >= XS_BIN_DOPPLER) cls = stage_line_bin<Rec, PROF>(g, cd, p, tlo, thi, ROWB, r);
+        else cls = stage_line<Rec, PROF>(g, cd, p, tlo, thi, ROWB, r);
+      }
       // LDS order: F1 | F1M | F2 | F2M | F3 | F3M (FP64) | general
       const unsigned long long b1 = __ballot(cls == kRowF1);
       const unsigned long long b1m = __ballot(cls == kRowF1M);
@@ -469,7 +621,138 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
       if (cls != kRowSkip) srec[slot] = r;
       __syncthreads();
 
-      if constexpr (F32) {
+      if constexpr (PROF >= XS_BIN_DOPPLER) {
+        // ---- binned profiles: bin means from the closed-form bin integrals ----
+        constexpr int BASE = PROF - 4;
+        constexpr bool GAU = BASE == XS_DOPPLER || BASE == XS_GAUSSIAN;
+        // x of chunk j, and the bin width h, in the profile's unit
+        auto xof = [&](const Rec& rr, int j) -> Real {
+          if constexpr (F32) {
+            return fmaf(rr.jfb + lane_off + (float)(64 * j), rr.a, rr.nb);
+          } else {
+#pragma clang fp contract(off)
+            return (nuk[j] - rr.nu) * rr.inv;
+          }
+        };
+        auto hof = [&](const Rec& rr) -> Real {
+          if constexpr (F32) return rr.a;
+          else return m.dnu * rr.inv;
+        };
+        auto add = [&](int j, Real v) {
+          if constexpr (F32) acc32[j] += v;
+          else acc64[j] += v;
+        };
+        auto uniform_bin = [&](int l0, int l1, auto masked, auto npairs) {
+          constexpr int NP = decltype(npairs)::value;
+          for (int l = l0; l < l1; ++l) {
+            const Rec& rr = srec[l];
+            const Real h = hof(rr), hh = (Real)0.5 * h, c0 = rr.c0, y = rr.y, y2 = y * y, yh = y * h;
+            int klo = 0, khi = 0;
+            if (masked) {
+              klo = uni(rr.klo);
+              khi = uni(rr.khi);
+            }
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+              const Real x = xof(rr, j);
+              Real t;
+              if constexpr (GAU) t = erf_bin<Real>(x, hh);
+              else if constexpr (BASE == XS_LORENTZ) t = atan_series<Real>(h * rcp_r<Real>(fma(x - hh, x + hh, (Real)1)));
+              else t = vpairs_bin<NP, true, Real>(x - hh, x + hh, yh, y2);
+              const int k = my0 + 64 * j;
+              add(j, (!masked || (k >= klo && k <= khi)) ? c0 * t : (Real)0);
+            }
+          }
+        };
+        using P1 = std::integral_constant<int, 1>;
+        using P2 = std::integral_constant<int, 2>;
+        using P3 = std::integral_constant<int, 3>;
+        uniform_bin(0, e1, std::false_type(), P1());
+        uniform_bin(e1, e1m, std::true_type(), P1());
+        if constexpr (BASE == XS_VOIGT) {
+          uniform_bin(e1m, e2, std::false_type(), P2());
+          uniform_bin(e2, e2m, std::true_type(), P2());
+          if constexpr (!F32) {
+            uniform_bin(e2m, e3, std::false_type(), P3());
+            uniform_bin(e3, e3m, std::true_type(), P3());
+          }
+        }
+        // general path: band per chunk (nearest point of each bin), the exact
+        // angle where the series does not hold
+        for (int l = e3m; l < eg; ++l) {
+          const Rec& rr = srec[l];
+          const Real h = hof(rr), hh = (Real)0.5 * h, c0 = rr.c0, y = rr.y, y2 = y * y, yh = y * h;
+          const int klo = uni(rr.klo), khi = uni(rr.khi);
+          KRange R0, R1, R2, R3, R4;
+          if constexpr (F32) {
+            R0 = KRange{uni(rr.rB.lo), uni(rr.rB.hi)};
+            R1 = KRange{uni(rr.rC.lo), uni(rr.rC.hi)};
+            R2 = KRange{uni(rr.rD.lo), uni(rr.rD.hi)};
+            R3 = R2;
+            R4 = R2;
+          } else {
+            R0 = KRange{uni(rr.r[0].lo), uni(rr.r[0].hi)};
+            R1 = KRange{uni(rr.r[1].lo), uni(rr.r[1].hi)};
+            R2 = KRange{uni(rr.r[2].lo), uni(rr.r[2].hi)};
+            R3 = KRange{uni(rr.r[3].lo), uni(rr.r[3].hi)};
+            R4 = KRange{uni(rr.r[4].lo), uni(rr.r[4].hi)};
+          }
+          const bool flag = F32 && BASE == XS_VOIGT && uni(rr.flag);
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            const int cl = row_lo + 64 * j, ch = cl + 63;
+            if (ch < klo || cl > khi) continue;
+            const bool full = cl >= klo && ch <= khi;
+            const int k = my0 + 64 * j;
+            const Real x = xof(rr, j);
+            Real v;
+            if constexpr (GAU) {
+              if (!meets(cl, ch, R0)) continue;  // every bin mean of the chunk is 0
+              v = erf_bin<Real>(x, hh);
+            } else if constexpr (BASE == XS_LORENTZ) {
+              v = !meets(cl, ch, R0) ? atan_series<Real>(h * rcp_r<Real>(fma(x - hh, x + hh, (Real)1)))
+                                     : lor_bin<Real>(x, hh, h);
+            } else {
+              bool wide = false;
+              if constexpr (F32) {
+                if (flag) {
+                  // |x| or y beyond FP32's safe range: the FP64 evaluator
+                  const double xd = (double)(k - rr.kc) * (double)rr.a + (double)rr.nb;
+                  v = (full || (k >= klo && k <= khi)) ? (Real)voigt_bin_f64(xd, (double)y, 0.5 * (double)h)
+                                                       : (Real)0;
+                  wide = true;
+                }
+              }
+              if (wide) {
+              } else if (!meets(cl, ch, R0)) {
+                v = vpairs_bin<1, false, Real>(x - hh, x + hh, yh, y2);
+              } else if (!meets(cl, ch, R1)) {
+                v = vpairs_bin<2, false, Real>(x - hh, x + hh, yh, y2);
+              } else if (!meets(cl, ch, R2)) {
+                v = vpairs_bin<3, false, Real>(x - hh, x + hh, yh, y2);
+              } else if constexpr (F32) {
+                // a chunk that reaches |z|^2 < 36: the rational antiderivative
+                // on every lane (valid everywhere, so no divergence)
+                v = (Real)voigt_bin_core<24>((double)x, (double)y, 0.5 * (double)h);
+              } else {
+                const double xn = fmax(fabs(x) - hh, 0.0);
+                if (!meets(cl, ch, R3)) v = vpairs_bin<4, false, Real>(x - hh, x + hh, yh, y2);
+                else if (!meets(cl, ch, R4) || fma(xn, xn, y2) >= 64.0)
+                  v = vpairs_bin<6, false, Real>(x - hh, x + hh, yh, y2);
+                else v = voigt_bin_core<40>(x, y, hh);
+              }
+            }
+            add(j, (full || (k >= klo && k <= khi)) ? c0 * v : (Real)0);
+          }
+        }
+        if constexpr (F32) {
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            acc64[j] += (double)acc32[j];
+            acc32[j] = 0.0f;
+          }
+        }
+      } else if constexpr (F32) {
         // x = (k - k_c) a - b, with k - k_c = (tlo - k_c) + (offset in tile):
         // integers, exact in FP32 within a window
         // ---- first formula; then the same under the window mask ----
@@ -818,8 +1101,10 @@ void launch_gather(const ModelDev& m, const Work& w, const Tiling& t, double* si
   if (m.profile == P) gather_dispatch<R, P>(a, M, blocks, s);
   if (m.prec == XS_FP32) {
     XS_P(float, XS_DOPPLER) XS_P(float, XS_GAUSSIAN) XS_P(float, XS_LORENTZ) XS_P(float, XS_VOIGT)
+    XS_P(float, XS_BIN_DOPPLER) XS_P(float, XS_BIN_GAUSSIAN) XS_P(float, XS_BIN_LORENTZ) XS_P(float, XS_BIN_VOIGT)
   } else {
     XS_P(double, XS_DOPPLER) XS_P(double, XS_GAUSSIAN) XS_P(double, XS_LORENTZ) XS_P(double, XS_VOIGT)
+    XS_P(double, XS_BIN_DOPPLER) XS_P(double, XS_BIN_GAUSSIAN) XS_P(double, XS_BIN_LORENTZ) XS_P(double, XS_BIN_VOIGT)
   }
 #undef XS_P
   const int rb = (int)std::min<int64_t>(65536, a.n_ct);
@@ -947,6 +1232,90 @@ __global__ __launch_bounds__(256) void k_scatter(ScatterArgs g) {
   }
 }
 
+// Line-parallel scatter of the binned profiles: one wave per (line,
+// condition), the band chosen per lane by the bin's nearest point.
+template <typename Real, int PROF>
+__global__ __launch_bounds__(256) void k_scatter_bin(ScatterArgs g) {
+  constexpr int BASE = PROF - 4;
+  const ModelDev& m = g.m;
+  const int lane = threadIdx.x & 63;
+  const int64_t nkept = g.off[m.n_buckets];
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int64_t total = nkept * m.n_cond;
+  for (int64_t wi = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); wi < total;
+       wi += nwaves) {
+    const int64_t p = wi / m.n_cond;
+    const int c = (int)(wi % m.n_cond);
+    const CondDev cd = g.cond[c];
+    const double nu = g.rnu[p];
+    int64_t klo, khi;
+    if (!line_window(nu, cd.cut, m.nu0, m.dnu, m.n_bins, klo, khi)) continue;
+    const double S = sizeof(Real) == 4 ? (double)((const float*)g.rS)[(int64_t)cd.slot * g.max_lines + p]
+                                       : ((const double*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
+    if (S == 0.0) continue;
+    const double scale = sizeof(Real) == 4 ? exp(g.sb[cd.slot]) : 1.0;
+    double inv, y = 0.0, c0;
+    if (BASE == XS_DOPPLER || BASE == XS_GAUSSIAN) {
+      inv = sqrt(kLN2) / (BASE == XS_GAUSSIAN ? cd.hwhm : nu * cd.dop);
+      c0 = S * 0.5 / m.dnu;
+    } else {
+      const double gamma = (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac;
+      if (BASE == XS_LORENTZ) {
+        inv = 1.0 / gamma;
+        c0 = S / (kPI * m.dnu);
+      } else {
+        inv = sqrt(kLN2) / (nu * cd.dop);
+        y = gamma * inv;
+        c0 = S / (sqrt(kPI) * m.dnu);
+      }
+    }
+    const double h = m.dnu * inv, hh = 0.5 * h;
+    double* out = g.sigma + (int64_t)c * m.n_bins;
+    if constexpr (sizeof(Real) == 4) {
+      const int64_t kc = home_bin(nu, m.nu0, m.dnu);
+      const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
+      const float a = (float)h, b = (float)(delta * inv), hf = 0.5f * a, yf = (float)y, y2 = yf * yf;
+      const float yh = yf * a, c0f = (float)c0;
+      const bool wide = BASE == XS_VOIGT &&
+                        (fmax(fabs((double)(klo - kc) * a), fabs((double)(khi - kc) * a)) + hh > 1.0e9 ||
+                         y > 1.0e9);
+      for (int64_t k = klo + lane; k <= khi; k += 64) {
+        const float x = fmaf((float)(k - kc), a, -b);
+        float v;
+        if (BASE == XS_DOPPLER || BASE == XS_GAUSSIAN) {
+          v = (fabsf(x) - hf > 10.1f) ? 0.0f : erf_bin<float>(x, hf);
+        } else if (BASE == XS_LORENTZ) {
+          v = lor_bin<float>(x, hf, a);
+        } else if (wide) {
+          v = (float)voigt_bin_f64((double)(k - kc) * (double)a - (double)b, y, (double)hf);
+        } else {
+          const float xn = fmaxf(fabsf(x) - hf, 0.0f), rho = fmaf(xn, xn, y2);
+          if (rho >= 900.0f) v = vpairs_bin<1, false, float>(x - hf, x + hf, yh, y2);
+          else if (rho >= 64.0f) v = vpairs_bin<2, false, float>(x - hf, x + hf, yh, y2);
+          else if (rho >= 36.0f) v = vpairs_bin<3, false, float>(x - hf, x + hf, yh, y2);
+          else v = (float)voigt_bin_core<24>((double)x, y, (double)hf);
+        }
+        v *= c0f;
+        if (v != 0.0f) unsafeAtomicAdd(out + k, scale * (double)v);
+      }
+    } else {
+      for (int64_t k = klo + lane; k <= khi; k += 64) {
+        double x;
+        {
+#pragma clang fp contract(off)
+          x = (nu_of_bin(m.nu0, m.dnu, k) - nu) * inv;
+        }
+        double v;
+        if (BASE == XS_DOPPLER || BASE == XS_GAUSSIAN) v = (fabs(x) - hh > 27.3) ? 0.0 : erf_bin<double>(x, hh);
+        else if (BASE == XS_LORENTZ) v = lor_bin<double>(x, hh, h);
+        else v = voigt_bin_f64(x, y, hh);
+        v *= c0;
+        if (v != 0.0) unsafeAtomicAdd(out + k, v);
+      }
+    }
+  }
+}
+
 __global__ void k_fill(double* p, int64_t n, int accumulate) {
   if (accumulate) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -982,6 +1351,17 @@ void launch_scatter(const ModelDev& m, const Work& w, double* sigma, int accumul
     XS_S(double, XS_DOPPLER) XS_S(double, XS_GAUSSIAN) XS_S(double, XS_LORENTZ) XS_S(double, XS_VOIGT)
   }
 #undef XS_S
+#define XS_SB(R, P)                                                                \
+  if (m.profile == P) {                                                            \
+    hipLaunchKernelGGL((k_scatter_bin<R, P>), dim3(blocks), dim3(256), 0, s, a);   \
+    return;                                                                        \
+  }
+  if (m.prec == XS_FP32) {
+    XS_SB(float, XS_BIN_DOPPLER) XS_SB(float, XS_BIN_GAUSSIAN) XS_SB(float, XS_BIN_LORENTZ) XS_SB(float, XS_BIN_VOIGT)
+  } else {
+    XS_SB(double, XS_BIN_DOPPLER) XS_SB(double, XS_BIN_GAUSSIAN) XS_SB(double, XS_BIN_LORENTZ) XS_SB(double, XS_BIN_VOIGT)
+  }
+#undef XS_SB
 }
 
 }  // namespace xs

@@ -76,17 +76,18 @@ namespace {
 
 int validate_model(const xs_model* m) {
   if (!m) return fail(XS_EINVAL, "model is NULL");
-  if (m->profile < XS_DOPPLER || m->profile > XS_VOIGT) return fail(XS_EINVAL, "model.profile out of range");
+  if (m->profile < XS_DOPPLER || m->profile > XS_BIN_VOIGT) return fail(XS_EINVAL, "model.profile out of range");
+  const int base = base_profile(m->profile);
   if (m->mode < XS_ABSORPTION || m->mode > XS_EMISSION) return fail(XS_EINVAL, "model.mode out of range");
   if (m->population < XS_LTE || m->population > XS_NLTE_2T) return fail(XS_EINVAL, "model.population out of range");
   if (m->precision < XS_FP64 || m->precision > XS_FP32) return fail(XS_EINVAL, "model.precision out of range");
   if (m->algo < XS_GATHER || m->algo > XS_SCATTER) return fail(XS_EINVAL, "model.algo out of range");
-  if ((m->profile == XS_DOPPLER || m->profile == XS_VOIGT) && !(m->mass_amu > 0.0 && finite(m->mass_amu)))
+  if ((base == XS_DOPPLER || base == XS_VOIGT) && !(m->mass_amu > 0.0 && finite(m->mass_amu)))
     return fail(XS_EINVAL, "model.mass_amu must be > 0");
   if (!(m->T_ref > 0.0 && finite(m->T_ref))) return fail(XS_EINVAL, "model.T_ref must be > 0");
   if (!(m->P_ref > 0.0 && finite(m->P_ref))) return fail(XS_EINVAL, "model.P_ref must be > 0");
-  if (m->profile == XS_GAUSSIAN && !(m->hwhm_fixed > 0.0 && finite(m->hwhm_fixed)))
-    return fail(XS_EINVAL, "model.hwhm_fixed must be > 0 for XS_GAUSSIAN");
+  if (base == XS_GAUSSIAN && !(m->hwhm_fixed > 0.0 && finite(m->hwhm_fixed)))
+    return fail(XS_EINVAL, "model.hwhm_fixed must be > 0 for XS_GAUSSIAN / XS_BIN_GAUSSIAN");
   return XS_OK;
 }
 
@@ -107,7 +108,8 @@ int validate_conds(const xs_model* m, const xs_grid* g, int32_t n, const xs_cond
     if (!(q.cutoff > 0.0 && finite(q.cutoff))) return fail(XS_EINVAL, id + "cutoff must be > 0");
     if (q.cutoff / g->dnu > double(1 << 28)) return fail(XS_EINVAL, id + "cutoff / dnu too large");
     if (!(q.P >= 0.0 && finite(q.P))) return fail(XS_EINVAL, id + "P must be >= 0");
-    if (m->profile == XS_LORENTZ && !(q.P > 0.0)) return fail(XS_EINVAL, id + "P must be > 0 for XS_LORENTZ");
+    if (base_profile(m->profile) == XS_LORENTZ && !(q.P > 0.0))
+      return fail(XS_EINVAL, id + "P must be > 0 for XS_LORENTZ / XS_BIN_LORENTZ");
     if (m->population == XS_LTE) {
       if (!(q.T > 0.0 && finite(q.T))) return fail(XS_EINVAL, id + "T must be > 0");
     } else {
@@ -134,7 +136,7 @@ int validate_lines(const xs_plan* p, const xs_lines* l) {
   if (l->n < 0 || l->n > p->max_lines) return fail(XS_EINVAL, "lines.n must be in [0, max_lines]");
   if (l->n > 0 && (!l->upper || !l->lower || !l->einstein_a))
     return fail(XS_EINVAL, "lines.upper / lower / einstein_a is NULL");
-  const int prof = p->model.profile;
+  const int prof = base_profile(p->model.profile);
   if ((prof == XS_LORENTZ || prof == XS_VOIGT)) {
     if (!l->gamma_ref && !(l->gamma_ref_scalar >= 0.0 && finite(l->gamma_ref_scalar)))
       return fail(XS_EINVAL, "lines.gamma_ref_scalar must be >= 0");
@@ -239,7 +241,7 @@ void derive(xs_plan* p) {
     cd.Tr = c.T_rot;
     cd.cut = c.cutoff;
     cd.Tk = (m.population == XS_LTE) ? c.T : c.T_rot;
-    cd.dop = (m.profile == XS_GAUSSIAN || m.profile == XS_LORENTZ)
+    cd.dop = (base_profile(m.profile) == XS_GAUSSIAN || base_profile(m.profile) == XS_LORENTZ)
                  ? 0.0
                  : std::sqrt(2.0 * kKB * cd.Tk * kLN2 / (m.mass_amu * kAMU)) / kC;
     cd.hwhm = m.hwhm_fixed;
@@ -570,6 +572,8 @@ int xs_profile_adjoint(xs_plan* p, const xs_states* st, const xs_lines* ln, cons
   if (!p->prepared) return fail(XS_EINVAL, "xs_profile_adjoint before xs_prepare");
   if (p->model.population != XS_LTE)
     return fail(XS_EUNSUPPORTED, "adjoint: two-temperature populations are not supported");
+  if (p->model.profile >= XS_BIN_DOPPLER)
+    return fail(XS_EUNSUPPORTED, "adjoint: binned profiles are not supported");
   if (!g || !dT || !dP || !dls) return fail(XS_EINVAL, "adjoint: dL_dsigma, dL_dT, dL_dP and dL_dlog_scale are required");
   if (ln->n != p->last_lines_in) return fail(XS_EINVAL, "adjoint: lines differ from the prepared ones");
   launch_adjoint(p->md, p->w, view(st), view(ln), g, dT, dP, dgref, dnexp, dls, ln->n, p->stream);
@@ -583,6 +587,8 @@ int xs_cross_section_adjoint(xs_plan* p, const xs_states* st, const xs_lines* ln
   if ((rc = check_call(p, st, ln))) return rc;
   if (p->model.population != XS_LTE)
     return fail(XS_EUNSUPPORTED, "adjoint: two-temperature populations are not supported");
+  if (p->model.profile >= XS_BIN_DOPPLER)
+    return fail(XS_EUNSUPPORTED, "adjoint: binned profiles are not supported");
   if (!g || !dT || !dP || !dls) return fail(XS_EINVAL, "adjoint: dL_dsigma, dL_dT, dL_dP and dL_dlog_scale are required");
   if ((rc = preprocess(p, st, ln))) return rc;
   launch_adjoint(p->md, p->w, view(st), view(ln), g, dT, dP, dgref, dnexp, dls, ln->n, p->stream);

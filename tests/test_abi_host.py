@@ -105,14 +105,15 @@ def _create(X, model=None, grid=None, conds=None, max_lines=100):
 
 @pytest.mark.parametrize("case", [
     "profile", "mode", "population", "precision", "algo", "mass", "T_ref", "P_ref", "hwhm",
-    "dnu", "nu0", "n_bins", "n_cond", "cutoff", "T", "P", "lorentz_P0", "Tvib", "max_lines"])
+    "dnu", "nu0", "n_bins", "n_cond", "cutoff", "T", "P", "lorentz_P0", "Tvib", "max_lines",
+    "bin_hwhm", "bin_mass", "bin_lorentz_P0", "profile_neg"])
 def test_plan_create_rejects_bad_arguments(case):
     X = _binding()
     nan = float("nan")
     cond = lambda **kw: X.xs_condition(kw.get("T", 1000.0), kw.get("P", 1.0), kw.get("Tv", 1000.0),
                                        kw.get("Tr", 1000.0), kw.get("cut", 25.0))
     args = {
-        "profile": dict(model=_model(X, profile=9)),
+        "profile": dict(model=_model(X, profile=8)),
         "mode": dict(model=_model(X, mode=-1)),
         "population": dict(model=_model(X, population=5)),
         "precision": dict(model=_model(X, precision=2)),
@@ -131,6 +132,10 @@ def test_plan_create_rejects_bad_arguments(case):
         "lorentz_P0": dict(model=_model(X, profile=X.XS_LORENTZ), conds=[cond(P=0.0)]),
         "Tvib": dict(model=_model(X, population=X.XS_NLTE_2T), conds=[cond(Tv=0.0)]),
         "max_lines": dict(max_lines=0),
+        "bin_hwhm": dict(model=_model(X, profile=X.XS_BIN_GAUSSIAN, hwhm_fixed=-1.0)),
+        "bin_mass": dict(model=_model(X, profile=X.XS_BIN_VOIGT, mass_amu=0.0)),
+        "bin_lorentz_P0": dict(model=_model(X, profile=X.XS_BIN_LORENTZ), conds=[cond(P=0.0)]),
+        "profile_neg": dict(model=_model(X, profile=-1)),
     }[case]
     rc, msg = _create(X, **args)
     assert rc == X.XS_EINVAL, (case, rc, msg)
