@@ -358,12 +358,26 @@ __device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, int64_t p,
   const KRange none = KRange{0x7fffffff, -0x7fffffff}, all = KRange{klo, khi};
   KRange nz = all, n1 = none, n2 = none, n3 = all;
   bool can2 = false, gauss = false;
-  // series condition of a band with threshold rho and largest node s
-  auto series_ok = [](double rho, double s, double y, double h, double T) {
-    const double y2 = y * y, xn = sqrt(fmax(rho - y2, 0.0));
-    const double dmin = xn > s ? y2 + (xn - s) * (xn - s) : y2 - 0.25 * h * h;
-    return dmin > 0.0 && y * h <= T * dmin;
+  // Largest atan argument of the row's bins (a bound; huge if the series
+  // cannot apply): Voigt node terms y h / (y^2 + (x_a - s)(x_b - s)) with
+  // nodes up to s, Lorentzian h / (1 + x_a x_b).  xr0, xr1: x at the row's
+  // first and last bin.
+  auto row_t = [&](double xr0, double xr1, double hh, double y, double s) {
+    const double xn = xr0 > 0.0 ? xr0 : (xr1 < 0.0 ? -xr1 : 0.0);  // nearest bin centre
+    const double en = fmax(xn - hh, 0.0);                              // its nearer edge
+    double dmin;
+    if (BASE == XS_LORENTZ) dmin = xn > hh ? 1.0 + en * (en + 2.0 * hh) : 1.0 - hh * hh;
+    else dmin = en > s ? y * y + (en - s) * (en - s) : y * y - hh * hh;
+    const double num = BASE == XS_LORENTZ ? 2.0 * hh : 2.0 * y * hh;
+    return dmin > 0.0 ? num / dmin : 1.0e30;
   };
+  // terms of the atan series for a bound t (relative error t^2/3, t^4/5,
+  // t^8/9 for 1, 2, 4 terms); 0 if t is beyond the series
+  auto terms = [](double t, bool f32) {
+    if (f32) return t <= 3.0e-4 ? 1 : t <= 0.02 ? 2 : t <= 0.1 ? 4 : 0;
+    return t <= 5.0e-8 ? 1 : t <= 2.5e-4 ? 2 : t <= 0.02 ? 4 : 0;
+  };
+  int nt1 = 0, nt2 = 0, nt3 = 0;
   if constexpr (sizeof(Rec) == sizeof(RecF)) {
     const float S = ((const float*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
     if (S == 0.0f) return kRowSkip;
@@ -398,21 +412,27 @@ __device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, int64_t p,
       r.rB = x_range_f(10.1f + hh, a, b, kc, klo, khi);  // erfc(10.1) < 1e-45
       nz = r.rB;
       gauss = true;
-    } else if (BASE == XS_LORENTZ) {
-      // series where 1 + x_a x_b >= h / 0.1, i.e. |x| >= sqrt(10 h - 1 + hh^2)
-      r.rB = x_range_f(sqrtf(fmaxf(10.0f * a - 1.0f + hh * hh, 0.0f)) * 1.001f, a, b, kc, klo, khi);
-      n1 = r.rB;
     } else {
-      const float y2 = y * y;
-      auto X = [&](float rho) { return rho > y2 ? sqrtf(rho - y2) + hh : 0.0f; };
-      r.rB = x_range_f(X(900.9f), a, b, kc, klo, khi);
-      r.rC = x_range_f(X(64.064f), a, b, kc, klo, khi);
-      r.rD = x_range_f(X(36.036f), a, b, kc, klo, khi);
-      const float xmax = fmaxf(fabsf((float)(klo - kc) * a - b), fabsf((float)(khi - kc) * a - b)) + hh;
-      if (!(xmax <= 1.0e9f) || !(y <= 1.0e9f)) r.flag = 1;
-      n1 = series_ok(900.0, GH::s2[0], y, a, 0.1) ? r.rB : all;
-      n2 = series_ok(64.0, GH::s4[1], y, a, 0.1) ? r.rC : all;
-      can2 = true;
+      const double xr0 = (double)(lo - kc) * a - b, xr1 = (double)(hi - kc) * a - b;
+      if (BASE == XS_LORENTZ) {
+        // series where 1 + x_a x_b >= h / 0.1, i.e. |x| >= sqrt(10 h - 1 + hh^2)
+        r.rB = x_range_f(sqrtf(fmaxf(10.0f * a - 1.0f + hh * hh, 0.0f)) * 1.001f, a, b, kc, klo, khi);
+        nt1 = terms(row_t(xr0, xr1, hh, y, 0.0), true);
+        n1 = nt1 ? none : all;
+      } else {
+        const float y2 = y * y;
+        auto X = [&](float rho) { return rho > y2 ? sqrtf(rho - y2) + hh : 0.0f; };
+        r.rB = x_range_f(X(900.9f), a, b, kc, klo, khi);
+        r.rC = x_range_f(X(64.064f), a, b, kc, klo, khi);
+        r.rD = x_range_f(X(36.036f), a, b, kc, klo, khi);
+        const float xmax = fmaxf(fabsf((float)(klo - kc) * a - b), fabsf((float)(khi - kc) * a - b)) + hh;
+        if (!(xmax <= 1.0e9f) || !(y <= 1.0e9f)) r.flag = 1;
+        nt1 = terms(row_t(xr0, xr1, hh, y, GH::s2[0]), true);
+        nt2 = terms(row_t(xr0, xr1, hh, y, GH::s4[1]), true);
+        n1 = nt1 ? r.rB : all;
+        n2 = nt2 ? r.rC : all;
+        can2 = true;
+      }
     }
   } else {
     const double S = ((const double*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
@@ -445,32 +465,43 @@ __device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, int64_t p,
       r.r[0] = x_range(27.3 + hh, a, b, kc, klo, khi);  // erfc(27.3) underflows FP64
       nz = r.r[0];
       gauss = true;
-    } else if (BASE == XS_LORENTZ) {
-      // series where 1 + x_a x_b >= h / 0.02
-      r.r[0] = x_range(sqrt(fmax(50.0 * a - 1.0 + hh * hh, 0.0)) * 1.001, a, b, kc, klo, khi);
-      n1 = r.r[0];
     } else {
-      const double y2 = y * y;
-      auto xr = [&](double rho) {
-        return x_range_f(rho > y2 ? (float)(sqrt(rho - y2) + hh) : 0.0f, af, bf, kc, klo, khi);
-      };
-      r.r[0] = xr(9.0e6 * 1.001);
-      r.r[1] = xr(6400.0 * 1.001);
-      r.r[2] = xr(400.0 * 1.001);
-      r.r[3] = xr(144.0 * 1.001);
-      r.r[4] = xr(64.0 * 1.001);
-      n1 = series_ok(9.0e6, GH::s2[0], y, a, 0.02) ? r.r[0] : all;
-      n2 = series_ok(6400.0, GH::s4[1], y, a, 0.02) ? r.r[1] : all;
-      n3 = series_ok(400.0, GH::s6[2], y, a, 0.02) ? r.r[2] : all;
-      can2 = true;
+      const double xr0 = (double)(lo - kc) * a - b, xr1 = (double)(hi - kc) * a - b;
+      if (BASE == XS_LORENTZ) {
+        // series where 1 + x_a x_b >= h / 0.02
+        r.r[0] = x_range(sqrt(fmax(50.0 * a - 1.0 + hh * hh, 0.0)) * 1.001, a, b, kc, klo, khi);
+        nt1 = terms(row_t(xr0, xr1, hh, y, 0.0), false);
+        n1 = nt1 ? none : all;
+      } else {
+        const double y2 = y * y;
+        auto xr = [&](double rho) {
+          return x_range_f(rho > y2 ? (float)(sqrt(rho - y2) + hh) : 0.0f, af, bf, kc, klo, khi);
+        };
+        r.r[0] = xr(9.0e6 * 1.001);
+        r.r[1] = xr(6400.0 * 1.001);
+        r.r[2] = xr(400.0 * 1.001);
+        r.r[3] = xr(144.0 * 1.001);
+        r.r[4] = xr(64.0 * 1.001);
+        nt1 = terms(row_t(xr0, xr1, hh, y, GH::s2[0]), false);
+        nt2 = terms(row_t(xr0, xr1, hh, y, GH::s4[1]), false);
+        nt3 = terms(row_t(xr0, xr1, hh, y, GH::s6[2]), false);
+        n1 = nt1 ? r.r[0] : all;
+        n2 = nt2 ? r.r[1] : all;
+        n3 = nt3 ? r.r[2] : all;
+        can2 = true;
+      }
     }
   }
   if (!meets(lo, hi, nz)) return kRowSkip;
   if (r.flag) return kRowGeneral;
   if (gauss) return (inside && nz.lo <= lo && nz.hi >= hi) ? kRowF1 : kRowGeneral;
+  // the uniform classes carry their series length in pad0
+  r.pad0 = nt1;
   if (!meets(lo, hi, n1)) return inside ? kRowF1 : kRowF1M;
+  r.pad0 = nt2;
   if (can2 && !meets(lo, hi, n2)) return inside ? kRowF2 : kRowF2M;
   if constexpr (sizeof(Rec) == sizeof(RecD)) {
+    r.pad0 = nt3;
     if (BASE == XS_VOIGT && !meets(lo, hi, n3)) return inside ? kRowF3 : kRowF3M;
   }
   return kRowGeneral;
@@ -642,8 +673,15 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
           if constexpr (F32) acc32[j] += v;
           else acc64[j] += v;
         };
+        // Uniform classes.  With 1 or 2 terms of the atan series, a Voigt
+        // node pair +-s takes one reciprocal: den-+ = P -+ 2 s x with
+        // P = x^2 + (y^2 + s^2 - hh^2), so t+ + t- = 2 y h P / D and
+        // t+ t- = (y h)^2 / D, D = den- den+ = P^2 - 4 s^2 x^2; the series
+        // atan(t+) + atan(t-) = (t+ + t-)(1 - (t+ + t-)^2/3 + t+ t-) + O(t^5).
+        // The Lorentzian likewise: t = h / (x^2 + 1 - hh^2).
         auto uniform_bin = [&](int l0, int l1, auto masked, auto npairs) {
           constexpr int NP = decltype(npairs)::value;
+          const double* tau = gh_tau<NP>();
           for (int l = l0; l < l1; ++l) {
             const Rec& rr = srec[l];
             const Real h = hof(rr), hh = (Real)0.5 * h, c0 = rr.c0, y = rr.y, y2 = y * y, yh = y * h;
@@ -652,16 +690,50 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
               klo = uni(rr.klo);
               khi = uni(rr.khi);
             }
+            const int nt = GAU ? 4 : uni(rr.pad0);
+            auto run = [&](auto nterms) {
+              constexpr int NT = decltype(nterms)::value;
+              Real cp[NP];
 #pragma unroll
-            for (int j = 0; j < M; ++j) {
-              const Real x = xof(rr, j);
-              Real t;
-              if constexpr (GAU) t = erf_bin<Real>(x, hh);
-              else if constexpr (BASE == XS_LORENTZ) t = atan_series<Real>(h * rcp_r<Real>(fma(x - hh, x + hh, (Real)1)));
-              else t = vpairs_bin<NP, true, Real>(x - hh, x + hh, yh, y2);
-              const int k = my0 + 64 * j;
-              add(j, (!masked || (k >= klo && k <= khi)) ? c0 * t : (Real)0);
-            }
+              for (int q = 0; q < NP; ++q) cp[q] = (BASE == XS_LORENTZ) ? fma(-hh, hh, (Real)1) : y2 + ((Real)tau[q] - hh * hh);
+#pragma unroll
+              for (int j = 0; j < M; ++j) {
+                const Real x = xof(rr, j);
+                Real t;
+                if constexpr (GAU) {
+                  t = erf_bin<Real>(x, hh);
+                } else if constexpr (BASE == XS_LORENTZ) {
+                  const Real tl = h * rcp_r<Real>(fma(x, x, cp[0]));
+                  if constexpr (NT == 1) t = tl;
+                  else if constexpr (NT == 2) t = tl * fma(tl * tl, (Real)(-1.0 / 3.0), (Real)1);
+                  else t = atan_series<Real>(tl);
+                } else if constexpr (NT == 4) {
+                  t = vpairs_bin<NP, true, Real>(x - hh, x + hh, yh, y2);
+                } else {
+                  const Real u = x * x;
+                  t = (Real)0;
+#pragma unroll
+                  for (int q = 0; q < NP; ++q) {
+                    const Real P = u + cp[q];
+                    const Real iD = rcp_r<Real>(fma(P, P, u * (Real)(-4.0 * tau[q])));
+                    Real e;
+                    if constexpr (NT == 1) {
+                      e = P * iD;
+                    } else {
+                      const Real A = yh * iD, e1 = (Real)2 * P * A;
+                      e = P * iD * fma(e1 * e1, (Real)(-1.0 / 3.0), (Real)1 + yh * A);
+                    }
+                    t = fma((Real)(gh_w<NP>()[q] / kPI), e, t);
+                  }
+                  t *= (Real)2 * yh;
+                }
+                const int k = my0 + 64 * j;
+                add(j, (!masked || (k >= klo && k <= khi)) ? c0 * t : (Real)0);
+              }
+            };
+            if (nt == 1) run(std::integral_constant<int, 1>());
+            else if (nt == 2) run(std::integral_constant<int, 2>());
+            else run(std::integral_constant<int, 4>());
           }
         };
         using P1 = std::integral_constant<int, 1>;
