@@ -31,7 +31,7 @@ DOPPLER, GAUSSIAN, LORENTZ, VOIGT = 0, 1, 2, 3
 # bin-integrated forms: the mean of the profile over the bin centred on the point
 BIN_DOPPLER, BIN_GAUSSIAN, BIN_LORENTZ, BIN_VOIGT = 4, 5, 6, 7
 ABSORPTION, EMISSION = 0, 1
-LTE, NLTE_2T = 0, 1
+LTE, NLTE_2T, NLTE_DENSITY = 0, 1, 2
 
 
 def build(force: bool = False) -> str:
@@ -54,8 +54,8 @@ def lib():
         L.or_c2.restype = d
         L.or_max_threads.restype = i32
         L.or_constants.argtypes = [p]
-        L.or_partition.argtypes = [i64, p, p, p, p, i32, d, d, d, p, p]
-        L.or_intensities.argtypes = [i64, p, p, p, p, p, p, p, p, i32, i32, d, d, d, d, p, p, p]
+        L.or_partition.argtypes = [i64, p, p, p, p, p, i32, d, d, d, p, p]
+        L.or_intensities.argtypes = [i64, p, p, p, p, p, p, p, p, p, i32, i32, d, d, d, d, p, p, p]
         L.or_dlnS_dT.argtypes = [i64, p, p, p, i32, d, d, d, p]
         L.or_widths.argtypes = [i64, p, p, p, d, d, i32, d, d, d, d, d, d, p, p]
         L.or_faddeeva.argtypes = [d, d, p, p]
@@ -131,8 +131,11 @@ def partition(states, pop: int, T: float, T_vib: float = 0.0, T_rot: float = 0.0
     g = _c(states.g_tot, np.float64)
     v = _c(states.v, np.int32)
     ev = _c(states.e_vib, np.float64)
+    nv = _c(getattr(states, "n_vib", None), np.float64)
+    if pop == NLTE_DENSITY and nv is None:
+        raise ValueError("custom vibronic densities need states.n_vib")
     Q, dQ = C.c_double(), C.c_double()
-    lib().or_partition(E.shape[0], _p(E), _p(g), _p(v), _p(ev), pop, T, T_vib, T_rot,
+    lib().or_partition(E.shape[0], _p(E), _p(g), _p(v), _p(ev), _p(nv), pop, T, T_vib, T_rot,
                        C.byref(Q), C.byref(dQ))
     return Q.value, dQ.value
 
@@ -149,11 +152,14 @@ def intensities(states, lines, mode: int, pop: int, T: float, Q: float, T_vib: f
     g = _c(states.g_tot, np.float64)
     v = _c(states.v, np.int32)
     ev = _c(states.e_vib, np.float64)
+    nv = _c(getattr(states, "n_vib", None), np.float64)
+    if pop == NLTE_DENSITY and nv is None:
+        raise ValueError("custom vibronic densities need states.n_vib")
     nu = np.empty(n)
     S = np.empty(n)
     keep = np.empty(n, np.int8)
-    lib().or_intensities(n, _p(up), _p(lo), _p(A), _p(ls), _p(E), _p(g), _p(v), _p(ev), mode,
-                         pop, T, T_vib, T_rot, Q, _p(nu), _p(S), _p(keep))
+    lib().or_intensities(n, _p(up), _p(lo), _p(A), _p(ls), _p(E), _p(g), _p(v), _p(ev), _p(nv),
+                         mode, pop, T, T_vib, T_rot, Q, _p(nu), _p(S), _p(keep))
     return nu, S, keep
 
 
@@ -237,8 +243,8 @@ class CondResult:
 
 
 def kinetic_T(wl, cond) -> float:
-    """Temperature of the line widths: T (LTE) or T_rot (two temperatures)."""
-    return cond.T_rot if wl.population == NLTE_2T else cond.T
+    """Temperature of the line widths: T (LTE) or T_rot (non-LTE)."""
+    return cond.T if wl.population == LTE else cond.T_rot
 
 
 def run_condition(wl, lines, cond, bins: Optional[np.ndarray] = None,

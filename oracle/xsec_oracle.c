@@ -8,10 +8,12 @@
  * different published method (modified trapezoidal rule) from the GPU's.
  *
  * What it computes (PyExoCross 2.0, arXiv 2609.17273):
- *   - partition functions: Eq. (pf) for LTE, Eq. (Q nlte 2T) for two temperatures;
+ *   - partition functions: Eq. (pf) for LTE, Eq. (Q nlte 2T) for two temperatures,
+ *     Eq. (Q nlte Nvib) for custom vibronic densities;
  *   - line intensities: Eqs. (abs intensity lte), (nlte ab 2T),
- *     (ems intensity lte), (nlte em 2T), with E_rot = E - E_vib(v) from
- *     Eqs. (Enonlte) and (Erot nonlte);
+ *     (ems intensity lte), (nlte em 2T), (nlte ab pop density),
+ *     (nlte em pop density), with E_rot = E - E_vib(v) from Eqs. (Enonlte)
+ *     and (Erot nonlte);
  *   - cross sections: Eq. (xsec) with unit-area profiles, evaluated only at grid
  *     points with |nu - nu_fi| <= cutoff (section "Spectral synthesis"), lines
  *     with nu_fi <= 0 discarded;
@@ -49,7 +51,7 @@ enum { OR_DOPPLER = 0, OR_GAUSSIAN = 1, OR_LORENTZ = 2, OR_VOIGT = 3 };
 enum { OR_BIN_DOPPLER = 4, OR_BIN_GAUSSIAN = 5, OR_BIN_LORENTZ = 6, OR_BIN_VOIGT = 7 };
 static int or_base(int profile) { return profile >= 4 ? profile - 4 : profile; }
 enum { OR_ABSORPTION = 0, OR_EMISSION = 1 };
-enum { OR_LTE = 0, OR_NLTE_2T = 1 };
+enum { OR_LTE = 0, OR_NLTE_2T = 1, OR_NLTE_DENSITY = 2 };
 
 double or_c2(void) { return OR_H * OR_C / OR_KB; }
 int or_max_threads(void) { return omp_get_max_threads(); }
@@ -71,10 +73,12 @@ static double or_total(const or_sum* a) { return a->s + a->c; }
 /* LTE, Eq. (pf): Q(T) = sum_n g_n exp(-c2 E_n / T), and its T-derivative
  * dQ/dT = sum_n g_n (c2 E_n / T^2) exp(-c2 E_n / T).
  * Two temperatures, Eq. (Q nlte 2T): Q = sum g exp(-c2 Evib(v)/Tv) exp(-c2 Erot/Tr)
- * with Erot = E - Evib(v) (Eq. Erot nonlte).  dQdT is not defined there (NaN). */
+ * with Erot = E - Evib(v) (Eq. Erot nonlte).
+ * Custom vibronic densities, Eq. (Q nlte Nvib): Q = sum g n_vib(v) exp(-c2 Erot/Tr).
+ * dQdT is not defined for the non-LTE forms (NaN). */
 int or_partition(int64_t n, const double* E, const double* g, const int32_t* v,
-                 const double* evib, int pop, double T, double Tv, double Tr,
-                 double* Q, double* dQdT) {
+                 const double* evib, const double* nvib, int pop, double T, double Tv,
+                 double Tr, double* Q, double* dQdT) {
   const double c2 = or_c2();
   or_sum q = {0, 0}, dq = {0, 0};
   for (int64_t i = 0; i < n; ++i) {
@@ -82,10 +86,13 @@ int or_partition(int64_t n, const double* E, const double* g, const int32_t* v,
       double b = exp(-c2 * E[i] / T);
       or_add(&q, g[i] * b);
       or_add(&dq, g[i] * (c2 * E[i] / (T * T)) * b);
-    } else {
+    } else if (pop == OR_NLTE_2T) {
       double ev = evib[v[i]];
       double er = E[i] - ev;
       or_add(&q, g[i] * exp(-c2 * ev / Tv) * exp(-c2 * er / Tr));
+    } else {
+      double er = E[i] - evib[v[i]];
+      or_add(&q, g[i] * nvib[v[i]] * exp(-c2 * er / Tr));
     }
   }
   *Q = or_total(&q);
@@ -104,13 +111,17 @@ int or_partition(int64_t n, const double* E, const double* g, const int32_t* v,
  *   eps = g_u h c A nu / (4 pi) * exp(-c2 E_u / T) / Q(T)
  * Emission, two temperatures (Eq. nlte em 2T):
  *   eps = h c / (4 pi) g_u A nu * exp(-c2 E_u,vib/Tv) exp(-c2 E_u,rot/Tr) / Q(Tv, Tr)
+ * Absorption, custom vibronic densities (Eq. nlte ab pop density):
+ *   I = g_u A / (8 pi c nu^2) * n_vib(v_l) exp(-c2 E_l,rot/Tr) (1 - exp(-c2 nu/Tr)) / Q(Tr)
+ * Emission, custom vibronic densities (Eq. nlte em pop density):
+ *   eps = h c / (4 pi) g_u A nu * n_vib(v_u) exp(-c2 E_u,rot/Tr) / Q(Tr)
  * (1 - exp(-x)) is formed as -expm1(-x).  An optional per-line log scale s_i
  * multiplies S_i by exp(s_i) (the per-line scales of the adjoint). */
 int or_intensities(int64_t nl, const int32_t* up, const int32_t* lo, const float* A,
                    const float* lscale, const double* E, const double* g,
-                   const int32_t* v, const double* evib, int mode, int pop, double T,
-                   double Tv, double Tr, double Q, double* nu_out, double* S_out,
-                   int8_t* keep) {
+                   const int32_t* v, const double* evib, const double* nvib, int mode,
+                   int pop, double T, double Tv, double Tr, double Q, double* nu_out,
+                   double* S_out, int8_t* keep) {
   const double c2 = or_c2();
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < nl; ++i) {
@@ -125,19 +136,25 @@ int or_intensities(int64_t nl, const int32_t* up, const int32_t* lo, const float
       double pre = g[u] * a / (8.0 * OR_PI * OR_C * nu * nu);
       if (pop == OR_LTE) {
         S = pre * exp(-c2 * E[l] / T) * (-expm1(-c2 * nu / T)) / Q;
-      } else {
+      } else if (pop == OR_NLTE_2T) {
         double evu = evib[v[u]], evl = evib[v[l]];
         double nuv = evu - evl, nur = (E[u] - evu) - (E[l] - evl);
         S = pre * exp(-c2 * evl / Tv) * exp(-c2 * (E[l] - evl) / Tr) *
             (-expm1(-c2 * (nuv / Tv + nur / Tr))) / Q;
+      } else {
+        double evl = evib[v[l]];
+        S = pre * nvib[v[l]] * exp(-c2 * (E[l] - evl) / Tr) * (-expm1(-c2 * nu / Tr)) / Q;
       }
     } else {
       double pre = g[u] * OR_H * OR_C * a * nu / (4.0 * OR_PI);
       if (pop == OR_LTE) {
         S = pre * exp(-c2 * E[u] / T) / Q;
-      } else {
+      } else if (pop == OR_NLTE_2T) {
         double evu = evib[v[u]];
         S = pre * exp(-c2 * evu / Tv) * exp(-c2 * (E[u] - evu) / Tr) / Q;
+      } else {
+        double evu = evib[v[u]];
+        S = pre * nvib[v[u]] * exp(-c2 * (E[u] - evu) / Tr) / Q;
       }
     }
     if (lscale) S *= exp((double)lscale[i]);

@@ -27,7 +27,7 @@ import numpy as np
 DOPPLER, GAUSSIAN, LORENTZ, VOIGT = 0, 1, 2, 3
 BIN_DOPPLER, BIN_GAUSSIAN, BIN_LORENTZ, BIN_VOIGT = 4, 5, 6, 7
 ABSORPTION, EMISSION = 0, 1
-LTE, NLTE_2T = 0, 1
+LTE, NLTE_2T, NLTE_DENSITY = 0, 1, 2
 
 
 @dataclass
@@ -35,7 +35,8 @@ class States:
     energy: np.ndarray                 # float64 [n], cm^-1
     g_tot: np.ndarray                  # float64 [n]
     v: Optional[np.ndarray] = None     # int32 [n] vibrational manifold (2T only)
-    e_vib: Optional[np.ndarray] = None  # float64 [n_v] E_vib(v) (2T only)
+    e_vib: Optional[np.ndarray] = None  # float64 [n_v] E_vib(v) (non-LTE only)
+    n_vib: Optional[np.ndarray] = None  # float64 [n_v] vibronic densities (custom-density runs)
 
     @property
     def n(self) -> int:
@@ -280,6 +281,20 @@ def config(k: int, *, n_lines: Optional[int] = None, n_states: Optional[int] = N
                     conditions=list(conditions), profile=profile, mode=mode, population=pop,
                     mass_amu=mass, n_lines=nl, n_chunks=chunks, seed=seed, nu_max=hi,
                     line_kind=kind, _ss=ss)
+
+
+def with_vib_densities(wl: Workload, seed: int = 77) -> Workload:
+    """The two-temperature workload's states and lines under user vibronic
+    densities instead of T_vib: one weight per manifold, 10^U(-3, 0),
+    normalised to sum 1 (the densities' normalisation in the paper's
+    custom-density population model).  Only T_rot of each condition is used."""
+    if wl.states.e_vib is None:
+        raise ValueError("vibronic densities need states with manifolds (workload 5)")
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    w = 10.0 ** rng.uniform(-3.0, 0.0, wl.states.e_vib.shape[0])
+    wl.states.n_vib = w / w.sum()
+    wl.population = NLTE_DENSITY
+    return wl
 
 
 def sample_bins(n_bins: int, n_sample: int, seed: int) -> np.ndarray:
