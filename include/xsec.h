@@ -65,9 +65,13 @@ typedef enum {
 /* Absorption (Eq. abs intensity lte, Eq. nlte ab 2T) or emission
  * (Eq. ems intensity lte, Eq. nlte em 2T) intensities. */
 typedef enum { XS_ABSORPTION = 0, XS_EMISSION = 1 } xs_mode;
-/* LTE Boltzmann populations (Eq. F lte) or the two-temperature populations of
- * Eq. (F nlte 2T) with E = E_vib(v) + E_rot (Eqs. Enonlte, Erot nonlte). */
-typedef enum { XS_LTE = 0, XS_NLTE_2T = 1 } xs_population;
+/* LTE Boltzmann populations (Eq. F lte); the two-temperature populations of
+ * Eq. (F nlte 2T) with E = E_vib(v) + E_rot (Eqs. Enonlte, Erot nonlte),
+ * intensities by Eqs. (nlte ab 2T), (nlte em 2T); or custom vibronic
+ * densities, Eq. (F nlte Nvib): a user weight n_vib(v) per manifold and
+ * rotational levels at T_rot, Q(T_rot) by Eq. (Q nlte Nvib), intensities by
+ * Eqs. (nlte ab pop density), (nlte em pop density). */
+typedef enum { XS_LTE = 0, XS_NLTE_2T = 1, XS_NLTE_DENSITY = 2 } xs_population;
 /* XS_FP64: every step in FP64.  XS_FP32: profile arithmetic in FP32 with
  * intensities stored as S~ = exp(ln S - s_b) in FP32 (s_b = max ln|S| over
  * the chunk, per temperature), FP64 partition functions, window bounds and
@@ -98,7 +102,8 @@ typedef struct {
 } xs_grid;
 
 /* One thermodynamic condition.  LTE uses T (K); two-temperature runs use
- * T_vib and T_rot and take T_rot as the kinetic temperature of the Doppler and
+ * T_vib and T_rot, custom-density runs T_rot only (T and T_vib ignored); both
+ * non-LTE forms take T_rot as the kinetic temperature of the Doppler and
  * pressure widths (section on LTE/non-LTE comparison).  P in bar (>= 0;
  * > 0 for Lorentzian).  cutoff: line-wing cut-off in cm^-1 (> 0): grid point k
  * receives line i iff |nu_k - nu_i| <= cutoff, both sides rounded in FP64. */
@@ -107,9 +112,12 @@ typedef struct {
 } xs_condition;
 
 /* States (Table tab:exomolstates, compulsory part): term values E (cm^-1,
- * FP64) and total degeneracies g_tot (FP64), dense 0-based indices.  Two-
- * temperature runs also need v[n] (manifold index, 0 <= v < n_v) and the
- * table e_vib[n_v] of E_vib(v) (cm^-1). */
+ * FP64) and total degeneracies g_tot (FP64), dense 0-based indices.  Non-LTE
+ * runs also need v[n] (manifold index, 0 <= v < n_v) and the table e_vib[n_v]
+ * of E_vib(v) (cm^-1); custom-density runs also the weights n_vib[n_v]
+ * (relative populations of the manifolds, Eq. Nvib; only their ratios
+ * matter, since Q carries the same weights; a weight that is not > 0 gives
+ * its manifold's states no population).  All arrays are device memory. */
 typedef struct {
   int64_t n;
   const double* energy;
@@ -117,6 +125,7 @@ typedef struct {
   const int32_t* v;        /* NULL for LTE */
   const double* e_vib;     /* NULL for LTE */
   int32_t n_v;
+  const double* n_vib;     /* XS_NLTE_DENSITY only, else ignored */
 } xs_states;
 
 /* Transitions (Table tab:exomoltrans) and broadening (Table tab:exomolbroad):

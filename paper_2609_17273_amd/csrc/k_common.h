@@ -61,13 +61,18 @@ __device__ __forceinline__ int64_t home_bin(double nui, double nu0, double dnu) 
 //     (negative intensity under population inversion)
 //  emission LTE    (Eq. ems intensity lte):  ln(g_u h c A nu / (4 pi)) - c2 E_u / T - ln Q
 //  emission 2T     (Eq. nlte em 2T):         ... - c2 E_u,vib/Tv - c2 E_u,rot/Tr - ln Q
+//  absorption, custom densities (Eq. nlte ab pop density):
+//     ln(g_u A / (8 pi c nu^2)) + ln n_vib(v_l) - c2 E_l,rot/Tr + ln(1 - exp(-c2 nu/Tr)) - ln Q
+//  emission, custom densities (Eq. nlte em pop density):
+//     ln(g_u h c A nu / (4 pi)) + ln n_vib(v_u) - c2 E_u,rot/Tr - ln Q
+//     (a weight that is not > 0 gives ln S = -inf: no intensity)
 // (1 - exp(-x)) is formed as -expm1(-x); a per-line log scale s adds s.
 // ---------------------------------------------------------------------------
 // A line is usable only if its state indices (and, for two temperatures,
 // their manifold indices) are inside the caller's tables.
 __device__ __forceinline__ bool line_indices_ok(const StatesView& st, int32_t u, int32_t l, int pop) {
   if ((uint32_t)u >= (uint64_t)st.n || (uint32_t)l >= (uint64_t)st.n) return false;
-  if (pop == XS_NLTE_2T &&
+  if (pop != XS_LTE &&
       ((uint32_t)st.v[u] >= (uint32_t)st.n_v || (uint32_t)st.v[l] >= (uint32_t)st.n_v))
     return false;
   return true;
@@ -75,6 +80,7 @@ __device__ __forceinline__ bool line_indices_ok(const StatesView& st, int32_t u,
 
 struct LineState {
   double Eu, El, gu, evu, evl;
+  double nvu, nvl;  // vibronic densities of the upper and lower manifolds
 };
 
 __device__ inline double ln_intensity(int mode, int pop, const LineState& ls, double A,
@@ -86,6 +92,9 @@ __device__ inline double ln_intensity(int mode, int pop, const LineState& ls, do
     r = log(ls.gu * A) - log(8.0 * kPI * kC) - 2.0 * log(nu);
     if (pop == XS_LTE) {
       r += -kC2 * ls.El / T + log(-expm1(-kC2 * nu / T));
+    } else if (pop == XS_NLTE_DENSITY) {
+      r += (ls.nvl > 0.0 ? log(ls.nvl) : -INFINITY) - kC2 * (ls.El - ls.evl) / Tr +
+           log(-expm1(-kC2 * nu / Tr));
     } else {
       double nuv = ls.evu - ls.evl;
       double nur = (ls.Eu - ls.evu) - (ls.El - ls.evl);
@@ -98,6 +107,8 @@ __device__ inline double ln_intensity(int mode, int pop, const LineState& ls, do
     r = log(ls.gu * kH * kC * A * nu / (4.0 * kPI));
     if (pop == XS_LTE)
       r += -kC2 * ls.Eu / T;
+    else if (pop == XS_NLTE_DENSITY)
+      r += (ls.nvu > 0.0 ? log(ls.nvu) : -INFINITY) - kC2 * (ls.Eu - ls.evu) / Tr;
     else
       r += -kC2 * ls.evu / Tv - kC2 * (ls.Eu - ls.evu) / Tr;
   }

@@ -39,7 +39,12 @@ __global__ __launch_bounds__(256) void k_partition(ModelDev m, const SlotDev* sl
       const int32_t vi = st.v[i];
       if ((uint32_t)vi < (uint32_t)st.n_v) {  // states with an invalid manifold index are skipped
         const double ev = st.ev[vi];
-        q += st.g[i] * exp(-kC2 * ev / sd.Tv - kC2 * (E - ev) / sd.Tr);
+        if (m.pop == XS_NLTE_2T) {
+          q += st.g[i] * exp(-kC2 * ev / sd.Tv - kC2 * (E - ev) / sd.Tr);
+        } else {  // custom vibronic densities, Eq. (Q nlte Nvib)
+          const double w = st.nv[vi];
+          if (w > 0.0) q += st.g[i] * w * exp(-kC2 * (E - ev) / sd.Tr);
+        }
       }
     }
   }
@@ -99,11 +104,17 @@ __device__ __forceinline__ LineState line_state(const StatesView& st, int32_t u,
   s.Eu = st.E[u];
   s.El = st.E[l];
   s.gu = st.g[u];
-  if (pop == XS_NLTE_2T) {
+  if (pop != XS_LTE) {
     s.evu = st.ev[st.v[u]];
     s.evl = st.ev[st.v[l]];
   } else {
     s.evu = s.evl = 0.0;
+  }
+  if (pop == XS_NLTE_DENSITY) {
+    s.nvu = st.nv[st.v[u]];
+    s.nvl = st.nv[st.v[l]];
+  } else {
+    s.nvu = s.nvl = 1.0;
   }
   return s;
 }

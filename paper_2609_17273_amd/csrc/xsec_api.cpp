@@ -79,7 +79,8 @@ int validate_model(const xs_model* m) {
   if (m->profile < XS_DOPPLER || m->profile > XS_BIN_VOIGT) return fail(XS_EINVAL, "model.profile out of range");
   const int base = base_profile(m->profile);
   if (m->mode < XS_ABSORPTION || m->mode > XS_EMISSION) return fail(XS_EINVAL, "model.mode out of range");
-  if (m->population < XS_LTE || m->population > XS_NLTE_2T) return fail(XS_EINVAL, "model.population out of range");
+  if (m->population < XS_LTE || m->population > XS_NLTE_DENSITY)
+    return fail(XS_EINVAL, "model.population out of range");
   if (m->precision < XS_FP64 || m->precision > XS_FP32) return fail(XS_EINVAL, "model.precision out of range");
   if (m->algo < XS_GATHER || m->algo > XS_SCATTER) return fail(XS_EINVAL, "model.algo out of range");
   if ((base == XS_DOPPLER || base == XS_VOIGT) && !(m->mass_amu > 0.0 && finite(m->mass_amu)))
@@ -113,7 +114,8 @@ int validate_conds(const xs_model* m, const xs_grid* g, int32_t n, const xs_cond
     if (m->population == XS_LTE) {
       if (!(q.T > 0.0 && finite(q.T))) return fail(XS_EINVAL, id + "T must be > 0");
     } else {
-      if (!(q.T_vib > 0.0 && finite(q.T_vib))) return fail(XS_EINVAL, id + "T_vib must be > 0");
+      if (m->population == XS_NLTE_2T && !(q.T_vib > 0.0 && finite(q.T_vib)))
+        return fail(XS_EINVAL, id + "T_vib must be > 0");
       if (!(q.T_rot > 0.0 && finite(q.T_rot))) return fail(XS_EINVAL, id + "T_rot must be > 0");
     }
   }
@@ -124,9 +126,11 @@ int validate_states(const xs_plan* p, const xs_states* s) {
   if (!s) return fail(XS_EINVAL, "states is NULL");
   if (s->n < 1 || s->n > (int64_t(1) << 31) - 1) return fail(XS_EINVAL, "states.n must be in [1, 2^31-1]");
   if (!s->energy || !s->g_tot) return fail(XS_EINVAL, "states.energy / states.g_tot is NULL");
-  if (p->model.population == XS_NLTE_2T) {
-    if (!s->v || !s->e_vib) return fail(XS_EINVAL, "two-temperature runs need states.v and states.e_vib");
+  if (p->model.population != XS_LTE) {
+    if (!s->v || !s->e_vib) return fail(XS_EINVAL, "non-LTE runs need states.v and states.e_vib");
     if (s->n_v < 1) return fail(XS_EINVAL, "states.n_v must be >= 1");
+    if (p->model.population == XS_NLTE_DENSITY && !s->n_vib)
+      return fail(XS_EINVAL, "custom-density runs need states.n_vib");
   }
   return XS_OK;
 }
@@ -166,6 +170,7 @@ StatesView view(const xs_states* s) {
   v.v = s->v;
   v.ev = s->e_vib;
   v.n_v = s->n_v;
+  v.nv = s->n_vib;
   return v;
 }
 
@@ -224,7 +229,7 @@ void derive(xs_plan* p) {
       s.Tr = c.T;
     } else {
       s.T = c.T_rot;
-      s.Tv = c.T_vib;
+      s.Tv = (m.population == XS_NLTE_2T) ? c.T_vib : 0.0;  // unused with densities
       s.Tr = c.T_rot;
     }
     int slot = -1;

@@ -66,6 +66,7 @@ struct StatesView {
   const int32_t* v;
   const double* ev;
   int32_t n_v;
+  const double* nv;  // vibronic densities (custom-density populations)
 };
 struct LinesView {
   int64_t n;

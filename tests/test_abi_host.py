@@ -52,7 +52,7 @@ _STRUCTS = {
                  "hwhm_fixed"],
     "xs_grid": ["nu0", "dnu", "n_bins"],
     "xs_condition": ["T", "P", "T_vib", "T_rot", "cutoff"],
-    "xs_states": ["n", "energy", "g_tot", "v", "e_vib", "n_v"],
+    "xs_states": ["n", "energy", "g_tot", "v", "e_vib", "n_v", "n_vib"],
     "xs_lines": ["n", "upper", "lower", "einstein_a", "gamma_ref", "n_exp", "log_scale",
                  "gamma_ref_scalar", "n_exp_scalar"],
     "xs_config": ["tile_bins", "bucket_bins", "persistent", "waves_per_cu", "chunk_lines"],
@@ -106,7 +106,7 @@ def _create(X, model=None, grid=None, conds=None, max_lines=100):
 @pytest.mark.parametrize("case", [
     "profile", "mode", "population", "precision", "algo", "mass", "T_ref", "P_ref", "hwhm",
     "dnu", "nu0", "n_bins", "n_cond", "cutoff", "T", "P", "lorentz_P0", "Tvib", "max_lines",
-    "bin_hwhm", "bin_mass", "bin_lorentz_P0", "profile_neg"])
+    "bin_hwhm", "bin_mass", "bin_lorentz_P0", "profile_neg", "density_Trot0"])
 def test_plan_create_rejects_bad_arguments(case):
     X = _binding()
     nan = float("nan")
@@ -136,6 +136,7 @@ def test_plan_create_rejects_bad_arguments(case):
         "bin_mass": dict(model=_model(X, profile=X.XS_BIN_VOIGT, mass_amu=0.0)),
         "bin_lorentz_P0": dict(model=_model(X, profile=X.XS_BIN_LORENTZ), conds=[cond(P=0.0)]),
         "profile_neg": dict(model=_model(X, profile=-1)),
+        "density_Trot0": dict(model=_model(X, population=X.XS_NLTE_DENSITY), conds=[cond(Tr=0.0)]),
     }[case]
     rc, msg = _create(X, **args)
     assert rc == X.XS_EINVAL, (case, rc, msg)
