@@ -57,6 +57,7 @@ def lib():
         L.or_partition.argtypes = [i64, p, p, p, p, p, i32, d, d, d, p, p]
         L.or_intensities.argtypes = [i64, p, p, p, p, p, p, p, p, p, i32, i32, d, d, d, d, p, p, p]
         L.or_dlnS_dT.argtypes = [i64, p, p, p, i32, d, d, d, p]
+        L.or_cooling.argtypes = [i64, p, p, p, i64, p, p, i32, p, p, p]
         L.or_widths.argtypes = [i64, p, p, p, d, d, i32, d, d, d, d, d, d, p, p]
         L.or_faddeeva.argtypes = [d, d, p, p]
         L.or_faddeeva_deriv.argtypes = [d, d, p, p, p, p]
@@ -161,6 +162,21 @@ def intensities(states, lines, mode: int, pop: int, T: float, Q: float, T_vib: f
     lib().or_intensities(n, _p(up), _p(lo), _p(A), _p(ls), _p(E), _p(g), _p(v), _p(ev), _p(nv),
                          mode, pop, T, T_vib, T_rot, Q, _p(nu), _p(S), _p(keep))
     return nu, S, keep
+
+
+def cooling(states, lines, T) -> tuple:
+    """(W(T), Q(T)) at the temperatures T (Eq. cf), erg s^-1 molecule^-1 sr^-1."""
+    T = _c(np.atleast_1d(T), np.float64)
+    up = _c(lines.upper, np.int32)
+    lo = _c(lines.lower, np.int32)
+    A = _c(lines.einstein_a, np.float32)
+    E = _c(states.energy, np.float64)
+    g = _c(states.g_tot, np.float64)
+    W = np.empty(T.shape[0])
+    Q = np.empty(T.shape[0])
+    lib().or_cooling(lines.n, _p(up), _p(lo), _p(A), E.shape[0], _p(E), _p(g), T.shape[0], _p(T),
+                     _p(W), _p(Q))
+    return W, Q
 
 
 def dlnS_dT(states, lines, mode: int, T: float, Q: float, dQdT: float) -> np.ndarray:

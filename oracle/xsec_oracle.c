@@ -20,6 +20,7 @@
  *   - profiles of Table (tab:profile): Doppler / Gaussian, Lorentzian, and the
  *     SciPy-convention Voigt (Re of the Faddeeva function), sampled at the
  *     grid points or averaged over the bins centred on them ("binned");
+ *   - the cooling function, Eq. (cf);
  *   - per-line adjoint sums of sigma against a cotangent dL/dsigma.
  *
  * Everything is the plain definition: sigma_k = sum_i S_i f_i(nu_k - nu_i),
@@ -177,6 +178,32 @@ int or_dlnS_dT(int64_t nl, const int32_t* up, const int32_t* lo, const double* E
       out[i] = c2 * E[lo[i]] / (T * T) - (c2 * nu / (T * T)) / expm1(c2 * nu / T) - dQdT / Q;
     else
       out[i] = c2 * E[up[i]] / (T * T) - dQdT / Q;
+  }
+  return 0;
+}
+
+/* ---- Cooling function --------------------------------------------------- */
+/* Eq. (cf): W(T) = 1/(4 pi Q(T)) sum over transitions of A h c nu g_u exp(-c2 E_u / T),
+ * with Q(T) of Eq. (pf), for each temperature of T[n_T] (erg s^-1 molecule^-1
+ * sr^-1).  Transitions with nu <= 0 are discarded, as everywhere.  The sum runs
+ * over the lines as they come (no grouping), in Neumaier summation; OpenMP over
+ * temperatures. */
+int or_cooling(int64_t nl, const int32_t* up, const int32_t* lo, const float* A, int64_t ns,
+               const double* E, const double* g, int32_t n_T, const double* T, double* W,
+               double* Q_out) {
+  const double c2 = or_c2();
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t j = 0; j < n_T; ++j) {
+    or_sum q = {0, 0}, w = {0, 0};
+    for (int64_t n = 0; n < ns; ++n) or_add(&q, g[n] * exp(-c2 * E[n] / T[j]));
+    for (int64_t i = 0; i < nl; ++i) {
+      double nu = E[up[i]] - E[lo[i]];
+      if (!(nu > 0.0)) continue;
+      or_add(&w, (double)A[i] * OR_H * OR_C * nu * g[up[i]] * exp(-c2 * E[up[i]] / T[j]));
+    }
+    double Q = or_total(&q);
+    W[j] = or_total(&w) / (4.0 * OR_PI * Q);
+    if (Q_out) Q_out[j] = Q;
   }
   return 0;
 }
