@@ -263,6 +263,22 @@ int xs_profile_adjoint(xs_plan* plan, const xs_states* states, const xs_lines* l
                        const double* dL_dsigma, double* dL_dT, double* dL_dP,
                        double* dL_dgamma_ref, double* dL_dn_exp, double* dL_dlog_scale);
 
+/* Cooling function, Eq. (cf) (LTE; XS_EUNSUPPORTED otherwise):
+ *   W(T_j) = 1/(4 pi Q(T_j)) sum over lines of A h c nu g_u exp(-c2 E_u / T_j)
+ * in erg s^-1 molecule^-1 sr^-1, with Q(T_j) of Eq. (pf), for the n_T
+ * temperatures T[n_T] (HOST array, K, each > 0 and finite; 1 <= n_T <= 2^20).
+ * W[n_T] (double, device) receives W; Q[n_T] (double, device, may be NULL)
+ * receives Q.  Lines with nu <= 0 or state indices outside the table add
+ * nothing (counted in xs_stats as for xs_prepare).  FP64 throughout, whatever
+ * model.precision; deterministic.  Uses the plan's workspace and stream and
+ * returns once the temperatures are uploaded; it overwrites the records of
+ * the last xs_prepare (xs_profile_pass / xs_profile_adjoint then need a new
+ * xs_prepare).  Requires lines->n <= max_lines.  Errors: XS_EINVAL (bad
+ * arguments, or n_T beyond what the workspace holds: 32 x 1024 x the GPU's
+ * compute units x 2 doubles less the partial sums), XS_EWORKSPACE. */
+int xs_cooling_function(xs_plan* plan, const xs_states* states, const xs_lines* lines,
+                        int32_t n_T, const double* T, double* W, double* Q);
+
 /* Record one xs_cross_section call with these arguments into a HIP graph
  * (no kernel runs during capture); xs_plan_replay launches it on the plan's
  * stream.  The pointers are kept until destroy or the next capture. */

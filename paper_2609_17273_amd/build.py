@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libxsec.so")
-SOURCES = ["k_lines.hip", "k_profile.hip", "k_adjoint.hip", "xsec_api.cpp"]
+SOURCES = ["k_lines.hip", "k_profile.hip", "k_adjoint.hip", "k_cooling.hip", "xsec_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -335,10 +335,11 @@ static void scan_excl(int32_t* a, int64_t n, int32_t* sums, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(256), 0, s, a, n, sums);
 }
 
-void launch_radix_sort(const ModelDev& m, const Work& w, int64_t n, hipStream_t s,
+void launch_radix_sort(const ModelDev& m, const Work& w, int64_t n, int64_t max_key, hipStream_t s,
                        int32_t** sorted_keys, int32_t** sorted_vals) {
+  (void)m;
   int bits = 1;
-  while ((1ll << bits) <= (long long)m.n_buckets) ++bits;
+  while ((1ll << bits) <= (long long)max_key) ++bits;
   const int passes = (bits + 7) / 8;
   const int nblk = (int)((n + kSortBlock - 1) / kSortBlock);
   const int32_t* ik = w.key;

@@ -70,6 +70,7 @@ struct xs_plan {
   hipGraphExec_t gexec = nullptr;
   int64_t last_lines_in = 0;
   bool prepared = false;     // records of an xs_prepare are in the workspace
+  std::vector<double> cf_T;  // temperatures of the last cooling-function call (upload source)
 };
 
 namespace {
@@ -361,7 +362,7 @@ int preprocess(xs_plan* p, const xs_states* st, const xs_lines* ln) {
   launch_partition(p->md, p->w, sv, p->stream);
   launch_lines_pass1(p->md, p->w, sv, lv, p->stream);
   int32_t *sk = nullptr, *svv = nullptr;
-  launch_radix_sort(p->md, p->w, lv.n, p->stream, &sk, &svv);
+  launch_radix_sort(p->md, p->w, lv.n, p->md.n_buckets, p->stream, &sk, &svv);
   launch_offsets_records(p->md, p->w, sv, lv, sk ? sk : p->w.keyA, svv ? svv : p->w.valA, lv.n,
                          p->stream);
   p->last_lines_in = lv.n;
@@ -598,6 +599,32 @@ int xs_cross_section_adjoint(xs_plan* p, const xs_states* st, const xs_lines* ln
   if ((rc = preprocess(p, st, ln))) return rc;
   launch_adjoint(p->md, p->w, view(st), view(ln), g, dT, dP, dgref, dnexp, dls, ln->n, p->stream);
   return hip_check(hipGetLastError(), "adjoint launch");
+}
+
+int xs_cooling_function(xs_plan* p, const xs_states* st, const xs_lines* ln, int32_t n_T,
+                        const double* T, double* W, double* Q) {
+  int rc;
+  if ((rc = check_call(p, st, ln))) return rc;
+  if (p->model.population != XS_LTE)
+    return fail(XS_EUNSUPPORTED, "cooling function: LTE populations only (Eq. cf)");
+  if (n_T < 1 || n_T > (1 << 20)) return fail(XS_EINVAL, "n_T must be in [1, 2^20]");
+  if (!T || !W) return fail(XS_EINVAL, "cooling function: T and W are required");
+  for (int32_t j = 0; j < n_T; ++j)
+    if (!(T[j] > 0.0 && std::isfinite(T[j]))) return fail(XS_EINVAL, "cooling function: temperatures must be > 0");
+  // temperatures and the per-(chunk, temperature) partial sums live in the
+  // gather's partial-row buffer
+  const int64_t need = ((int64_t)n_T + 31) / 32 * 32 + 2 * (int64_t)cooling_chunks(n_T) * n_T;
+  if (need > 2 * p->w.item_target * 1024)
+    return fail(XS_EINVAL, "cooling function: n_T too large for this plan's workspace");
+  p->cf_T.assign(T, T + n_T);
+  if ((rc = hip_check(hipMemcpyAsync(p->w.part, p->cf_T.data(), sizeof(double) * n_T,
+                                     hipMemcpyHostToDevice, p->stream), "cooling temperatures")))
+    return rc;
+  if ((rc = hip_check(hipStreamSynchronize(p->stream), "cooling temperatures sync"))) return rc;
+  launch_cooling(p->md, p->w, view(st), view(ln), p->w.part, n_T, W, Q, p->stream);
+  p->prepared = false;  // the records area now holds the cooling function's runs
+  p->last_lines_in = ln->n;
+  return hip_check(hipGetLastError(), "cooling launch");
 }
 
 int xs_plan_capture(xs_plan* p, const xs_states* st, const xs_lines* ln, double* sigma,

@@ -131,7 +131,9 @@ struct Tiling {
 void launch_partition(const ModelDev& m, const Work& w, const StatesView& st, hipStream_t s);
 void launch_lines_pass1(const ModelDev& m, const Work& w, const StatesView& st,
                         const LinesView& ln, hipStream_t s);
-void launch_radix_sort(const ModelDev& m, const Work& w, int64_t n, hipStream_t s,
+// Stable sort of the int32 keys w.key[0..n) (values 0..max_key) with their
+// positions; returns the sorted keys and positions (ping-pong buffers).
+void launch_radix_sort(const ModelDev& m, const Work& w, int64_t n, int64_t max_key, hipStream_t s,
                        int32_t** sorted_keys, int32_t** sorted_vals);
 void launch_offsets_records(const ModelDev& m, const Work& w, const StatesView& st,
                             const LinesView& ln, const int32_t* skeys, const int32_t* svals,
@@ -148,6 +150,11 @@ void launch_gather(const ModelDev& m, const Work& w, const Tiling& t, double* si
                    int accumulate, hipStream_t s);
 void launch_scatter(const ModelDev& m, const Work& w, double* sigma, int accumulate,
                     int64_t n_lines, hipStream_t s);
+
+// ---- cooling function (k_cooling.hip) ----
+int cooling_chunks(int32_t nT);
+void launch_cooling(const ModelDev& m, const Work& w, const StatesView& st, const LinesView& ln,
+                    const double* T_dev, int32_t nT, double* W, double* Q, hipStream_t s);
 
 // ---- adjoint (k_adjoint.hip) ----
 void launch_adjoint(const ModelDev& m, const Work& w, const StatesView& st, const LinesView& ln,

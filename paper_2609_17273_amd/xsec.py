@@ -92,6 +92,7 @@ SIGNATURES = {
                                            _P, _P, _P]),
     "xs_prepare": (C.c_int, [_P, C.POINTER(xs_states), C.POINTER(xs_lines)]),
     "xs_profile_pass": (C.c_int, [_P, _P, C.c_int32]),
+    "xs_cooling_function": (C.c_int, [_P, C.POINTER(xs_states), C.POINTER(xs_lines), C.c_int32, _P, _P, _P]),
     "xs_profile_adjoint": (C.c_int, [_P, C.POINTER(xs_states), C.POINTER(xs_lines), _P, _P, _P, _P, _P, _P]),
     "xs_plan_capture": (C.c_int, [_P, C.POINTER(xs_states), C.POINTER(xs_lines), _P, C.c_int32]),
     "xs_plan_replay": (C.c_int, [_P]),
@@ -187,6 +188,11 @@ def xs_prepare(plan, states, lines):
 
 def xs_profile_pass(plan, sigma_ptr, accumulate=0):
     return _check(lib().xs_profile_pass(plan, sigma_ptr, accumulate))
+
+
+def xs_cooling_function(plan, states, lines, n_T, T_host_ptr, W_ptr, Q_ptr):
+    return _check(lib().xs_cooling_function(plan, C.byref(states), C.byref(lines), n_T, T_host_ptr,
+                                            W_ptr, Q_ptr))
 
 
 def xs_profile_adjoint(plan, states, lines, g_ptr, dT_ptr, dP_ptr, dgref_ptr, dnexp_ptr, dls_ptr):
@@ -379,6 +385,16 @@ class Plan:
 
     def profile_adjoint(self, states: DeviceStates, lines: DeviceLines, dL_dsigma):
         return self.adjoint(states, lines, dL_dsigma, prepared=True)
+
+    def cooling_function(self, states: DeviceStates, lines: DeviceLines, T):
+        """(W(T), Q(T)) as device tensors for the temperatures T (host sequence)."""
+        t = self.torch
+        Th = np.ascontiguousarray(np.asarray(T, dtype=np.float64).ravel())
+        W = t.empty(Th.shape[0], dtype=t.float64, device="cuda")
+        Q = t.empty_like(W)
+        xs_cooling_function(self.h, states.struct(), lines.struct(), Th.shape[0],
+                            Th.ctypes.data_as(C.c_void_p), W.data_ptr(), Q.data_ptr())
+        return W, Q
 
     def adjoint(self, states: DeviceStates, lines: DeviceLines, dL_dsigma, prepared=False):
         t = self.torch
