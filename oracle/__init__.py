@@ -58,7 +58,7 @@ def lib():
         L.or_intensities.argtypes = [i64, p, p, p, p, p, p, p, p, p, i32, i32, d, d, d, d, p, p, p]
         L.or_dlnS_dT.argtypes = [i64, p, p, p, i32, d, d, d, p]
         L.or_cooling.argtypes = [i64, p, p, p, i64, p, p, i32, p, p, p]
-        L.or_widths.argtypes = [i64, p, p, p, d, d, i32, d, d, d, d, d, d, p, p]
+        L.or_widths.argtypes = [i64, p, p, p, d, d, i32, d, d, d, d, d, d, p, p, p, p]
         L.or_faddeeva.argtypes = [d, d, p, p]
         L.or_faddeeva_deriv.argtypes = [d, d, p, p, p, p]
         L.or_profile.argtypes = [i32, d, d, d]
@@ -189,16 +189,20 @@ def dlnS_dT(states, lines, mode: int, T: float, Q: float, dQdT: float) -> np.nda
 
 
 def widths(nu, lines, prof: int, T: float, P: float, mass_amu: float, T_ref: float = 296.0,
-           P_ref: float = 1.0, hwhm_fixed: float = 0.0):
+           P_ref: float = 1.0, hwhm_fixed: float = 0.0, lifetime: Optional[np.ndarray] = None):
+    """(alpha, gamma) per line; ``lifetime`` (per state, s) adds the upper
+    state's natural width to gamma."""
     n = nu.shape[0]
     nu = _c(nu, np.float64)
     gr = _c(lines.gamma_ref, np.float32)
     ne = _c(lines.n_exp, np.float32)
+    tau = _c(lifetime, np.float64)
+    up = _c(lines.upper, np.int32) if lifetime is not None else None
     alpha = np.empty(n)
     gamma = np.empty(n)
     lib().or_widths(n, _p(nu), _p(gr), _p(ne), float(lines.gamma_ref_scalar),
                     float(lines.n_exp_scalar), prof, T, P, mass_amu, T_ref, P_ref,
-                    hwhm_fixed, _p(alpha), _p(gamma))
+                    hwhm_fixed, _p(tau), _p(up), _p(alpha), _p(gamma))
     return alpha, gamma
 
 
@@ -271,7 +275,7 @@ def run_condition(wl, lines, cond, bins: Optional[np.ndarray] = None,
     nu, S, keep = intensities(wl.states, lines, wl.mode, wl.population, cond.T, Q,
                               cond.T_vib, cond.T_rot, log_scale)
     alpha, gamma = widths(nu, lines, wl.profile, Tk, cond.P, wl.mass_amu, wl.T_ref, wl.P_ref,
-                          wl.hwhm_fixed)
+                          wl.hwhm_fixed, getattr(wl.states, "lifetime", None))
     sig = sigma(nu, S, alpha, gamma, wl.profile, wl.grid, cond.cutoff, bins) if with_sigma else None
     return CondResult(Q, dQ, nu, S, keep, alpha, gamma, sig)
 
@@ -305,12 +309,15 @@ def adjoint(wl, lines, cond, g: np.ndarray, log_scale: Optional[np.ndarray] = No
     nexp = (np.full(lines.n, lines.n_exp_scalar) if lines.n_exp is None
             else lines.n_exp.astype(np.float64))
     S = r.S
+    # pressure part of gamma (a lifetime width, if any, depends on none of
+    # T, P, gamma_ref, n_exp; the profile sums above use the total width)
+    gp = gref * (wl.T_ref / T) ** nexp * (P / wl.P_ref)
     d_s = S * A
     d_gref = S * Cs * (wl.T_ref / T) ** nexp * (P / wl.P_ref)
-    d_n = S * Cs * r.gamma * np.log(wl.T_ref / T)
+    d_n = S * Cs * gp * np.log(wl.T_ref / T)
     dsg_dT = sg / (2.0 * T) if wl.profile != GAUSSIAN else np.zeros_like(sg)
-    dT_terms = S * (A * dlnS + B * dsg_dT - Cs * nexp * r.gamma / T)
-    dP = math.fsum(S * Cs * r.gamma / P) if P > 0 else 0.0
+    dT_terms = S * (A * dlnS + B * dsg_dT - Cs * nexp * gp / T)
+    dP = math.fsum(S * Cs * gp / P) if P > 0 else 0.0
     dT = math.fsum(dT_terms)
     return dict(dT=dT, dP=dP, d_log_scale=d_s, d_gamma_ref=d_gref, d_n_exp=d_n,
                 A=A, B=B, C=Cs, S=S, nu=r.nu, alpha=r.alpha, gamma=r.gamma, Q=r.Q, dQdT=r.dQdT)

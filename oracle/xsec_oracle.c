@@ -211,11 +211,17 @@ int or_cooling(int64_t nl, const int32_t* up, const int32_t* lo, const float* A,
 /* ---- Line widths (half widths at half maximum) -------------------------- */
 /* Doppler: alpha = (nu / c) sqrt(2 k_B T ln2 / (M amu)); fixed Gaussian: alpha = hwhm.
  * Lorentz (pressure): gamma = gamma_ref (T_ref / T)^n (P / P_ref).
- * In two-temperature runs T is the rotational (kinetic) temperature. */
+ * In non-LTE runs T is the rotational (kinetic) temperature.
+ * Predissociation (lifetime) broadening, section "Spectral synthesis": an
+ * upper state of lifetime tau (s) has the natural Lorentzian HWHM
+ * 1 / (4 pi c tau) in cm^-1 (energy width hbar / tau, FWHM 1/(2 pi c tau));
+ * Lorentzians convolve by adding their widths, so it adds to gamma.  Only a
+ * finite tau > 0 broadens (a stable state, tau = inf, adds nothing).  tau and
+ * up may be NULL. */
 int or_widths(int64_t nl, const double* nu, const float* gref, const float* nexp,
               double gref_scalar, double nexp_scalar, int profile, double T, double P,
               double mass_amu, double T_ref, double P_ref, double hwhm_fixed,
-              double* alpha, double* gamma) {
+              const double* tau, const int32_t* up, double* alpha, double* gamma) {
   const double dfac = sqrt(2.0 * OR_KB * T * OR_LN2 / (mass_amu * OR_AMU));
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < nl; ++i) {
@@ -223,6 +229,10 @@ int or_widths(int64_t nl, const double* nu, const float* gref, const float* nexp
     double gr = gref ? (double)gref[i] : gref_scalar;
     double ne = nexp ? (double)nexp[i] : nexp_scalar;
     gamma[i] = gr * pow(T_ref / T, ne) * (P / P_ref);
+    if (tau && up) {
+      double t = tau[up[i]];
+      if (t > 0.0 && isfinite(t)) gamma[i] += 1.0 / (4.0 * OR_PI * OR_C * t);
+    }
   }
   return 0;
 }

@@ -37,6 +37,7 @@ class States:
     v: Optional[np.ndarray] = None     # int32 [n] vibrational manifold (2T only)
     e_vib: Optional[np.ndarray] = None  # float64 [n_v] E_vib(v) (non-LTE only)
     n_vib: Optional[np.ndarray] = None  # float64 [n_v] vibronic densities (custom-density runs)
+    lifetime: Optional[np.ndarray] = None  # float64 [n] state lifetimes, s (inf: stable)
 
     @property
     def n(self) -> int:
@@ -294,6 +295,19 @@ def with_vib_densities(wl: Workload, seed: int = 77) -> Workload:
     w = 10.0 ** rng.uniform(-3.0, 0.0, wl.states.e_vib.shape[0])
     wl.states.n_vib = w / w.sum()
     wl.population = NLTE_DENSITY
+    return wl
+
+
+def with_lifetimes(wl: Workload, frac: float = 0.3, seed: int = 78) -> Workload:
+    """Give a fraction of the states finite lifetimes (predissociative states),
+    tau = 10^U(-13, -10) s, the rest inf (stable), as an ExoMol states file's
+    lifetime column would."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    n = wl.states.n
+    tau = np.full(n, np.inf)
+    pick = rng.random(n) < frac
+    tau[pick] = 10.0 ** rng.uniform(-13.0, -10.0, int(pick.sum()))
+    wl.states.lifetime = tau
     return wl
 
 
