@@ -111,7 +111,15 @@ typedef struct {
   double T, P, T_vib, T_rot, cutoff;
 } xs_condition;
 
-/* States (Table tab:exomolstates, compulsory part): term values E (cm^-1,
+/* Predissociation (lifetime) broadening (section "Spectral synthesis"): with
+ * states.lifetime given, a line whose upper state has a finite lifetime
+ * tau > 0 gets the natural Lorentzian HWHM 1/(4 pi c tau) (cm^-1) added to its
+ * pressure width gamma, for every profile with a Lorentzian part (Lorentzian,
+ * Voigt and their binned forms); stable states (tau = inf) and tau <= 0 or
+ * NaN add nothing.  The adjoint's gamma_ref, n_exp, T and P gradients act on
+ * the pressure part only, which the lifetime width does not depend on.
+ *
+ * States (Table tab:exomolstates, compulsory part): term values E (cm^-1,
  * FP64) and total degeneracies g_tot (FP64), dense 0-based indices.  Non-LTE
  * runs also need v[n] (manifold index, 0 <= v < n_v) and the table e_vib[n_v]
  * of E_vib(v) (cm^-1); custom-density runs also the weights n_vib[n_v]
@@ -126,6 +134,7 @@ typedef struct {
   const double* e_vib;     /* NULL for LTE */
   int32_t n_v;
   const double* n_vib;     /* XS_NLTE_DENSITY only, else ignored */
+  const double* lifetime;  /* per-state lifetime tau in s, or NULL: predissociation broadening */
 } xs_states;
 
 /* Transitions (Table tab:exomoltrans) and broadening (Table tab:exomolbroad):

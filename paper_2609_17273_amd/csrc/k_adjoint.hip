@@ -114,6 +114,7 @@ struct AdjArgs {
   const double* rnu;
   const float* rgref;
   const float* rnexp;
+  const double* rgpre;
   const int32_t* ridx;
   const void* rS;
   int64_t max_lines;
@@ -538,12 +539,13 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 4 : 3) void k_adjoint(AdjArgs
   for (int64_t bt = (int64_t)blockIdx.x * 4 + wave; bt < nbatch; bt += (int64_t)gridDim.x * 4) {
     const int64_t p = bt * 64 + lane;
     const bool have = p < nk;
-    double nu = 0.0, gref = 0.0, nexp = 0.0, Eu = 0.0, El = 0.0;
+    double nu = 0.0, gref = 0.0, nexp = 0.0, gpre = 0.0, Eu = 0.0, El = 0.0;
     int32_t i = 0;
     if (have) {
       nu = a.rnu[p];
       gref = (double)a.rgref[p];
       nexp = (double)a.rnexp[p];
+      gpre = a.rgpre[p];
       i = a.ridx[p];
       Eu = a.st.E[a.ln.up[i]];
       El = a.st.E[a.ln.lo[i]];
@@ -564,13 +566,16 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 4 : 3) void k_adjoint(AdjArgs
       const double alpha = (PROF == XS_GAUSSIAN) ? cd.hwhm : nu * cd.dop;
       const double sgm = alpha / sqrt2ln2;
       const double gpow = exp(nexp * cd.lnTr);
+      // gam: the pressure width (all the chain rule acts on); gtot adds the
+      // upper state's lifetime width and shapes the profile
       const double gam = gref * gpow * cd.pfac;
+      const double gtot = gam + gpre;
       double inv, y = 0.0;
       if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) inv = 1.0 / alpha;
-      else if (PROF == XS_LORENTZ) inv = 1.0 / gam;
+      else if (PROF == XS_LORENTZ) inv = 1.0 / gtot;
       else {
         inv = sqrt(kLN2) / alpha;
-        y = gam * inv;
+        y = gtot * inv;
       }
       const Sums3 ws = window_sums<R, PROF>(on, klo, khi, nu, inv, y, a.g + (int64_t)c * m.n_bins, m.nu0, m.dnu,
                                             m.n_bins, s_g[wave]);
@@ -583,9 +588,9 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 4 : 3) void k_adjoint(AdjArgs
         B = c0 * sB / sgm;
         C = 0.0;
       } else if (PROF == XS_LORENTZ) {
-        A = sA / (kPI * gam);
+        A = sA / (kPI * gtot);
         B = 0.0;
-        C = sC / (kPI * gam * gam);
+        C = sC / (kPI * gtot * gtot);
       } else {
         const double c0 = 1.0 / (sgm * sqrt(2.0 * kPI));
         A = c0 * sA;
@@ -670,6 +675,7 @@ void launch_adjoint(const ModelDev& m, const Work& w, const StatesView& st, cons
   a.rnu = w.rnu;
   a.rgref = w.rgref;
   a.rnexp = w.rnexp;
+  a.rgpre = w.rgpre;
   a.ridx = w.ridx;
   a.rS = w.rS;
   a.max_lines = w.max_lines;

@@ -382,7 +382,7 @@ __global__ __launch_bounds__(256) void k_records(ModelDev m, const SlotDev* slot
                                                  const double* sb, StatesView st, LinesView ln,
                                                  const int32_t* svals, const int32_t* off,
                                                  int64_t max_lines, double* rnu, float* rgref,
-                                                 float* rnexp, int32_t* ridx, void* rS,
+                                                 float* rnexp, double* rgpre, int32_t* ridx, void* rS,
                                                  const double* cut_class, int32_t* rkc, float* rdel,
                                                  int32_t* rwin) {
   const int64_t nk = off[m.n_buckets];
@@ -394,6 +394,11 @@ __global__ __launch_bounds__(256) void k_records(ModelDev m, const SlotDev* slot
     rnu[p] = nu;
     rgref[p] = ln.gref ? ln.gref[i] : (float)ln.gref_scalar;
     rnexp[p] = ln.nexp ? ln.nexp[i] : (float)ln.nexp_scalar;
+    {
+      // natural width of a predissociating upper state: HWHM 1/(4 pi c tau)
+      const double tau = st.tau ? st.tau[u] : 0.0;
+      rgpre[p] = (tau > 0.0 && tau < INFINITY) ? 1.0 / (4.0 * kPI * kC * tau) : 0.0;
+    }
     ridx[p] = i;
     // home bin, offset from it, and the exact window of every cut-off class
     const int64_t kc = home_bin(nu, m.nu0, m.dnu);
@@ -431,7 +436,7 @@ void launch_offsets_records(const ModelDev& m, const Work& w, const StatesView& 
   hipLaunchKernelGGL(k_offsets, dim3((unsigned)blocks), dim3(256), 0, s, skeys, n, m.n_buckets,
                      w.off);
   hipLaunchKernelGGL(k_records, dim3((unsigned)blocks), dim3(256), 0, s, m, w.slot, w.Q, w.sb, st,
-                     ln, svals, w.off, w.max_lines, w.rnu, w.rgref, w.rnexp, w.ridx, w.rS,
+                     ln, svals, w.off, w.max_lines, w.rnu, w.rgref, w.rnexp, w.rgpre, w.ridx, w.rS,
                      w.cut_class, w.rkc, w.rdel, w.rwin);
 }
 

@@ -37,10 +37,10 @@ struct LineParams {
 
 template <int PROF>
 __device__ __forceinline__ LineParams line_params(const ModelDev& m, const CondDev& cd, double nu,
-                                                  double gref, double nexp, double S) {
+                                                  double gref, double nexp, double gpre, double S) {
   LineParams lp;
   double alpha = (PROF == XS_GAUSSIAN) ? cd.hwhm : nu * cd.dop;
-  double gamma = gref * exp(nexp * cd.lnTr) * cd.pfac;
+  double gamma = gref * exp(nexp * cd.lnTr) * cd.pfac + gpre;
   if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
     lp.inv = 1.0 / alpha;
     lp.y = 0.0;
@@ -149,6 +149,7 @@ struct GatherArgs {
   const double* rnu;
   const float* rgref;
   const float* rnexp;
+  const double* rgpre;
   const void* rS;
   const int32_t* rkc;       // home bin of every sorted line
   const float* rdel;        // nu - nu_{k_c}
@@ -238,8 +239,8 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
       inv = rcp32(alpha);
       c0 = S * (float)0.46971863934982566 * inv;           // sqrt(ln2/pi)/alpha
     } else {
-      const float gamma = g.rgref[p] * __builtin_amdgcn_exp2f(g.rnexp[p] * (float)(cd.lnTr / kLN2)) *
-                          (float)cd.pfac;
+      const float gamma = fmaf(g.rgref[p] * __builtin_amdgcn_exp2f(g.rnexp[p] * (float)(cd.lnTr / kLN2)),
+                               (float)cd.pfac, (float)g.rgpre[p]);
       if (PROF == XS_LORENTZ) {
         inv = rcp32(gamma);
         c0 = S * (float)(1.0 / kPI) * inv;
@@ -288,7 +289,7 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
     if (S == 0.0) return kRowSkip;
     const double nu = g.rnu[p];
     const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
-    const LineParams lp = line_params<PROF>(m, cd, nu, (double)g.rgref[p], (double)g.rnexp[p], S);
+    const LineParams lp = line_params<PROF>(m, cd, nu, (double)g.rgref[p], (double)g.rnexp[p], g.rgpre[p], S);
     const double a = m.dnu * lp.inv, b = delta * lp.inv;
     const double y2 = lp.y * lp.y;
     r.nu = nu;
@@ -388,8 +389,8 @@ __device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, int64_t p,
       inv = (float)0.83255461115769776 * rcp32(alpha);  // sqrt(ln2)/alpha
       c0 = S * (float)(0.5 / m.dnu);
     } else {
-      const float gamma = g.rgref[p] * __builtin_amdgcn_exp2f(g.rnexp[p] * (float)(cd.lnTr / kLN2)) *
-                          (float)cd.pfac;
+      const float gamma = fmaf(g.rgref[p] * __builtin_amdgcn_exp2f(g.rnexp[p] * (float)(cd.lnTr / kLN2)),
+                               (float)cd.pfac, (float)g.rgpre[p]);
       if (BASE == XS_LORENTZ) {
         inv = rcp32(gamma);
         c0 = S * (float)(1.0 / (kPI * m.dnu));
@@ -441,7 +442,7 @@ __device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, int64_t p,
     const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
     double inv, y = 0.0, c0;
     const double gamma = (BASE == XS_LORENTZ || BASE == XS_VOIGT)
-                             ? (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac
+                             ? (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac + g.rgpre[p]
                              : 0.0;
     if (BASE == XS_DOPPLER || BASE == XS_GAUSSIAN) {
       const double alpha = BASE == XS_GAUSSIAN ? cd.hwhm : nu * cd.dop;
@@ -1140,6 +1141,7 @@ void launch_gather(const ModelDev& m, const Work& w, const Tiling& t, double* si
   a.rnu = w.rnu;
   a.rgref = w.rgref;
   a.rnexp = w.rnexp;
+  a.rgpre = w.rgpre;
   a.rS = w.rS;
   a.rkc = w.rkc;
   a.rdel = w.rdel;
@@ -1227,6 +1229,7 @@ struct ScatterArgs {
   const double* rnu;
   const float* rgref;
   const float* rnexp;
+  const double* rgpre;
   const void* rS;
   int64_t max_lines;
   double* sigma;
@@ -1251,7 +1254,7 @@ __global__ __launch_bounds__(256) void k_scatter(ScatterArgs g) {
                                  : ((const double*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
     if (S == 0.0) continue;
     const double scale = sizeof(Real) == 4 ? exp(g.sb[cd.slot]) : 1.0;
-    LineParams lp = line_params<PROF>(m, cd, nu, (double)g.rgref[p], (double)g.rnexp[p], S);
+    LineParams lp = line_params<PROF>(m, cd, nu, (double)g.rgref[p], (double)g.rnexp[p], g.rgpre[p], S);
     double* out = g.sigma + (int64_t)c * m.n_bins;
     if constexpr (sizeof(Real) == 4) {
       ScatF r;
@@ -1331,7 +1334,7 @@ __global__ __launch_bounds__(256) void k_scatter_bin(ScatterArgs g) {
       inv = sqrt(kLN2) / (BASE == XS_GAUSSIAN ? cd.hwhm : nu * cd.dop);
       c0 = S * 0.5 / m.dnu;
     } else {
-      const double gamma = (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac;
+      const double gamma = (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac + g.rgpre[p];
       if (BASE == XS_LORENTZ) {
         inv = 1.0 / gamma;
         c0 = S / (kPI * m.dnu);
@@ -1408,6 +1411,7 @@ void launch_scatter(const ModelDev& m, const Work& w, double* sigma, int accumul
   a.rnu = w.rnu;
   a.rgref = w.rgref;
   a.rnexp = w.rnexp;
+  a.rgpre = w.rgpre;
   a.rS = w.rS;
   a.max_lines = w.max_lines;
   a.sigma = sigma;

@@ -172,6 +172,7 @@ StatesView view(const xs_states* s) {
   v.ev = s->e_vib;
   v.n_v = s->n_v;
   v.nv = s->n_vib;
+  v.tau = s->lifetime;
   return v;
 }
 
@@ -305,6 +306,7 @@ size_t layout(xs_plan* p, char* base, Work* w) {
   x.rnu = (double*)take(8 * L);
   x.rgref = (float*)take(4 * L);
   x.rnexp = (float*)take(4 * L);
+  x.rgpre = (double*)take(8 * L);
   x.ridx = (int32_t*)take(4 * L);
   x.rkc = (int32_t*)take(4 * L);
   x.rdel = (float*)take(4 * L);

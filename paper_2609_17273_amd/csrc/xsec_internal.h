@@ -67,6 +67,7 @@ struct StatesView {
   const double* ev;
   int32_t n_v;
   const double* nv;  // vibronic densities (custom-density populations)
+  const double* tau; // state lifetimes (s) for predissociation broadening, or null
 };
 struct LinesView {
   int64_t n;
@@ -100,6 +101,7 @@ struct Work {
   double* rnu;              // sorted records: nu
   float* rgref;             //                 gamma_ref
   float* rnexp;             //                 n_exp
+  double* rgpre;            //                 lifetime HWHM of the upper state, 1/(4 pi c tau) or 0
   int32_t* ridx;            //                 original line index
   int32_t* rkc;             //                 home bin k_c = rint((nu - nu0)/dnu)
   float* rdel;              //                 nu - nu_{k_c}

@@ -54,7 +54,7 @@ class xs_condition(C.Structure):
 class xs_states(C.Structure):
     _fields_ = [("n", C.c_int64), ("energy", C.c_void_p), ("g_tot", C.c_void_p),
                 ("v", C.c_void_p), ("e_vib", C.c_void_p), ("n_v", C.c_int32),
-                ("n_vib", C.c_void_p)]
+                ("n_vib", C.c_void_p), ("lifetime", C.c_void_p)]
 
 
 class xs_lines(C.Structure):
@@ -237,23 +237,25 @@ def _ptr(t) -> Optional[int]:
 
 
 class DeviceStates:
-    """States as device tensors (E f64, g f64, optional v i32, e_vib f64 and
-    n_vib f64)."""
+    """States as device tensors (E f64, g f64, optional v i32, e_vib f64,
+    n_vib f64 and lifetime f64)."""
 
-    def __init__(self, energy, g_tot, v=None, e_vib=None, n_vib=None):
+    def __init__(self, energy, g_tot, v=None, e_vib=None, n_vib=None, lifetime=None):
         self.energy, self.g_tot, self.v, self.e_vib, self.n_vib = energy, g_tot, v, e_vib, n_vib
+        self.lifetime = lifetime
 
     @classmethod
     def from_numpy(cls, st, device="cuda"):
         import torch
         f = lambda a, dt: None if a is None else torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=device)
         return cls(f(st.energy, torch.float64), f(st.g_tot, torch.float64), f(st.v, torch.int32),
-                   f(st.e_vib, torch.float64), f(getattr(st, "n_vib", None), torch.float64))
+                   f(st.e_vib, torch.float64), f(getattr(st, "n_vib", None), torch.float64),
+                   f(getattr(st, "lifetime", None), torch.float64))
 
     def struct(self) -> xs_states:
         return xs_states(self.energy.shape[0], _ptr(self.energy), _ptr(self.g_tot), _ptr(self.v),
                          _ptr(self.e_vib), 0 if self.e_vib is None else self.e_vib.shape[0],
-                         _ptr(self.n_vib))
+                         _ptr(self.n_vib), _ptr(self.lifetime))
 
 
 class DeviceLines:

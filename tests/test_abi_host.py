@@ -52,7 +52,7 @@ _STRUCTS = {
                  "hwhm_fixed"],
     "xs_grid": ["nu0", "dnu", "n_bins"],
     "xs_condition": ["T", "P", "T_vib", "T_rot", "cutoff"],
-    "xs_states": ["n", "energy", "g_tot", "v", "e_vib", "n_v", "n_vib"],
+    "xs_states": ["n", "energy", "g_tot", "v", "e_vib", "n_v", "n_vib", "lifetime"],
     "xs_lines": ["n", "upper", "lower", "einstein_a", "gamma_ref", "n_exp", "log_scale",
                  "gamma_ref_scalar", "n_exp_scalar"],
     "xs_config": ["tile_bins", "bucket_bins", "persistent", "waves_per_cu", "chunk_lines"],
