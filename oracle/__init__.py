@@ -30,6 +30,8 @@ _CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-shared", 
 DOPPLER, GAUSSIAN, LORENTZ, VOIGT = 0, 1, 2, 3
 # bin-integrated forms: the mean of the profile over the bin centred on the point
 BIN_DOPPLER, BIN_GAUSSIAN, BIN_LORENTZ, BIN_VOIGT = 4, 5, 6, 7
+# pseudo-Voigt approximations (widths of the Voigt)
+PV_THOMPSON, PV_OLIVERO = 8, 9
 ABSORPTION, EMISSION = 0, 1
 LTE, NLTE_2T, NLTE_DENSITY = 0, 1, 2
 
@@ -298,7 +300,7 @@ def adjoint(wl, lines, cond, g: np.ndarray, log_scale: Optional[np.ndarray] = No
     if wl.population != LTE:
         raise ValueError("oracle adjoint: LTE only")
     if wl.profile >= BIN_DOPPLER:
-        raise ValueError("oracle adjoint: sampled profiles only")
+        raise ValueError("oracle adjoint: the sampled Doppler, Gaussian, Lorentzian and Voigt only")
     T, P = cond.T, cond.P
     r = run_condition(wl, lines, cond, log_scale=log_scale, with_sigma=False)
     A, B, Cs = adjoint_sums(r.nu, r.alpha, r.gamma, wl.profile, wl.grid, cond.cutoff, g)

@@ -19,7 +19,8 @@
  *     with nu_fi <= 0 discarded;
  *   - profiles of Table (tab:profile): Doppler / Gaussian, Lorentzian, and the
  *     SciPy-convention Voigt (Re of the Faddeeva function), sampled at the
- *     grid points or averaged over the bins centred on them ("binned");
+ *     grid points or averaged over the bins centred on them ("binned"), and
+ *     the Thompson and Olivero pseudo-Voigts;
  *   - the cooling function, Eq. (cf);
  *   - per-line adjoint sums of sigma against a cotangent dL/dsigma.
  *
@@ -50,7 +51,11 @@ enum { OR_DOPPLER = 0, OR_GAUSSIAN = 1, OR_LORENTZ = 2, OR_VOIGT = 3 };
  * methods): the mean of the profile over the bin [nu_k - dnu/2, nu_k + dnu/2]
  * centred on the grid point. */
 enum { OR_BIN_DOPPLER = 4, OR_BIN_GAUSSIAN = 5, OR_BIN_LORENTZ = 6, OR_BIN_VOIGT = 7 };
-static int or_base(int profile) { return profile >= 4 ? profile - 4 : profile; }
+/* Pseudo-Voigt approximations of the profile table, with the Voigt's widths. */
+enum { OR_PV_THOMPSON = 8, OR_PV_OLIVERO = 9 };
+static int or_base(int profile) {
+  return profile < 4 ? profile : (profile < 8 ? profile - 4 : OR_VOIGT);
+}
 enum { OR_ABSORPTION = 0, OR_EMISSION = 1 };
 enum { OR_LTE = 0, OR_NLTE_2T = 1, OR_NLTE_DENSITY = 2 };
 
@@ -365,7 +370,32 @@ void or_faddeeva_deriv(double x, double y, double* wp_re, double* wp_im, double*
  * Lorentzian with HWHM gamma: gamma / (pi (d^2 + gamma^2)).
  * Voigt (scipy.special.voigt_profile convention): Re w(z) / (sg sqrt(2 pi)),
  *   z = (d + i gamma) / (sg sqrt 2), sg = alpha / sqrt(2 ln 2). */
+/* Pseudo-Voigt: eta L(d; f) + (1 - eta) G(d; f), a unit-area Lorentzian and
+ * Gaussian of the same FWHM f, from the Gaussian and Lorentzian FWHM
+ * fG = 2 alpha, fL = 2 gamma.
+ *   Thompson, Cox & Hastings (1987): f^5 = fG^5 + 2.69269 fG^4 fL
+ *     + 2.42843 fG^3 fL^2 + 4.47163 fG^2 fL^3 + 0.07842 fG fL^4 + fL^5;
+ *   Olivero & Longbothum (1977): f = 0.5346 fL + sqrt(0.2166 fL^2 + fG^2);
+ * both with eta = 1.36603 r - 0.47719 r^2 + 0.11116 r^3, r = fL / f. */
+static double or_pseudo_voigt(int profile, double d, double alpha, double gamma) {
+  const double fG = 2.0 * alpha, fL = 2.0 * gamma;
+  double f;
+  if (profile == OR_PV_THOMPSON) {
+    double s = pow(fG, 5) + 2.69269 * pow(fG, 4) * fL + 2.42843 * pow(fG, 3) * fL * fL +
+               4.47163 * fG * fG * pow(fL, 3) + 0.07842 * fG * pow(fL, 4) + pow(fL, 5);
+    f = pow(s, 0.2);
+  } else {
+    f = 0.5346 * fL + sqrt(0.2166 * fL * fL + fG * fG);
+  }
+  const double r = fL / f;
+  const double eta = 1.36603 * r - 0.47719 * r * r + 0.11116 * r * r * r;
+  const double L = 2.0 / (OR_PI * f) / (1.0 + 4.0 * d * d / (f * f));
+  const double G = 2.0 * sqrt(OR_LN2 / OR_PI) / f * exp(-4.0 * OR_LN2 * d * d / (f * f));
+  return eta * L + (1.0 - eta) * G;
+}
+
 static double or_profile1(int profile, double d, double alpha, double gamma) {
+  if (profile >= OR_PV_THOMPSON) return or_pseudo_voigt(profile, d, alpha, gamma);
   if (profile == OR_DOPPLER || profile == OR_GAUSSIAN)
     return sqrt(OR_LN2 / OR_PI) / alpha * exp(-OR_LN2 * d * d / (alpha * alpha));
   if (profile == OR_LORENTZ) return gamma / (OR_PI * (d * d + gamma * gamma));
@@ -606,8 +636,8 @@ int or_sigma(int64_t nl, const double* nu, const double* S, const double* alpha,
       int64_t i = keys[j].i;
       if (!or_in_window(nuk, nu[i], cut)) continue;
       double d = nuk - nu[i];
-      double f = profile >= 4 ? or_binned1(profile, d, dnu, alpha[i], gamma[i])
-                              : or_profile1(profile, d, alpha[i], gamma[i]);
+      double f = (profile >= 4 && profile < 8) ? or_binned1(profile, d, dnu, alpha[i], gamma[i])
+                                               : or_profile1(profile, d, alpha[i], gamma[i]);
       or_add(&acc, S[i] * f);
     }
     out[q] = or_total(&acc);

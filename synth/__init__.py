@@ -26,6 +26,7 @@ import numpy as np
 # Enumerations mirrored from the C-ABI (include/xsec.h); plain ints here.
 DOPPLER, GAUSSIAN, LORENTZ, VOIGT = 0, 1, 2, 3
 BIN_DOPPLER, BIN_GAUSSIAN, BIN_LORENTZ, BIN_VOIGT = 4, 5, 6, 7
+PV_THOMPSON, PV_OLIVERO = 8, 9
 ABSORPTION, EMISSION = 0, 1
 LTE, NLTE_2T, NLTE_DENSITY = 0, 1, 2
 
