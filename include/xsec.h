@@ -56,11 +56,19 @@ typedef enum {
  * the profile over the bin [nu_k - dnu/2, nu_k + dnu/2] centred on each grid
  * point, i.e. (F(d + dnu/2) - F(d - dnu/2)) / dnu with F the profile's
  * cumulative distribution; the cut-off still tests the bin centre.  Widths and
- * parameters as for the sampled kind (XS_BIN_x = XS_x + 4).  Forward only:
- * the adjoint returns XS_EUNSUPPORTED for them. */
+ * parameters as for the sampled kind (XS_BIN_x = XS_x + 4).
+ * XS_PV_*: the pseudo-Voigt methods of the same table, with the Voigt's widths
+ * (Doppler alpha, Lorentzian gamma): eta L(d; f) + (1 - eta) G(d; f), a
+ * unit-area Lorentzian and Gaussian of one FWHM f from fG = 2 alpha and
+ * fL = 2 gamma, by the Thompson-Cox-Hastings width polynomial (XS_PV_THOMPSON)
+ * or the Olivero-Longbothum formula 0.5346 fL + sqrt(0.2166 fL^2 + fG^2)
+ * (XS_PV_OLIVERO), with eta = 1.36603 r - 0.47719 r^2 + 0.11116 r^3,
+ * r = fL / f.  Binned and pseudo-Voigt kinds are forward only: the adjoint
+ * returns XS_EUNSUPPORTED for them. */
 typedef enum {
   XS_DOPPLER = 0, XS_GAUSSIAN = 1, XS_LORENTZ = 2, XS_VOIGT = 3,
-  XS_BIN_DOPPLER = 4, XS_BIN_GAUSSIAN = 5, XS_BIN_LORENTZ = 6, XS_BIN_VOIGT = 7
+  XS_BIN_DOPPLER = 4, XS_BIN_GAUSSIAN = 5, XS_BIN_LORENTZ = 6, XS_BIN_VOIGT = 7,
+  XS_PV_THOMPSON = 8, XS_PV_OLIVERO = 9
 } xs_profile;
 /* Absorption (Eq. abs intensity lte, Eq. nlte ab 2T) or emission
  * (Eq. ems intensity lte, Eq. nlte em 2T) intensities. */

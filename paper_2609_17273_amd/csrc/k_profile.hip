@@ -508,6 +508,54 @@ __device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, int64_t p,
   return kRowGeneral;
 }
 
+// Staging for the pseudo-Voigts (as stage_line).  Record fields: the lane
+// variable x = 2 d / f as for the Lorentzian (a, nb, jfb / nu, inv);
+// c0 = S times the Lorentzian part's factor, y = S times the Gaussian part's;
+// rB / r[0] = bins where the Gaussian part 2^{-x^2} is not zero in the
+// precision.  First class: rows where only the Lorentzian part is left.
+template <typename Rec, int PROF>
+__device__ int stage_line_pv(const GatherArgs& g, const CondDev& cd, int64_t p, int64_t tlo,
+                             int64_t thi, int rowb, Rec& r) {
+  const ModelDev& m = g.m;
+  const int2 win = ((const int2*)g.rwin)[(int64_t)cd.cclass * g.max_lines + p];
+  if (win.x > win.y || win.y < tlo || win.x > thi) return kRowSkip;
+  const int kc = g.rkc[p];
+  const int klo = max(win.x, (int)tlo), khi = min(win.y, (int)thi);
+  r.klo = klo;
+  r.khi = khi;
+  r.flag = 0;
+  r.kc = kc;
+  const int lo = (int)tlo, hi = lo + rowb - 1;
+  const bool inside = klo <= lo && khi >= hi;
+  const double nu = g.rnu[p];
+  const double S = sizeof(Rec) == sizeof(RecF) ? (double)((const float*)g.rS)[(int64_t)cd.slot * g.max_lines + p]
+                                               : ((const double*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
+  if (S == 0.0) return kRowSkip;
+  const double gamma = (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac + g.rgpre[p];
+  const PVConst pc = pv_const(PROF, nu * cd.dop, gamma, S);
+  const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
+  const double a = m.dnu * pc.inv, b = delta * pc.inv;
+  KRange gz;
+  if constexpr (sizeof(Rec) == sizeof(RecF)) {
+    r.a = (float)a;
+    r.nb = (float)(-b);
+    r.jfb = (float)(lo - kc);
+    r.c0 = (float)pc.cL;
+    r.y = (float)pc.cG;
+    r.rB = x_range_f(12.649110640673518f, (float)a, (float)b, kc, klo, khi);  // 2^{-x^2} = 0 beyond sqrt(160)
+    gz = r.rB;
+  } else {
+    r.nu = nu;
+    r.inv = pc.inv;
+    r.c0 = pc.cL;
+    r.y = pc.cG;
+    r.r[0] = x_range(sqrt(1100.0), a, b, kc, klo, khi);
+    gz = r.r[0];
+  }
+  if (!meets(lo, hi, gz)) return inside ? kRowF1 : kRowF1M;
+  return kRowGeneral;
+}
+
 // ---- far-region evaluators ------------------------------------------------
 // The hardware FP64 reciprocal has a relative error below 5e-8 on gfx950
 // (measured over 1e6 arguments spanning 1e-30..1e30); one Newton step
@@ -624,7 +672,8 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
       int cls = kRowSkip;
       const int64_t p = p0 + lane;
       if (p < q1) {
-        if constexpr (PROF >= XS_BIN_DOPPLER) cls = stage_line_bin<Rec, PROF>(g, cd, p, tlo, thi, ROWB, r);
+        if constexpr (PROF >= XS_PV_THOMPSON) cls = stage_line_pv<Rec, PROF>(g, cd, p, tlo, thi, ROWB, r);
+        else if constexpr (PROF >= XS_BIN_DOPPLER) cls = stage_line_bin<Rec, PROF>(g, cd, p, tlo, thi, ROWB, r);
         else cls = stage_line<Rec, PROF>(g, cd, p, tlo, thi, ROWB, r);
       }
       // LDS order: F1 | F1M | F2 | F2M | F3 | F3M (FP64) | general
@@ -653,7 +702,70 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
       if (cls != kRowSkip) srec[slot] = r;
       __syncthreads();
 
-      if constexpr (PROF >= XS_BIN_DOPPLER) {
+      if constexpr (PROF >= XS_PV_THOMPSON) {
+        // ---- pseudo-Voigts: cL/(1 + x^2) + cG 2^{-x^2} ----
+        auto xv = [&](const Rec& rr, int j) -> Real {
+          if constexpr (F32) {
+            return fmaf(rr.jfb + lane_off + (float)(64 * j), rr.a, rr.nb);
+          } else {
+#pragma clang fp contract(off)
+            return (nuk[j] - rr.nu) * rr.inv;
+          }
+        };
+        auto addv = [&](int j, Real v) {
+          if constexpr (F32) acc32[j] += v;
+          else acc64[j] += v;
+        };
+        // rows where the Gaussian part is zero: the Lorentzian part alone
+        auto lor_rows = [&](int l0, int l1, auto masked) {
+          for (int l = l0; l < l1; ++l) {
+            const Rec& rr = srec[l];
+            const Real c0 = rr.c0;
+            int klo = 0, khi = 0;
+            if (masked) {
+              klo = uni(rr.klo);
+              khi = uni(rr.khi);
+            }
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+              const Real x = xv(rr, j);
+              const Real t = c0 * rcp_r<Real>(fma(x, x, (Real)1));
+              const int k = my0 + 64 * j;
+              addv(j, (!masked || (k >= klo && k <= khi)) ? t : (Real)0);
+            }
+          }
+        };
+        lor_rows(0, e1, std::false_type());
+        lor_rows(e1, e1m, std::true_type());
+        for (int l = e3m; l < eg; ++l) {
+          const Rec& rr = srec[l];
+          const int klo = uni(rr.klo), khi = uni(rr.khi);
+          KRange R0;
+          if constexpr (F32) R0 = KRange{uni(rr.rB.lo), uni(rr.rB.hi)};
+          else R0 = KRange{uni(rr.r[0].lo), uni(rr.r[0].hi)};
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            const int cl = row_lo + 64 * j, ch = cl + 63;
+            if (ch < klo || cl > khi) continue;
+            const bool full = cl >= klo && ch <= khi;
+            const int k = my0 + 64 * j;
+            const Real x = xv(rr, j);
+            Real v = rr.c0 * rcp_r<Real>(fma(x, x, (Real)1));
+            if (meets(cl, ch, R0)) {
+              if constexpr (F32) v = fmaf(rr.y, __builtin_amdgcn_exp2f(-(x * x)), v);
+              else v = fma(rr.y, exp2(-(x * x)), v);
+            }
+            addv(j, (full || (k >= klo && k <= khi)) ? v : (Real)0);
+          }
+        }
+        if constexpr (F32) {
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            acc64[j] += (double)acc32[j];
+            acc32[j] = 0.0f;
+          }
+        }
+      } else if constexpr (PROF >= XS_BIN_DOPPLER) {
         // ---- binned profiles: bin means from the closed-form bin integrals ----
         constexpr int BASE = PROF - 4;
         constexpr bool GAU = BASE == XS_DOPPLER || BASE == XS_GAUSSIAN;
@@ -1176,9 +1288,11 @@ void launch_gather(const ModelDev& m, const Work& w, const Tiling& t, double* si
   if (m.prec == XS_FP32) {
     XS_P(float, XS_DOPPLER) XS_P(float, XS_GAUSSIAN) XS_P(float, XS_LORENTZ) XS_P(float, XS_VOIGT)
     XS_P(float, XS_BIN_DOPPLER) XS_P(float, XS_BIN_GAUSSIAN) XS_P(float, XS_BIN_LORENTZ) XS_P(float, XS_BIN_VOIGT)
+    XS_P(float, XS_PV_THOMPSON) XS_P(float, XS_PV_OLIVERO)
   } else {
     XS_P(double, XS_DOPPLER) XS_P(double, XS_GAUSSIAN) XS_P(double, XS_LORENTZ) XS_P(double, XS_VOIGT)
     XS_P(double, XS_BIN_DOPPLER) XS_P(double, XS_BIN_GAUSSIAN) XS_P(double, XS_BIN_LORENTZ) XS_P(double, XS_BIN_VOIGT)
+    XS_P(double, XS_PV_THOMPSON) XS_P(double, XS_PV_OLIVERO)
   }
 #undef XS_P
   const int rb = (int)std::min<int64_t>(65536, a.n_ct);
@@ -1391,6 +1505,55 @@ __global__ __launch_bounds__(256) void k_scatter_bin(ScatterArgs g) {
   }
 }
 
+// Line-parallel scatter of the pseudo-Voigts.
+template <typename Real, int PROF>
+__global__ __launch_bounds__(256) void k_scatter_pv(ScatterArgs g) {
+  const ModelDev& m = g.m;
+  const int lane = threadIdx.x & 63;
+  const int64_t nkept = g.off[m.n_buckets];
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int64_t total = nkept * m.n_cond;
+  for (int64_t wi = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); wi < total;
+       wi += nwaves) {
+    const int64_t p = wi / m.n_cond;
+    const int c = (int)(wi % m.n_cond);
+    const CondDev cd = g.cond[c];
+    const double nu = g.rnu[p];
+    int64_t klo, khi;
+    if (!line_window(nu, cd.cut, m.nu0, m.dnu, m.n_bins, klo, khi)) continue;
+    const double S = sizeof(Real) == 4 ? (double)((const float*)g.rS)[(int64_t)cd.slot * g.max_lines + p]
+                                       : ((const double*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
+    if (S == 0.0) continue;
+    const double scale = sizeof(Real) == 4 ? exp(g.sb[cd.slot]) : 1.0;
+    const double gamma = (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac + g.rgpre[p];
+    const PVConst pc = pv_const(PROF, nu * cd.dop, gamma, S);
+    double* out = g.sigma + (int64_t)c * m.n_bins;
+    if constexpr (sizeof(Real) == 4) {
+      const int64_t kc = home_bin(nu, m.nu0, m.dnu);
+      const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
+      const float a = (float)(m.dnu * pc.inv), b = (float)(delta * pc.inv);
+      const float cL = (float)pc.cL, cG = (float)pc.cG;
+      for (int64_t k = klo + lane; k <= khi; k += 64) {
+        const float x = fmaf((float)(k - kc), a, -b);
+        float v = cL * __builtin_amdgcn_rcpf(fmaf(x, x, 1.0f));
+        if (x * x < 160.0f) v = fmaf(cG, __builtin_amdgcn_exp2f(-(x * x)), v);
+        unsafeAtomicAdd(out + k, scale * (double)v);
+      }
+    } else {
+      for (int64_t k = klo + lane; k <= khi; k += 64) {
+        double x;
+        {
+#pragma clang fp contract(off)
+          x = (nu_of_bin(m.nu0, m.dnu, k) - nu) * pc.inv;
+        }
+        double v = pc.cL / fma(x, x, 1.0);
+        if (x * x < 1100.0) v = fma(pc.cG, exp2(-(x * x)), v);
+        unsafeAtomicAdd(out + k, v);
+      }
+    }
+  }
+}
+
 __global__ void k_fill(double* p, int64_t n, int accumulate) {
   if (accumulate) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -1438,6 +1601,17 @@ void launch_scatter(const ModelDev& m, const Work& w, double* sigma, int accumul
     XS_SB(double, XS_BIN_DOPPLER) XS_SB(double, XS_BIN_GAUSSIAN) XS_SB(double, XS_BIN_LORENTZ) XS_SB(double, XS_BIN_VOIGT)
   }
 #undef XS_SB
+#define XS_SPV(R, P)                                                               \
+  if (m.profile == P) {                                                            \
+    hipLaunchKernelGGL((k_scatter_pv<R, P>), dim3(blocks), dim3(256), 0, s, a);    \
+    return;                                                                        \
+  }
+  if (m.prec == XS_FP32) {
+    XS_SPV(float, XS_PV_THOMPSON) XS_SPV(float, XS_PV_OLIVERO)
+  } else {
+    XS_SPV(double, XS_PV_THOMPSON) XS_SPV(double, XS_PV_OLIVERO)
+  }
+#undef XS_SPV
 }
 
 }  // namespace xs

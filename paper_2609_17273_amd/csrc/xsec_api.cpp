@@ -77,7 +77,7 @@ namespace {
 
 int validate_model(const xs_model* m) {
   if (!m) return fail(XS_EINVAL, "model is NULL");
-  if (m->profile < XS_DOPPLER || m->profile > XS_BIN_VOIGT) return fail(XS_EINVAL, "model.profile out of range");
+  if (m->profile < XS_DOPPLER || m->profile > XS_PV_OLIVERO) return fail(XS_EINVAL, "model.profile out of range");
   const int base = base_profile(m->profile);
   if (m->mode < XS_ABSORPTION || m->mode > XS_EMISSION) return fail(XS_EINVAL, "model.mode out of range");
   if (m->population < XS_LTE || m->population > XS_NLTE_DENSITY)
@@ -581,7 +581,7 @@ int xs_profile_adjoint(xs_plan* p, const xs_states* st, const xs_lines* ln, cons
   if (p->model.population != XS_LTE)
     return fail(XS_EUNSUPPORTED, "adjoint: two-temperature populations are not supported");
   if (p->model.profile >= XS_BIN_DOPPLER)
-    return fail(XS_EUNSUPPORTED, "adjoint: binned profiles are not supported");
+    return fail(XS_EUNSUPPORTED, "adjoint: binned and pseudo-Voigt profiles are not supported");
   if (!g || !dT || !dP || !dls) return fail(XS_EINVAL, "adjoint: dL_dsigma, dL_dT, dL_dP and dL_dlog_scale are required");
   if (ln->n != p->last_lines_in) return fail(XS_EINVAL, "adjoint: lines differ from the prepared ones");
   launch_adjoint(p->md, p->w, view(st), view(ln), g, dT, dP, dgref, dnexp, dls, ln->n, p->stream);
@@ -596,7 +596,7 @@ int xs_cross_section_adjoint(xs_plan* p, const xs_states* st, const xs_lines* ln
   if (p->model.population != XS_LTE)
     return fail(XS_EUNSUPPORTED, "adjoint: two-temperature populations are not supported");
   if (p->model.profile >= XS_BIN_DOPPLER)
-    return fail(XS_EUNSUPPORTED, "adjoint: binned profiles are not supported");
+    return fail(XS_EUNSUPPORTED, "adjoint: binned and pseudo-Voigt profiles are not supported");
   if (!g || !dT || !dP || !dls) return fail(XS_EINVAL, "adjoint: dL_dsigma, dL_dT, dL_dP and dL_dlog_scale are required");
   if ((rc = preprocess(p, st, ln))) return rc;
   launch_adjoint(p->md, p->w, view(st), view(ln), g, dT, dP, dgref, dnexp, dls, ln->n, p->stream);

@@ -19,8 +19,10 @@ constexpr double kPI = 3.14159265358979323846;
 constexpr double kLN2 = 0.69314718055994530942;
 
 constexpr int kMaxCond = 256;
-// Sampled kind of a profile: XS_BIN_x -> XS_x (widths and parameters are shared).
-constexpr int base_profile(int profile) { return profile >= 4 ? profile - 4 : profile; }
+// The kind whose widths a profile uses: XS_BIN_x -> XS_x; pseudo-Voigts -> XS_VOIGT.
+constexpr int base_profile(int profile) {
+  return profile < 4 ? profile : (profile < 8 ? profile - 4 : 3);
+}
 constexpr int kQBlocks = 256;     // partial sums per slot in the partition-function reduction
 constexpr int kItemsPerCU = 64;   // gather work items aimed at per compute unit when tiles are split
 constexpr int kAdjBlocks = 2048;  // persistent blocks of the adjoint (fixed: deterministic sums)

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libxsec.so")
 XS_OK, XS_EINVAL, XS_ENOMEM, XS_EDEVICE, XS_EWORKSPACE, XS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 XS_DOPPLER, XS_GAUSSIAN, XS_LORENTZ, XS_VOIGT = 0, 1, 2, 3
 XS_BIN_DOPPLER, XS_BIN_GAUSSIAN, XS_BIN_LORENTZ, XS_BIN_VOIGT = 4, 5, 6, 7
+XS_PV_THOMPSON, XS_PV_OLIVERO = 8, 9
 XS_ABSORPTION, XS_EMISSION = 0, 1
 XS_LTE, XS_NLTE_2T, XS_NLTE_DENSITY = 0, 1, 2
 XS_FP64, XS_FP32 = 0, 1

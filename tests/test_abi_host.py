@@ -113,7 +113,7 @@ def test_plan_create_rejects_bad_arguments(case):
     cond = lambda **kw: X.xs_condition(kw.get("T", 1000.0), kw.get("P", 1.0), kw.get("Tv", 1000.0),
                                        kw.get("Tr", 1000.0), kw.get("cut", 25.0))
     args = {
-        "profile": dict(model=_model(X, profile=8)),
+        "profile": dict(model=_model(X, profile=10)),
         "mode": dict(model=_model(X, mode=-1)),
         "population": dict(model=_model(X, population=5)),
         "precision": dict(model=_model(X, precision=2)),
