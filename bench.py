@@ -37,18 +37,22 @@ sys.path.insert(0, ROOT)
 # kernels use).  (rho threshold, flops) from the outermost region inward:
 #   forward FP32: 1 node pair: x = fma(r,a,-b) 2, u 1, u+q 1, d = fma 2, rcp 1,
 #                 numerator fma 2, accumulate fma 2 = 11; 2 pairs 19;
-#                 Taylor core (K = 16, complex Horner in FP64) 140.
+#                 core: Weideman's rational approximation with N = 24 terms in
+#                 FP64 (q and Z 14, 23 complex Horner steps x 7 = 161, Re w 11,
+#                 x, scale and accumulate 4) = 190.
 #   forward FP64: 1 pair 11; 2 pairs (one division) 19; 3/4/6 pairs 30/39/57;
-#                 core (K = 22) 188.
+#                 core N = 40: 14 + 39 x 7 + 11 + 4 = 302.
 #   adjoint FP32: 1 pair: x 2, u 1, pair terms 18 (u+q, d, rcp, e, s, t),
-#                 three accumulations 6 = 27; 2 pairs 54; core (w and w') 280.
+#                 three accumulations 6 = 27; 2 pairs 54; core: w (N = 24, both
+#                 parts: 14 + 161 + 17), w' = -2zw + 2i/sqrt(pi) and Re G 13,
+#                 x, |z|^2 5, three accumulations 6 = 216.
 #   adjoint FP64: 1/2/3 pairs 27/54/78; 4/6 pairs (general form) 113/161;
-#                 core (K = 22) 372.
+#                 core N = 40: 14 + 273 + 17 + 24 = 328.
 FLOP_REGIONS = {
-    ("fwd", "f32"): [(900.0, 11), (64.0, 19), (0.0, 140)],
-    ("fwd", "f64"): [(9.0e6, 11), (6400.0, 19), (400.0, 30), (144.0, 39), (64.0, 57), (0.0, 188)],
-    ("adj", "f32"): [(900.0, 27), (64.0, 54), (0.0, 280)],
-    ("adj", "f64"): [(9.0e6, 27), (6400.0, 54), (400.0, 78), (144.0, 113), (64.0, 161), (0.0, 372)],
+    ("fwd", "f32"): [(900.0, 11), (64.0, 19), (0.0, 190)],
+    ("fwd", "f64"): [(9.0e6, 11), (6400.0, 19), (400.0, 30), (144.0, 39), (64.0, 57), (0.0, 302)],
+    ("adj", "f32"): [(900.0, 27), (64.0, 54), (0.0, 216)],
+    ("adj", "f64"): [(9.0e6, 27), (6400.0, 54), (400.0, 78), (144.0, 113), (64.0, 161), (0.0, 328)],
 }
 # MI355X vector peaks, no packed-FP32 (packed FP32 is disabled in this build):
 # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP32
@@ -212,6 +216,35 @@ def batched_48(X, wl, ds, dl, n_lines):
     return out
 
 
+def pseudo_voigt(X, wl, ds, dl, n_lines, cfg, sampled_ms):
+    """The Olivero and Thompson pseudo-Voigts on the same 1e7 lines and
+    condition: profile pass alone, FP32 form, main-step kernel configuration."""
+    import torch
+    out = {"lines": n_lines}
+    for kind, name in ((X.XS_PV_OLIVERO, "olivero_f32"), (X.XS_PV_THOMPSON, "thompson_f32")):
+        p = X.Plan(kind, X.XS_ABSORPTION, X.XS_LTE, X.XS_FP32, wl.grid, wl.conditions, n_lines,
+                   mass_amu=wl.mass_amu)
+        p.set_config(**cfg)
+        sig = torch.empty((1, wl.grid.n_bins), dtype=torch.float64, device="cuda")
+        p.prepare(ds, dl)
+        p.profile(out=sig)
+        pairs = p.stats()["window_pairs"]
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            p.profile(out=sig)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        out[name] = {"profile_pass_ms": round(ms, 3), "evals_per_s": pairs / (ms / 1e3),
+                     "over_sampled_voigt_f32": round(ms / sampled_ms, 3)}
+        log(f"pseudo-Voigt {name}: {ms:.2f} ms")
+        p.close()
+        del sig
+    return out
+
+
 def binned_voigt(X, wl, ds, dl, n_lines, cfg, sampled_ms):
     """The binned Voigt profile (bin means, Table tab:profile) on the same 1e7
     lines and condition: the profile pass alone (after one prepare), FP32 and
@@ -243,6 +276,49 @@ def binned_voigt(X, wl, ds, dl, n_lines, cfg, sampled_ms):
     out["f32_over_sampled_f32"] = round(out["f32"]["profile_pass_ms"] / sampled_ms, 3)
     out["fp32_over_fp64_speedup"] = round(out["f64"]["profile_pass_ms"] / out["f32"]["profile_pass_ms"], 3)
     return out
+
+
+# Cooling-function reduction: VALU instructions per (item, temperature) term
+# in k_cf_sum (gfx950 assembly of this build: the FP64 exp is a rounding
+# argument reduction, a degree-11 polynomial, ldexp and range selects, 21
+# instructions, plus the exponent product and the accumulating FMA).  Peak
+# issue: 256 CU x 64 lanes x 2.4 GHz = 39.3e12 lane-instructions/s (FP64 FMA
+# issues at full rate on this chip).
+CF_INSTR_PER_TERM = 23
+PEAK_LANE_INSTR = 256 * 64 * 2.4e9
+
+
+def cooling_function(X, wl, ds, dl, lines):
+    """Cooling function W(T), Eq. (cf), of the same 1e6 states and 1e7 lines
+    on the 1-5000 K grid (1 K steps), FP64."""
+    import numpy as np
+    import torch
+    T = np.arange(1.0, 5001.0)
+    p = X.Plan(X.XS_VOIGT, X.XS_EMISSION, X.XS_LTE, X.XS_FP64, wl.grid, wl.conditions, lines.n,
+               mass_amu=wl.mass_amu)
+    p.cooling_function(ds, dl, T)
+    torch.cuda.synchronize()
+    reps, ms = 3, 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        p.cooling_function(ds, dl, T)
+        e1.record()
+        torch.cuda.synchronize()
+        ms += e0.elapsed_time(e1) / reps
+    p.close()
+    E = wl.states.energy
+    nu = E[lines.upper] - E[lines.lower]
+    runs = int(np.unique(lines.upper[nu > 0]).size)
+    terms = (wl.states.n + runs) * T.size
+    ach = terms * CF_INSTR_PER_TERM / (ms / 1e3)
+    log(f"cooling function: {ms:.2f} ms, {terms:.3e} terms")
+    return {"temperatures": int(T.size), "lines": lines.n, "states": wl.states.n, "upper_state_runs": runs,
+            "ms": round(ms, 3), "terms": terms, "terms_per_s": terms / (ms / 1e3),
+            "line_temperature_pairs_per_s": lines.n * T.size / (ms / 1e3),
+            "roofline": {"bound": "alu", "achieved": round(ach / 1e12, 3), "peak": round(PEAK_LANE_INSTR / 1e12, 3),
+                         "unit": "T VALU lane-instructions/s", "frac": round(ach / PEAK_LANE_INSTR, 4),
+                         "instr_per_term": CF_INSTR_PER_TERM}}
 
 
 def stream_2t(X, n_lines=50_000_000, n_chunks=5):
@@ -371,6 +447,8 @@ def main():
             ps.close()
         extras["gather_over_scatter_speedup_f32"] = round(extras["scatter_f32"]["profile_pass_ms"] / per32["forward"], 2)
         extras["binned_voigt"] = binned_voigt(X, wl, ds, dl, lines.n, cfg, per32["forward"])
+        extras["pseudo_voigt"] = pseudo_voigt(X, wl, ds, dl, lines.n, cfg, per32["forward"])
+        extras["cooling_function"] = cooling_function(X, wl, ds, dl, lines)
         extras["batched_48"] = batched_48(X, wl, ds, dl, lines.n)
         extras["stream_2t"] = stream_2t(X)
 

@@ -545,7 +545,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 4 : 3) void k_adjoint(AdjArgs
       nu = a.rnu[p];
       gref = (double)a.rgref[p];
       nexp = (double)a.rnexp[p];
-      gpre = a.rgpre[p];
+      gpre = a.rgpre ? a.rgpre[p] : 0.0;
       i = a.ridx[p];
       Eu = a.st.E[a.ln.up[i]];
       El = a.st.E[a.ln.lo[i]];

@@ -394,9 +394,9 @@ __global__ __launch_bounds__(256) void k_records(ModelDev m, const SlotDev* slot
     rnu[p] = nu;
     rgref[p] = ln.gref ? ln.gref[i] : (float)ln.gref_scalar;
     rnexp[p] = ln.nexp ? ln.nexp[i] : (float)ln.nexp_scalar;
-    {
+    if (rgpre) {
       // natural width of a predissociating upper state: HWHM 1/(4 pi c tau)
-      const double tau = st.tau ? st.tau[u] : 0.0;
+      const double tau = st.tau[u];
       rgpre[p] = (tau > 0.0 && tau < INFINITY) ? 1.0 / (4.0 * kPI * kC * tau) : 0.0;
     }
     ridx[p] = i;

@@ -149,7 +149,7 @@ struct GatherArgs {
   const double* rnu;
   const float* rgref;
   const float* rnexp;
-  const double* rgpre;
+  const double* rgpre;      // lifetime widths, or null when the states have no lifetimes
   const void* rS;
   const int32_t* rkc;       // home bin of every sorted line
   const float* rdel;        // nu - nu_{k_c}
@@ -240,7 +240,7 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
       c0 = S * (float)0.46971863934982566 * inv;           // sqrt(ln2/pi)/alpha
     } else {
       const float gamma = fmaf(g.rgref[p] * __builtin_amdgcn_exp2f(g.rnexp[p] * (float)(cd.lnTr / kLN2)),
-                               (float)cd.pfac, (float)g.rgpre[p]);
+                               (float)cd.pfac, g.rgpre ? (float)g.rgpre[p] : 0.0f);
       if (PROF == XS_LORENTZ) {
         inv = rcp32(gamma);
         c0 = S * (float)(1.0 / kPI) * inv;
@@ -289,7 +289,7 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
     if (S == 0.0) return kRowSkip;
     const double nu = g.rnu[p];
     const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
-    const LineParams lp = line_params<PROF>(m, cd, nu, (double)g.rgref[p], (double)g.rnexp[p], g.rgpre[p], S);
+    const LineParams lp = line_params<PROF>(m, cd, nu, (double)g.rgref[p], (double)g.rnexp[p], g.rgpre ? g.rgpre[p] : 0.0, S);
     const double a = m.dnu * lp.inv, b = delta * lp.inv;
     const double y2 = lp.y * lp.y;
     r.nu = nu;
@@ -390,7 +390,7 @@ __device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, int64_t p,
       c0 = S * (float)(0.5 / m.dnu);
     } else {
       const float gamma = fmaf(g.rgref[p] * __builtin_amdgcn_exp2f(g.rnexp[p] * (float)(cd.lnTr / kLN2)),
-                               (float)cd.pfac, (float)g.rgpre[p]);
+                               (float)cd.pfac, g.rgpre ? (float)g.rgpre[p] : 0.0f);
       if (BASE == XS_LORENTZ) {
         inv = rcp32(gamma);
         c0 = S * (float)(1.0 / (kPI * m.dnu));
@@ -442,7 +442,7 @@ __device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, int64_t p,
     const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
     double inv, y = 0.0, c0;
     const double gamma = (BASE == XS_LORENTZ || BASE == XS_VOIGT)
-                             ? (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac + g.rgpre[p]
+                             ? (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac + (g.rgpre ? g.rgpre[p] : 0.0)
                              : 0.0;
     if (BASE == XS_DOPPLER || BASE == XS_GAUSSIAN) {
       const double alpha = BASE == XS_GAUSSIAN ? cd.hwhm : nu * cd.dop;
@@ -531,7 +531,7 @@ __device__ int stage_line_pv(const GatherArgs& g, const CondDev& cd, int64_t p, 
   const double S = sizeof(Rec) == sizeof(RecF) ? (double)((const float*)g.rS)[(int64_t)cd.slot * g.max_lines + p]
                                                : ((const double*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
   if (S == 0.0) return kRowSkip;
-  const double gamma = (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac + g.rgpre[p];
+  const double gamma = (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac + (g.rgpre ? g.rgpre[p] : 0.0);
   const PVConst pc = pv_const(PROF, nu * cd.dop, gamma, S);
   const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
   const double a = m.dnu * pc.inv, b = delta * pc.inv;
@@ -1343,7 +1343,7 @@ struct ScatterArgs {
   const double* rnu;
   const float* rgref;
   const float* rnexp;
-  const double* rgpre;
+  const double* rgpre;      // lifetime widths, or null when the states have no lifetimes
   const void* rS;
   int64_t max_lines;
   double* sigma;
@@ -1368,7 +1368,7 @@ __global__ __launch_bounds__(256) void k_scatter(ScatterArgs g) {
                                  : ((const double*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
     if (S == 0.0) continue;
     const double scale = sizeof(Real) == 4 ? exp(g.sb[cd.slot]) : 1.0;
-    LineParams lp = line_params<PROF>(m, cd, nu, (double)g.rgref[p], (double)g.rnexp[p], g.rgpre[p], S);
+    LineParams lp = line_params<PROF>(m, cd, nu, (double)g.rgref[p], (double)g.rnexp[p], g.rgpre ? g.rgpre[p] : 0.0, S);
     double* out = g.sigma + (int64_t)c * m.n_bins;
     if constexpr (sizeof(Real) == 4) {
       ScatF r;
@@ -1448,7 +1448,7 @@ __global__ __launch_bounds__(256) void k_scatter_bin(ScatterArgs g) {
       inv = sqrt(kLN2) / (BASE == XS_GAUSSIAN ? cd.hwhm : nu * cd.dop);
       c0 = S * 0.5 / m.dnu;
     } else {
-      const double gamma = (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac + g.rgpre[p];
+      const double gamma = (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac + (g.rgpre ? g.rgpre[p] : 0.0);
       if (BASE == XS_LORENTZ) {
         inv = 1.0 / gamma;
         c0 = S / (kPI * m.dnu);
@@ -1525,7 +1525,7 @@ __global__ __launch_bounds__(256) void k_scatter_pv(ScatterArgs g) {
                                        : ((const double*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
     if (S == 0.0) continue;
     const double scale = sizeof(Real) == 4 ? exp(g.sb[cd.slot]) : 1.0;
-    const double gamma = (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac + g.rgpre[p];
+    const double gamma = (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac + (g.rgpre ? g.rgpre[p] : 0.0);
     const PVConst pc = pv_const(PROF, nu * cd.dop, gamma, S);
     double* out = g.sigma + (int64_t)c * m.n_bins;
     if constexpr (sizeof(Real) == 4) {

@@ -71,6 +71,7 @@ struct xs_plan {
   int64_t last_lines_in = 0;
   bool prepared = false;     // records of an xs_prepare are in the workspace
   std::vector<double> cf_T;  // temperatures of the last cooling-function call (upload source)
+  bool has_tau = false;      // the last xs_prepare had state lifetimes (records hold their widths)
 };
 
 namespace {
@@ -356,6 +357,14 @@ int upload(xs_plan* p) {
   return hip_check(hipStreamSynchronize(p->stream), "upload sync");
 }
 
+// The workspace as the kernels see it: without state lifetimes the records'
+// lifetime widths are neither written nor read.
+Work kernel_work(const xs_plan* p) {
+  Work w = p->w;
+  if (!p->has_tau) w.rgpre = nullptr;
+  return w;
+}
+
 // Everything up to the sorted records; returns XS_OK once enqueued.
 int preprocess(xs_plan* p, const xs_states* st, const xs_lines* ln) {
   const StatesView sv = view(st);
@@ -365,7 +374,8 @@ int preprocess(xs_plan* p, const xs_states* st, const xs_lines* ln) {
   launch_lines_pass1(p->md, p->w, sv, lv, p->stream);
   int32_t *sk = nullptr, *svv = nullptr;
   launch_radix_sort(p->md, p->w, lv.n, p->md.n_buckets, p->stream, &sk, &svv);
-  launch_offsets_records(p->md, p->w, sv, lv, sk ? sk : p->w.keyA, svv ? svv : p->w.valA, lv.n,
+  p->has_tau = st->lifetime != nullptr;
+  launch_offsets_records(p->md, kernel_work(p), sv, lv, sk ? sk : p->w.keyA, svv ? svv : p->w.valA, lv.n,
                          p->stream);
   p->last_lines_in = lv.n;
   p->prepared = true;
@@ -374,9 +384,9 @@ int preprocess(xs_plan* p, const xs_states* st, const xs_lines* ln) {
 
 int profile_pass(xs_plan* p, double* sigma, int accumulate) {
   if (p->model.algo == XS_SCATTER)
-    launch_scatter(p->md, p->w, sigma, accumulate, 0, p->stream);
+    launch_scatter(p->md, kernel_work(p), sigma, accumulate, 0, p->stream);
   else
-    launch_gather(p->md, p->w, p->tiling, sigma, accumulate, p->stream);
+    launch_gather(p->md, kernel_work(p), p->tiling, sigma, accumulate, p->stream);
   return hip_check(hipGetLastError(), "profile launch");
 }
 
@@ -584,7 +594,7 @@ int xs_profile_adjoint(xs_plan* p, const xs_states* st, const xs_lines* ln, cons
     return fail(XS_EUNSUPPORTED, "adjoint: binned and pseudo-Voigt profiles are not supported");
   if (!g || !dT || !dP || !dls) return fail(XS_EINVAL, "adjoint: dL_dsigma, dL_dT, dL_dP and dL_dlog_scale are required");
   if (ln->n != p->last_lines_in) return fail(XS_EINVAL, "adjoint: lines differ from the prepared ones");
-  launch_adjoint(p->md, p->w, view(st), view(ln), g, dT, dP, dgref, dnexp, dls, ln->n, p->stream);
+  launch_adjoint(p->md, kernel_work(p), view(st), view(ln), g, dT, dP, dgref, dnexp, dls, ln->n, p->stream);
   return hip_check(hipGetLastError(), "adjoint launch");
 }
 
@@ -599,7 +609,7 @@ int xs_cross_section_adjoint(xs_plan* p, const xs_states* st, const xs_lines* ln
     return fail(XS_EUNSUPPORTED, "adjoint: binned and pseudo-Voigt profiles are not supported");
   if (!g || !dT || !dP || !dls) return fail(XS_EINVAL, "adjoint: dL_dsigma, dL_dT, dL_dP and dL_dlog_scale are required");
   if ((rc = preprocess(p, st, ln))) return rc;
-  launch_adjoint(p->md, p->w, view(st), view(ln), g, dT, dP, dgref, dnexp, dls, ln->n, p->stream);
+  launch_adjoint(p->md, kernel_work(p), view(st), view(ln), g, dT, dP, dgref, dnexp, dls, ln->n, p->stream);
   return hip_check(hipGetLastError(), "adjoint launch");
 }
 

@@ -104,6 +104,7 @@ struct Work {
   float* rgref;             //                 gamma_ref
   float* rnexp;             //                 n_exp
   double* rgpre;            //                 lifetime HWHM of the upper state, 1/(4 pi c tau) or 0
+                            //                 (kernels get null when the states carry no lifetimes)
   int32_t* ridx;            //                 original line index
   int32_t* rkc;             //                 home bin k_c = rint((nu - nu0)/dnu)
   float* rdel;              //                 nu - nu_{k_c}
