@@ -622,6 +622,16 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
   constexpr bool F32 = sizeof(Real) == 4;
   constexpr int ROWB = 64 * M;
   __shared__ Rec srec[64];
+  // FP32 Voigt: the points of a core chunk with |z|^2 < 36 go to a queue and
+  // are evaluated 64 at a time by the rational approximation, their values
+  // added into a row buffer; the chunk's other lanes take three node pairs.
+  // Only these points need the approximation, while a core chunk spans 64
+  // points (about five times as many for the benchmark's lines).
+  constexpr bool CQ = F32 && PROF == XS_VOIGT;
+  constexpr int CQN = CQ ? 128 : 1;
+  __shared__ float cq_x[CQN], cq_y[CQN], cq_c[CQN];
+  __shared__ int cq_b[CQN];
+  __shared__ float rowbuf[CQ ? ROWB : 1];
 
   const int lane = threadIdx.x;
   const ModelDev& m = g.m;
@@ -664,7 +674,27 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
       acc64[j] = 0.0;
       acc32[j] = 0.0f;
       if (!F32) nuk[j] = nu_of_bin(m.nu0, m.dnu, my0 + 64 * j);
+      if constexpr (CQ) rowbuf[lane + 64 * j] = 0.0f;
     }
+    // ring of queued core points: qn entries from qh (wave-uniform).  The
+    // block is one wave, whose LDS accesses complete in issue order, so a
+    // compiler-level wave barrier orders the lanes' pushes and pops.
+    int qh = 0, qn = 0;
+    // evaluate the n (<= 64) oldest entries into the row buffer
+    auto cq_pop = [&](int n) {
+      if constexpr (CQ) {
+        __builtin_amdgcn_wave_barrier();
+        if (lane < n) {
+          const int e = (qh + lane) & (CQN - 1);
+          double wr, wi;
+          w_weideman<24>((double)cq_x[e], (double)cq_y[e], wr, wi);
+          atomicAdd(&rowbuf[cq_b[e]], (float)((double)cq_c[e] * wr));
+        }
+        __builtin_amdgcn_wave_barrier();
+        qh = (qh + n) & (CQN - 1);
+        qn -= n;
+      }
+    };
 
     for (int64_t p0 = q0; p0 < q1; p0 += 64) {
       // ---- stage: exact window test and class, compaction into LDS by class ----
@@ -1048,6 +1078,26 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
               v = pair_term<float>(rr.B1, u) + pair_term<float>(rr.B2, u);
             } else if (!meets(cl, ch, rD)) {
               v = gh3_f32(x * x, rr.y, rr.c0);
+            } else if constexpr (CQ) {
+              // a chunk that reaches |z| < 6: three node pairs where
+              // |z|^2 >= 36, the others queued for the rational approximation
+              const float u = x * x, y = rr.y;
+              const bool core = fmaf(y, y, u) < 36.0f;
+              const bool inwin = full || (k >= klo && k <= khi);
+              v = core ? 0.0f : gh3_f32(u, y, rr.c0);
+              const unsigned long long bal = __ballot(core && inwin);
+              if (bal) {
+                const int slot = (qh + qn + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                  __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u))) & (CQN - 1);
+                if (core && inwin) {
+                  cq_x[slot] = x;
+                  cq_y[slot] = y;
+                  cq_c[slot] = rr.c0;
+                  cq_b[slot] = k - row_lo;
+                }
+                qn += __popcll(bal);
+                if (qn >= 64) cq_pop(64);
+              }
             } else {
               // a chunk that reaches |z| < 6: every lane takes the rational
               // approximation (valid everywhere, so no divergence)
@@ -1154,6 +1204,14 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
       }
     }
 
+    if constexpr (CQ) {
+      // the queue's remaining points, then the row buffer into the sums
+      if (qn > 0) cq_pop(qn);
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < M; ++j) acc64[j] += (double)rowbuf[lane + 64 * j];
+      __syncthreads();
+    }
     // ---- write the tile, or this item's partial row ----
     if (nch == 1) {
       const double scale = F32 ? exp(g.sb[cd.slot]) : 1.0;
