@@ -321,6 +321,64 @@ def cooling_function(X, wl, ds, dl, lines):
                          "instr_per_term": CF_INSTR_PER_TERM}}
 
 
+def lifetime_voigt(X, wl, ds_plain, dl, n_lines, cfg, sampled_ms):
+    """The Voigt profile pass of the same 1e7 lines with predissociation
+    widths on a third of the states (lifetimes 10^U(-13,-10) s), FP32."""
+    import torch
+    import synth
+    synth.with_lifetimes(wl, frac=0.33, seed=5)
+    ds = X.DeviceStates.from_numpy(wl.states)
+    wl.states.lifetime = None
+    p = X.Plan(X.XS_VOIGT, X.XS_ABSORPTION, X.XS_LTE, X.XS_FP32, wl.grid, wl.conditions, n_lines,
+               mass_amu=wl.mass_amu)
+    p.set_config(**cfg)
+    sig = torch.empty((1, wl.grid.n_bins), dtype=torch.float64, device="cuda")
+    p.prepare(ds, dl)
+    p.profile(out=sig)
+    pairs = p.stats()["window_pairs"]
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        p.profile(out=sig)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    p.close()
+    log(f"lifetime Voigt f32: {ms:.2f} ms")
+    return {"lines": n_lines, "states_with_lifetimes": 0.33, "profile_pass_ms": round(ms, 3),
+            "evals_per_s": pairs / (ms / 1e3), "over_no_lifetimes": round(ms / sampled_ms, 3)}
+
+
+def density_2t(X, n_lines=50_000_000, n_chunks=5):
+    """Two-temperature emission lines of the streaming workload under custom
+    vibronic densities (one weight per manifold, T_rot only), resident, FP32:
+    prepare (Q(T_rot), intensities with the densities) + profile pass."""
+    import torch
+    import synth
+    wl = synth.with_vib_densities(synth.config(5, n_lines=n_lines, n_chunks=n_chunks))
+    sizes = wl.chunk_sizes()
+    ds = X.DeviceStates.from_numpy(wl.states)
+    dls = [X.DeviceLines.from_numpy(wl.chunk(j)) for j in range(n_chunks)]
+    plan = X.Plan(wl.profile, wl.mode, wl.population, X.XS_FP32, wl.grid, wl.conditions, max(sizes),
+                  mass_amu=wl.mass_amu)
+    sig = torch.zeros((len(wl.conditions), wl.grid.n_bins), dtype=torch.float64, device="cuda")
+    plan.cross_section(ds, dls[0], out=sig)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for j, dl in enumerate(dls):
+        plan.cross_section(ds, dl, out=sig, accumulate=j > 0)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    plan.close()
+    n = sum(sizes)
+    log(f"density 2T: {n} lines, {ms:.1f} ms")
+    return {"lines": n, "chunks": n_chunks, "conditions": len(wl.conditions), "ms_resident": round(ms, 2),
+            "line_conditions_per_s": n * len(wl.conditions) / (ms / 1e3)}
+
+
 def stream_2t(X, n_lines=50_000_000, n_chunks=5):
     """Chunk streaming of the two-temperature emission workload (4 (T_vib,
     T_rot) pairs, Doppler at T_rot, grid 0-30000 cm^-1 step 0.05): chunks held
@@ -448,9 +506,11 @@ def main():
         extras["gather_over_scatter_speedup_f32"] = round(extras["scatter_f32"]["profile_pass_ms"] / per32["forward"], 2)
         extras["binned_voigt"] = binned_voigt(X, wl, ds, dl, lines.n, cfg, per32["forward"])
         extras["pseudo_voigt"] = pseudo_voigt(X, wl, ds, dl, lines.n, cfg, per32["forward"])
+        extras["lifetime_voigt"] = lifetime_voigt(X, wl, ds, dl, lines.n, cfg, per32["forward"])
         extras["cooling_function"] = cooling_function(X, wl, ds, dl, lines)
         extras["batched_48"] = batched_48(X, wl, ds, dl, lines.n)
         extras["stream_2t"] = stream_2t(X)
+        extras["density_2t"] = density_2t(X)
 
     # roofline of the dominant kernel (events around each launch, same stream)
     fracs = region_fractions(wl, lines, cond)
