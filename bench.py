@@ -54,7 +54,7 @@ FLOP_REGIONS = {
     ("adj", "f32"): [(900.0, 27), (64.0, 54), (0.0, 216)],
     ("adj", "f64"): [(9.0e6, 27), (6400.0, 54), (400.0, 78), (144.0, 113), (64.0, 161), (0.0, 328)],
 }
-# MI355X vector peaks, no packed-FP32 (packed FP32 is disabled in this build):
+# MI355X vector peaks, no packed-FP32 (the kernels are compiled without packed FP32):
 # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP32
 # and FP64 alike.  The published 157.3 TFLOP/s FP32 figure needs packed math.
 PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
@@ -279,7 +279,7 @@ def binned_voigt(X, wl, ds, dl, n_lines, cfg, sampled_ms):
 
 
 # Cooling-function reduction: VALU instructions per (item, temperature) term
-# in k_cf_sum (gfx950 assembly of this build: the FP64 exp is a rounding
+# in k_cf_sum (its compiled gfx950 assembly: the FP64 exp is a rounding
 # argument reduction, a degree-11 polynomial, ldexp and range selects, 21
 # instructions, plus the exponent product and the accumulating FMA).  Peak
 # issue: 256 CU x 64 lanes x 2.4 GHz = 39.3e12 lane-instructions/s (FP64 FMA

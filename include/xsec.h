@@ -45,7 +45,7 @@ typedef enum {
   XS_ENOMEM = -2,       /* a host allocation failed */
   XS_EDEVICE = -3,      /* a HIP runtime call or an enqueued kernel failed */
   XS_EWORKSPACE = -4,   /* no workspace bound, or the bound one is too small */
-  XS_EUNSUPPORTED = -5  /* a valid combination this build does not implement */
+  XS_EUNSUPPORTED = -5  /* a valid combination this library does not implement */
 } xs_status;
 
 /* Line profile (Table tab:profile): Doppler (width from T, nu, mass); Gaussian
