@@ -418,6 +418,71 @@ def stream_2t(X, n_lines=50_000_000, n_chunks=5):
     return out
 
 
+def full_configs(X):
+    """The batched opacity grid (48 conditions) at its full 1e8 lines in one
+    captured graph, FP32 and FP64; and the two-temperature emission workload
+    at its full 1e9 lines, streamed from host memory in 10 chunks of 1e8
+    (chunks generated into host memory first), FP32."""
+    import torch
+    import synth
+    out = {}
+    wl = synth.config(3)
+    t0 = time.perf_counter()
+    ln = wl.lines()
+    log(f"batched: generated {ln.n} lines in {time.perf_counter() - t0:.1f} s")
+    ds = X.DeviceStates.from_numpy(wl.states)
+    dl = X.DeviceLines.from_numpy(ln)
+    del ln
+    res = {"lines": wl.n_lines, "conditions": len(wl.conditions)}
+    for prec, name in ((X.XS_FP32, "f32"), (X.XS_FP64, "f64")):
+        p = X.Plan(X.XS_VOIGT, X.XS_ABSORPTION, X.XS_LTE, prec, wl.grid, wl.conditions, wl.n_lines,
+                   mass_amu=wl.mass_amu)
+        sig = torch.empty((len(wl.conditions), wl.grid.n_bins), dtype=torch.float64, device="cuda")
+        p.capture(ds, dl, sig)
+        p.replay()
+        torch.cuda.synchronize()
+        pairs = p.stats()["window_pairs"]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        p.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        res[name] = {"ms": round(ms, 1), "window_pairs": pairs, "evals_per_s": pairs / (ms / 1e3),
+                     "line_conditions_per_s": wl.n_lines * len(wl.conditions) / (ms / 1e3)}
+        log(f"batched 1e8 {name}: {ms:.0f} ms, {pairs:.3e} pairs")
+        p.close()
+        del sig
+    res["fp32_over_fp64_speedup"] = round(res["f64"]["ms"] / res["f32"]["ms"], 3)
+    out["batched_48_full"] = res
+    del dl, ds
+    torch.cuda.empty_cache()
+    wl = synth.config(5)
+    sizes = wl.chunk_sizes()
+    t0 = time.perf_counter()
+    chunks = []
+    for j in range(wl.n_chunks):
+        chunks.append(wl.chunk(j))
+        log(f"stream: chunk {j} generated ({time.perf_counter() - t0:.1f} s)")
+    ds = X.DeviceStates.from_numpy(wl.states)
+    plan = X.Plan(wl.profile, wl.mode, wl.population, X.XS_FP32, wl.grid, wl.conditions, max(sizes),
+                  mass_amu=wl.mass_amu)
+    sig = torch.zeros((len(wl.conditions), wl.grid.n_bins), dtype=torch.float64, device="cuda")
+    st = X.ChunkStreamer(plan, max(sizes))
+    st.run(ds, chunks[:1], sig)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = st.run(ds, chunks, sig)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    out["stream_2t_full"] = {"lines": n, "chunks": len(chunks), "conditions": len(wl.conditions),
+                             "ms_streamed": round(ms, 1),
+                             "line_conditions_per_s": n * len(wl.conditions) / (ms / 1e3)}
+    log(f"stream 1e9: {ms:.0f} ms")
+    plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -427,6 +492,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and scatter comparisons")
     ap.add_argument("--n-lines", type=int, default=None, help="(testing) fewer lines")
     ap.add_argument("--calib-copy", action="store_true", help="run only a 1 GiB device copy (PMC calibration)")
+    ap.add_argument("--full-configs", action="store_true",
+                    help="run only the batched 48-condition grid at 1e8 lines and the two-temperature "
+                         "emission stream at 1e9 lines (minutes; prints their own JSON line)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -449,6 +517,10 @@ def main():
 
     import synth
     import paper_2609_17273_amd as X
+
+    if args.full_configs:
+        print(json.dumps(full_configs(X)), flush=True)
+        return
 
     t_gen = time.perf_counter()
     wl = synth.config(2, n_lines=args.n_lines)

@@ -238,12 +238,19 @@ struct WM<40> {
   static constexpr double b[40] = XS_WM40_B;
 };
 
+// 1/d by the hardware FP64 reciprocal (relative error below 5e-8 on gfx950)
+// and one Newton step (below 3e-15).
+__device__ __forceinline__ double rcp_nr(double d) {
+  const double r = __builtin_amdgcn_rcp(d);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
 template <int N>
 __device__ __forceinline__ void w_weideman(double x, double y, double& wr, double& wi) {
   constexpr double L = WM<N>::L;
   // q = 1/((L + y) - i x) = ((L + y) + i x) / D
   const double lr = L + y;
-  const double iD = 1.0 / fma(lr, lr, x * x);
+  const double iD = rcp_nr(fma(lr, lr, x * x));
   const double qr = lr * iD, qi = x * iD;
   // Z = ((L - y) + i x) q
   const double ly = L - y;
@@ -402,7 +409,7 @@ template <int N>
 __device__ __forceinline__ double w_int_im(double x, double y) {
   constexpr double L = WM<N>::L;
   const double lr = L + y;
-  const double iD = 1.0 / fma(lr, lr, x * x);
+  const double iD = rcp_nr(fma(lr, lr, x * x));
   const double qr = lr * iD, qi = x * iD;
   const double ly = L - y;
   const double Zr = fma(ly, qr, -x * qi), Zi = fma(ly, qi, x * qr);

@@ -189,13 +189,14 @@ __device__ __forceinline__ void tile_candidates(const GatherArgs& g, const CondD
 __device__ __forceinline__ float rcp32(float d) { return __builtin_amdgcn_rcpf(d); }
 
 // Bin range where |x| < X, relative to k_c, in FP32 (the one-bin margin
-// covers the rounding of a, b and of the quotient), clipped to the window.
+// covers the rounding of a, b and of the quotient, whose reciprocal is the
+// hardware's, within 1 ulp), clipped to the window.
 __device__ __forceinline__ KRange x_range_f(float X, float a, float b, int kc, int klo, int khi) {
   KRange r;
   r.lo = 0x7fffffff;
   r.hi = -0x7fffffff;
   if (!(X > 0.0f)) return r;
-  const float ra = 1.0f / a;
+  const float ra = rcp32(a);
   const float lo = fminf(fmaxf(floorf((b - X) * ra) - 1.0f, -1.0e9f), 1.0e9f);
   const float hi = fminf(fmaxf(ceilf((b + X) * ra) + 1.0f, -1.0e9f), 1.0e9f);
   const int l = max((int)lo + kc, klo - 1), h = min((int)hi + kc, khi + 1);
@@ -271,15 +272,18 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
         return Pair<float>{cw, cw * p2, 2.0f * y2 - 2.0f * (float)tau, p2 * p2};
       };
       r.A = make(GH::t2[0], GH::w2[0]);
-      r.B1 = make(GH::t4[0], GH::w4[0]);
-      r.B2 = make(GH::t4[1], GH::w4[1]);
       r.rB = x_range_f(sqrtf(fmaxf(900.9f - y2, 0.0f)), a, b, kc, klo, khi);
-      r.rC = x_range_f(sqrtf(fmaxf(64.064f - y2, 0.0f)), a, b, kc, klo, khi);
-      r.rD = x_range_f(sqrtf(fmaxf(36.036f - y2, 0.0f)), a, b, kc, klo, khi);
       // FP32 keeps u (u + q) + p^2 finite for |x|, y < ~1e9; lines beyond that
       // (nu of a few 1e-3 cm^-1 or less) are evaluated in FP64.
       const float xmax = fmaxf(fabsf((float)(klo - kc) * a - b), fabsf((float)(khi - kc) * a - b));
       if (!(xmax <= 1.0e9f) || !(y <= 1.0e9f)) r.flag = 1;
+      // a row in the one-pair region needs nothing more (lines are sorted by
+      // home bin, so whole batches far from the tile stop here together)
+      if (!r.flag && !meets(lo, hi, r.rB)) return inside ? kRowF1 : kRowF1M;
+      r.B1 = make(GH::t4[0], GH::w4[0]);
+      r.B2 = make(GH::t4[1], GH::w4[1]);
+      r.rC = x_range_f(sqrtf(fmaxf(64.064f - y2, 0.0f)), a, b, kc, klo, khi);
+      r.rD = x_range_f(sqrtf(fmaxf(36.036f - y2, 0.0f)), a, b, kc, klo, khi);
       n1 = r.rB;
       n2 = r.rC;
       can2 = true;
@@ -305,9 +309,10 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
       gauss = true;
     } else if (PROF == XS_VOIGT) {
       r.A = make_pair<double>(lp.c0, lp.y, GH::t2[0], GH::w2[0]);
+      r.r[0] = xr(9.0e6 * 1.001);
+      if (!meets(lo, hi, r.r[0])) return inside ? kRowF1 : kRowF1M;  // one-pair row
       r.B1 = make_pair<double>(lp.c0, lp.y, GH::t4[0], GH::w4[0]);
       r.B2 = make_pair<double>(lp.c0, lp.y, GH::t4[1], GH::w4[1]);
-      r.r[0] = xr(9.0e6 * 1.001);
       r.r[1] = xr(6400.0 * 1.001);
       r.r[2] = xr(400.0 * 1.001);
       r.r[3] = xr(144.0 * 1.001);
@@ -424,11 +429,15 @@ __device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, int64_t p,
         const float y2 = y * y;
         auto X = [&](float rho) { return rho > y2 ? sqrtf(rho - y2) + hh : 0.0f; };
         r.rB = x_range_f(X(900.9f), a, b, kc, klo, khi);
-        r.rC = x_range_f(X(64.064f), a, b, kc, klo, khi);
-        r.rD = x_range_f(X(36.036f), a, b, kc, klo, khi);
         const float xmax = fmaxf(fabsf((float)(klo - kc) * a - b), fabsf((float)(khi - kc) * a - b)) + hh;
         if (!(xmax <= 1.0e9f) || !(y <= 1.0e9f)) r.flag = 1;
         nt1 = terms(row_t(xr0, xr1, hh, y, GH::s2[0]), true);
+        if (!r.flag && nt1 && !meets(lo, hi, r.rB)) {  // a one-pair row: nothing more needed
+          r.pad0 = nt1;
+          return inside ? kRowF1 : kRowF1M;
+        }
+        r.rC = x_range_f(X(64.064f), a, b, kc, klo, khi);
+        r.rD = x_range_f(X(36.036f), a, b, kc, klo, khi);
         nt2 = terms(row_t(xr0, xr1, hh, y, GH::s4[1]), true);
         n1 = nt1 ? r.rB : all;
         n2 = nt2 ? r.rC : all;
