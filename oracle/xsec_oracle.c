@@ -620,7 +620,7 @@ int or_sigma(int64_t nl, const double* nu, const double* S, const double* alpha,
     if (nu[i] > 0.0) { keys[m].nu = nu[i]; keys[m].i = i; ++m; }
   qsort(keys, (size_t)m, sizeof(or_key), or_key_cmp);
   const int64_t nq = bins ? n_out : n_bins;
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 1)
   for (int64_t q = 0; q < nq; ++q) {
     int64_t k = bins ? bins[q] : q;
     double nuk = or_nu_k(nu0, dnu, k);

@@ -141,6 +141,10 @@ struct __attribute__((aligned(16))) RecD {
   int pad0, pad1;
 };
 
+// the staging precision of a record type
+template <typename Rec>
+using LReal = typename std::conditional<sizeof(Rec) == sizeof(RecF), float, double>::type;
+
 struct GatherArgs {
   ModelDev m;
   const CondDev* cond;
@@ -207,18 +211,52 @@ __device__ __forceinline__ KRange x_range_f(float X, float a, float b, int kc, i
   return r;
 }
 
+// Per-line inputs of the staging for one condition.  They are loaded in one
+// round (the window test does not wait for its own load before the rest are
+// issued), and for the narrow Gaussians one batch ahead of their use.
+template <typename Real>
+struct LineIn {
+  int2 win;     // exact window of the line's cut-off class
+  int kc;       // home bin
+  float del;    // FP32 form: nu - nu_{k_c}
+  double nu;
+  Real S;       // intensity (FP32 form: scaled)
+  float gref, nexp;
+  double gpre;  // lifetime width, 0 without lifetimes
+};
+template <typename Real, int PROF>
+__device__ __forceinline__ LineIn<Real> load_line(const GatherArgs& g, const CondDev& cd, int64_t p) {
+  constexpr int B = base_profile(PROF);
+  LineIn<Real> in;
+  in.win = ((const int2*)g.rwin)[(int64_t)cd.cclass * g.max_lines + p];
+  in.kc = g.rkc[p];
+  in.nu = g.rnu[p];
+  in.S = ((const Real*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
+  in.del = sizeof(Real) == 4 ? g.rdel[p] : 0.0f;
+  if constexpr (B == XS_LORENTZ || B == XS_VOIGT) {
+    in.gref = g.rgref[p];
+    in.nexp = g.rnexp[p];
+    in.gpre = g.rgpre ? g.rgpre[p] : 0.0;
+  } else {
+    in.gref = 0.0f;
+    in.nexp = 0.0f;
+    in.gpre = 0.0;
+  }
+  return in;
+}
+
 // Staging: does line p touch bins [tlo, thi] under condition cd?  Fills the
 // record and returns its class for the tile row [tlo, tlo + rowb - 1].  The
 // line's home bin and exact window come from the record pass; the FP32 form
 // derives its constants in FP32 (relative error a few units of 1e-7, far
 // inside its tolerance), the FP64 form in FP64.
 template <typename Rec, int PROF>
-__device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int64_t tlo,
+__device__ int stage_line(const GatherArgs& g, const CondDev& cd, const LineIn<LReal<Rec>>& in, int64_t tlo,
                           int64_t thi, int rowb, Rec& r) {
   const ModelDev& m = g.m;
-  const int2 win = ((const int2*)g.rwin)[(int64_t)cd.cclass * g.max_lines + p];
+  const int2 win = in.win;
   if (win.x > win.y || win.y < tlo || win.x > thi) return kRowSkip;
-  const int kc = g.rkc[p];
+  const int kc = in.kc;
   const int klo = max(win.x, (int)tlo), khi = min(win.y, (int)thi);
   r.klo = klo;
   r.khi = khi;
@@ -231,17 +269,17 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
   KRange nz = KRange{klo, khi}, n1 = KRange{0x7fffffff, -0x7fffffff}, n2 = n1;
   bool can2 = false, gauss = false;
   if constexpr (sizeof(Rec) == sizeof(RecF)) {
-    const float S = ((const float*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
+    const float S = in.S;
     if (S == 0.0f) return kRowSkip;
-    const float nu = (float)g.rnu[p];
+    const float nu = (float)in.nu;
     float inv, y = 0.0f, c0;
     if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
       const float alpha = PROF == XS_GAUSSIAN ? (float)cd.hwhm : nu * (float)cd.dop;
       inv = rcp32(alpha);
       c0 = S * (float)0.46971863934982566 * inv;           // sqrt(ln2/pi)/alpha
     } else {
-      const float gamma = fmaf(g.rgref[p] * __builtin_amdgcn_exp2f(g.rnexp[p] * (float)(cd.lnTr / kLN2)),
-                               (float)cd.pfac, g.rgpre ? (float)g.rgpre[p] : 0.0f);
+      const float gamma = fmaf(in.gref * __builtin_amdgcn_exp2f(in.nexp * (float)(cd.lnTr / kLN2)),
+                               (float)cd.pfac, (float)in.gpre);
       if (PROF == XS_LORENTZ) {
         inv = rcp32(gamma);
         c0 = S * (float)(1.0 / kPI) * inv;
@@ -251,7 +289,7 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
         c0 = S * (float)0.56418958354775628 * inv;         // 1/(sg sqrt(2 pi))
       }
     }
-    const float a = (float)m.dnu * inv, b = g.rdel[p] * inv;
+    const float a = (float)m.dnu * inv, b = in.del * inv;
     r.a = a;
     r.nb = -b;
     r.jfb = (float)(lo - kc);  // integer, exact in FP32 within a window
@@ -289,11 +327,11 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
       can2 = true;
     }
   } else {
-    const double S = ((const double*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
+    const double S = in.S;
     if (S == 0.0) return kRowSkip;
-    const double nu = g.rnu[p];
+    const double nu = in.nu;
     const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
-    const LineParams lp = line_params<PROF>(m, cd, nu, (double)g.rgref[p], (double)g.rnexp[p], g.rgpre ? g.rgpre[p] : 0.0, S);
+    const LineParams lp = line_params<PROF>(m, cd, nu, (double)in.gref, (double)in.nexp, in.gpre, S);
     const double a = m.dnu * lp.inv, b = delta * lp.inv;
     const double y2 = lp.y * lp.y;
     r.nu = nu;
@@ -347,13 +385,13 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, int64_t p, int
 // band: with the band's nearest |x| = sqrt(rho - y^2), the denominators
 // y^2 + (x_a -+ s)(x_b -+ s) are at least dmin below.
 template <typename Rec, int PROF>
-__device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, int64_t p, int64_t tlo,
+__device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, const LineIn<LReal<Rec>>& in, int64_t tlo,
                               int64_t thi, int rowb, Rec& r) {
   constexpr int BASE = PROF - 4;
   const ModelDev& m = g.m;
-  const int2 win = ((const int2*)g.rwin)[(int64_t)cd.cclass * g.max_lines + p];
+  const int2 win = in.win;
   if (win.x > win.y || win.y < tlo || win.x > thi) return kRowSkip;
-  const int kc = g.rkc[p];
+  const int kc = in.kc;
   const int klo = max(win.x, (int)tlo), khi = min(win.y, (int)thi);
   r.klo = klo;
   r.khi = khi;
@@ -385,17 +423,17 @@ __device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, int64_t p,
   };
   int nt1 = 0, nt2 = 0, nt3 = 0;
   if constexpr (sizeof(Rec) == sizeof(RecF)) {
-    const float S = ((const float*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
+    const float S = in.S;
     if (S == 0.0f) return kRowSkip;
-    const float nu = (float)g.rnu[p];
+    const float nu = (float)in.nu;
     float inv, y = 0.0f, c0;
     if (BASE == XS_DOPPLER || BASE == XS_GAUSSIAN) {
       const float alpha = BASE == XS_GAUSSIAN ? (float)cd.hwhm : nu * (float)cd.dop;
       inv = (float)0.83255461115769776 * rcp32(alpha);  // sqrt(ln2)/alpha
       c0 = S * (float)(0.5 / m.dnu);
     } else {
-      const float gamma = fmaf(g.rgref[p] * __builtin_amdgcn_exp2f(g.rnexp[p] * (float)(cd.lnTr / kLN2)),
-                               (float)cd.pfac, g.rgpre ? (float)g.rgpre[p] : 0.0f);
+      const float gamma = fmaf(in.gref * __builtin_amdgcn_exp2f(in.nexp * (float)(cd.lnTr / kLN2)),
+                               (float)cd.pfac, (float)in.gpre);
       if (BASE == XS_LORENTZ) {
         inv = rcp32(gamma);
         c0 = S * (float)(1.0 / (kPI * m.dnu));
@@ -405,7 +443,7 @@ __device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, int64_t p,
         c0 = S * (float)(0.56418958354775628 / m.dnu);  // 1/(sqrt(pi) dnu)
       }
     }
-    const float a = (float)m.dnu * inv, b = g.rdel[p] * inv, hh = 0.5f * a;
+    const float a = (float)m.dnu * inv, b = in.del * inv, hh = 0.5f * a;
     r.a = a;
     r.nb = -b;
     r.jfb = (float)(lo - kc);
@@ -445,13 +483,13 @@ __device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, int64_t p,
       }
     }
   } else {
-    const double S = ((const double*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
+    const double S = in.S;
     if (S == 0.0) return kRowSkip;
-    const double nu = g.rnu[p];
+    const double nu = in.nu;
     const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
     double inv, y = 0.0, c0;
     const double gamma = (BASE == XS_LORENTZ || BASE == XS_VOIGT)
-                             ? (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac + (g.rgpre ? g.rgpre[p] : 0.0)
+                             ? (double)in.gref * exp((double)in.nexp * cd.lnTr) * cd.pfac + in.gpre
                              : 0.0;
     if (BASE == XS_DOPPLER || BASE == XS_GAUSSIAN) {
       const double alpha = BASE == XS_GAUSSIAN ? cd.hwhm : nu * cd.dop;
@@ -523,12 +561,12 @@ __device__ int stage_line_bin(const GatherArgs& g, const CondDev& cd, int64_t p,
 // rB / r[0] = bins where the Gaussian part 2^{-x^2} is not zero in the
 // precision.  First class: rows where only the Lorentzian part is left.
 template <typename Rec, int PROF>
-__device__ int stage_line_pv(const GatherArgs& g, const CondDev& cd, int64_t p, int64_t tlo,
+__device__ int stage_line_pv(const GatherArgs& g, const CondDev& cd, const LineIn<LReal<Rec>>& in, int64_t tlo,
                              int64_t thi, int rowb, Rec& r) {
   const ModelDev& m = g.m;
-  const int2 win = ((const int2*)g.rwin)[(int64_t)cd.cclass * g.max_lines + p];
+  const int2 win = in.win;
   if (win.x > win.y || win.y < tlo || win.x > thi) return kRowSkip;
-  const int kc = g.rkc[p];
+  const int kc = in.kc;
   const int klo = max(win.x, (int)tlo), khi = min(win.y, (int)thi);
   r.klo = klo;
   r.khi = khi;
@@ -536,11 +574,10 @@ __device__ int stage_line_pv(const GatherArgs& g, const CondDev& cd, int64_t p, 
   r.kc = kc;
   const int lo = (int)tlo, hi = lo + rowb - 1;
   const bool inside = klo <= lo && khi >= hi;
-  const double nu = g.rnu[p];
-  const double S = sizeof(Rec) == sizeof(RecF) ? (double)((const float*)g.rS)[(int64_t)cd.slot * g.max_lines + p]
-                                               : ((const double*)g.rS)[(int64_t)cd.slot * g.max_lines + p];
+  const double nu = in.nu;
+  const double S = (double)in.S;
   if (S == 0.0) return kRowSkip;
-  const double gamma = (double)g.rgref[p] * exp((double)g.rnexp[p] * cd.lnTr) * cd.pfac + (g.rgpre ? g.rgpre[p] : 0.0);
+  const double gamma = (double)in.gref * exp((double)in.nexp * cd.lnTr) * cd.pfac + in.gpre;
   const PVConst pc = pv_const(PROF, nu * cd.dop, gamma, S);
   const double delta = nu - nu_of_bin(m.nu0, m.dnu, kc);
   const double a = m.dnu * pc.inv, b = delta * pc.inv;
@@ -641,6 +678,13 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
   __shared__ float cq_x[CQN], cq_y[CQN], cq_c[CQN];
   __shared__ int cq_b[CQN];
   __shared__ float rowbuf[CQ ? ROWB : 1];
+  // Gaussian lines narrower than the tile (the usual Doppler case: a few
+  // tens of nonzero points) add their nonzero points into an LDS row instead
+  // of testing every chunk of the row per line: one line per lane where it
+  // has at most kLaneSpan such points, else 64 points per wave step.
+  constexpr bool GN = PROF == XS_DOPPLER || PROF == XS_GAUSSIAN;
+  constexpr int kLaneSpan = 96;
+  __shared__ Real gbuf[GN ? ROWB : 1];
 
   const int lane = threadIdx.x;
   const ModelDev& m = g.m;
@@ -684,6 +728,7 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
       acc32[j] = 0.0f;
       if (!F32) nuk[j] = nu_of_bin(m.nu0, m.dnu, my0 + 64 * j);
       if constexpr (CQ) rowbuf[lane + 64 * j] = 0.0f;
+      if constexpr (GN) gbuf[lane + 64 * j] = (Real)0;
     }
     // ring of queued core points: qn entries from qh (wave-uniform).  The
     // block is one wave, whose LDS accesses complete in issue order, so a
@@ -704,6 +749,46 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
         qn -= n;
       }
     };
+    // general-class Gaussian lines wider than kLaneSpan points: the points of
+    // the row inside both the window and the range where 2^{-x^2} is not
+    // zero, 64 at a time; every point outside that range would add an exact
+    // zero.  Within one wave the LDS adds of successive lines complete in
+    // issue order.
+    auto gauss_rows = [&](int l0, int l1) {
+      if constexpr (GN) {
+        for (int l = l0; l < l1; ++l) {
+          const Rec& rr = srec[l];
+          int kl, kh;
+          if constexpr (F32) {
+            kl = max(uni(rr.klo), uni(rr.rB.lo));
+            kh = min(uni(rr.khi), uni(rr.rB.hi));
+          } else {
+            kl = max(uni(rr.klo), uni(rr.r[0].lo));
+            kh = min(uni(rr.khi), uni(rr.r[0].hi));
+          }
+          kl = max(kl, row_lo);
+          kh = min(kh, row_lo + ROWB - 1);
+          for (int k0 = kl; k0 <= kh; k0 += 64) {
+            const int k = k0 + lane;
+            if (k <= kh) {
+              Real v;
+              if constexpr (F32) {
+                const float x = fmaf(rr.jfb + (float)(k - row_lo), rr.a, rr.nb);
+                v = rr.c0 * __builtin_amdgcn_exp2f(-(x * x));
+              } else {
+                double x;
+                {
+#pragma clang fp contract(off)
+                  x = (nu_of_bin(m.nu0, m.dnu, k) - rr.nu) * rr.inv;
+                }
+                v = rr.c0 * exp2(-(x * x));
+              }
+              atomicAdd(&gbuf[k - row_lo], v);
+            }
+          }
+        }
+      }
+    };
 
     for (int64_t p0 = q0; p0 < q1; p0 += 64) {
       // ---- stage: exact window test and class, compaction into LDS by class ----
@@ -711,9 +796,57 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
       int cls = kRowSkip;
       const int64_t p = p0 + lane;
       if (p < q1) {
-        if constexpr (PROF >= XS_PV_THOMPSON) cls = stage_line_pv<Rec, PROF>(g, cd, p, tlo, thi, ROWB, r);
-        else if constexpr (PROF >= XS_BIN_DOPPLER) cls = stage_line_bin<Rec, PROF>(g, cd, p, tlo, thi, ROWB, r);
-        else cls = stage_line<Rec, PROF>(g, cd, p, tlo, thi, ROWB, r);
+        const LineIn<Real> in = load_line<Real, PROF>(g, cd, p);
+        if constexpr (PROF >= XS_PV_THOMPSON) cls = stage_line_pv<Rec, PROF>(g, cd, in, tlo, thi, ROWB, r);
+        else if constexpr (PROF >= XS_BIN_DOPPLER) cls = stage_line_bin<Rec, PROF>(g, cd, in, tlo, thi, ROWB, r);
+        else cls = stage_line<Rec, PROF>(g, cd, in, tlo, thi, ROWB, r);
+      }
+      if constexpr (GN) {
+        // A narrow Gaussian (at most kLaneSpan nonzero points in the row)
+        // stays on its lane, which adds its points into the LDS row; each
+        // lane starts at its own offset within its points so that lanes of
+        // neighbouring lines rarely add to one point in the same step.
+        // Wider ones take the wave-wide path below.
+        int kl = 0, n = 0;
+        if (cls == kRowGeneral) {
+          KRange R;
+          if constexpr (F32) R = r.rB;
+          else R = r.r[0];
+          kl = max(r.klo, R.lo);
+          n = min(r.khi, R.hi) - kl + 1;
+          if (n <= kLaneSpan) cls = kRowSkip;
+          else n = 0;
+        }
+        if (__ballot(n > 0)) {
+          int i = n > 0 ? lane % n : 0;
+          for (int it = 0; it < n; ++it) {
+            const int k = kl + i;
+            Real v;
+            if constexpr (F32) {
+              const float x = fmaf(r.jfb + (float)(k - row_lo), r.a, r.nb);
+              v = r.c0 * __builtin_amdgcn_exp2f(-(x * x));
+            } else {
+              double x;
+              {
+#pragma clang fp contract(off)
+                x = (nu_of_bin(m.nu0, m.dnu, k) - r.nu) * r.inv;
+              }
+              v = r.c0 * exp2(-(x * x));
+            }
+            atomicAdd(&gbuf[k - row_lo], v);
+            i = (i + 1 == n) ? 0 : i + 1;
+          }
+          if constexpr (F32) {
+            // at most one line per lane went into this batch's FP32 row
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+              acc64[j] += (double)gbuf[lane + 64 * j];
+              gbuf[lane + 64 * j] = 0.0f;
+            }
+            __syncthreads();
+          }
+        }
       }
       // LDS order: F1 | F1M | F2 | F2M | F3 | F3M (FP64) | general
       const unsigned long long b1 = __ballot(cls == kRowF1);
@@ -1054,7 +1187,8 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
           second(e2, e2m, std::true_type());
         }
         // ---- general path: per-chunk decisions ----
-        for (int l = e3m; l < eg; ++l) {
+        if constexpr (GN) gauss_rows(e3m, eg);
+        else for (int l = e3m; l < eg; ++l) {
           const RecF& rr = srec[l];
           const float a = rr.a, nb = rr.nb, jf0 = rr.jfb + lane_off;
           const int klo = uni(rr.klo), khi = uni(rr.khi);
@@ -1122,6 +1256,17 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
           acc64[j] += (double)acc32[j];
           acc32[j] = 0.0f;
         }
+        if constexpr (GN) {
+          if (eg > e3m) {
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+              acc64[j] += (double)gbuf[lane + 64 * j];
+              gbuf[lane + 64 * j] = 0.0f;
+            }
+            __syncthreads();
+          }
+        }
       } else {
         // FP64 form: x from the exact difference nu_k - nu_i
         auto uniform = [&](int l0, int l1, auto masked, auto npairs) {
@@ -1170,7 +1315,8 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
           uniform(e2m, e3, std::false_type(), P3());
           uniform(e3, e3m, std::true_type(), P3());
         }
-        for (int l = e3m; l < eg; ++l) {
+        if constexpr (GN) gauss_rows(e3m, eg);
+        else for (int l = e3m; l < eg; ++l) {
           const RecD& rr = srec[l];
           const double nu = rr.nu, inv = rr.inv;
           const int klo = uni(rr.klo), khi = uni(rr.khi);
@@ -1213,6 +1359,12 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
       }
     }
 
+    if constexpr (GN && !F32) {
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < M; ++j) acc64[j] += gbuf[lane + 64 * j];
+      __syncthreads();
+    }
     if constexpr (CQ) {
       // the queue's remaining points, then the row buffer into the sums
       if (qn > 0) cq_pop(qn);

@@ -257,6 +257,17 @@ void derive(xs_plan* p) {
     cd.pfac = c.P / m.P_ref;
     cd.slot = slot;
     cd.wbins = (int32_t)std::ceil(c.cutoff / p->grid.dnu) + 2;
+    if (m.profile == XS_DOPPLER || m.profile == XS_GAUSSIAN) {
+      // 2^{-(dnu/alpha)^2} is exactly zero in the working precision once
+      // (dnu/alpha)^2 exceeds 160 (FP32) or 1100 (FP64), and a kept line has
+      // nu <= grid end + cut-off, so no line reaches a tile from farther
+      // than X alpha_max: the gather need not stage it.
+      const double X = (m.precision == XS_FP32) ? std::sqrt(160.0) : std::sqrt(1100.0);
+      const double nu_end = p->grid.nu0 + (double)(p->grid.n_bins - 1) * p->grid.dnu;
+      const double amax = (m.profile == XS_GAUSSIAN) ? m.hwhm_fixed : (nu_end + c.cutoff) * cd.dop;
+      const double reach = std::ceil(X * amax / p->grid.dnu) + 2.0;
+      if (std::isfinite(reach) && reach < (double)cd.wbins) cd.wbins = (int32_t)reach;
+    }
     maxcut = std::max(maxcut, c.cutoff);
     int cc = -1;
     for (size_t q = 0; q < p->cut_class.size(); ++q)

@@ -38,7 +38,7 @@ struct CondDev {
   double lnTr;    // ln(T_ref / Tk)
   double pfac;    // P / P_ref
   int32_t slot;   // intensity slot (distinct T or (T_vib, T_rot))
-  int32_t wbins;  // ceil(cut / dnu) + 2: bound on |k - k_c| inside the window
+  int32_t wbins;  // bound on |k - k_c| of a nonzero term: ceil(cut / dnu) + 2, less for a narrow Gaussian
   int32_t cclass; // cut-off class (index of the distinct cut-off)
   int32_t pad;
 };

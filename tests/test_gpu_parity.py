@@ -110,13 +110,19 @@ def test_sigma_gather_small(name, prec):
         _check_sigma(f"{name}/c{ci}", got[ci], ref, prec, st)
 
 
-def test_sigma_gaussian_fixed_hwhm():
+@pytest.mark.parametrize("hwhm", [0.002, 0.037, 0.3])
+@pytest.mark.parametrize("tile", [256, 512, 1024])
+def test_sigma_gaussian_fixed_hwhm(hwhm, tile):
+    """Fixed-HWHM Gaussian at step 0.01: lines with a few nonzero points (one
+    line per lane), about a hundred (FP32) or a few hundred (FP64) nonzero
+    points (64 points per wave step), and more than a tile (whole-tile rows)."""
     wl = synth.config(2, n_states=5000, n_lines=5000, nu_hi=600.0, profile=synth.GAUSSIAN)
-    wl.hwhm_fixed = 0.037
+    wl.hwhm_fixed = hwhm
     ref = oracle.run_condition(wl, wl.lines(), wl.conditions[0]).sigma
     for prec in (FP64, FP32):
-        got, st, _ = gpu_sigma(wl, wl.lines(), prec)
-        _check_sigma("gaussian_fixed", got[0], ref, prec, st)
+        got, st, _ = gpu_sigma(wl, wl.lines(), prec,
+                               config=dict(tile_bins=tile, bucket_bins=256, persistent=1, waves_per_cu=16))
+        _check_sigma(f"gaussian_fixed hwhm={hwhm} tile={tile}", got[0], ref, prec, st)
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
