@@ -170,7 +170,8 @@ typedef struct {
  * chunk_lines: 0 = automatic (about 64 items per compute unit when the
  * tiles alone are too few), else a multiple of 64 (the automatic size wins
  * when it is larger).  bucket_bins: grid points per line bucket (power of two,
- * 64..4096); persistent: 1 = one persistent launch pulling items from a
+ * 64..4096; a new plan starts at 64 for the Doppler and fixed-width Gaussian,
+ * 256 otherwise); persistent: 1 = one persistent launch pulling items from a
  * device queue, 0 = one workgroup per item; waves_per_cu: size of the
  * persistent grid in waves per compute unit (4..64). */
 typedef struct {

@@ -119,10 +119,33 @@ __device__ __forceinline__ LineState line_state(const StatesView& st, int32_t u,
   return s;
 }
 
+// As line_state, with the energies and degeneracy from the line's pack (the
+// state tables are read only for the non-LTE manifold terms).
+__device__ __forceinline__ LineState line_state(const StatesView& st, const LinePack& lp, int pop) {
+  LineState s;
+  s.Eu = lp.Eu;
+  s.El = lp.El;
+  s.gu = lp.gu;
+  if (pop != XS_LTE) {
+    s.evu = st.ev[st.v[lp.u]];
+    s.evl = st.ev[st.v[lp.l]];
+  } else {
+    s.evu = s.evl = 0.0;
+  }
+  if (pop == XS_NLTE_DENSITY) {
+    s.nvu = st.nv[st.v[lp.u]];
+    s.nvl = st.nv[st.v[lp.l]];
+  } else {
+    s.nvu = s.nvl = 1.0;
+  }
+  return s;
+}
+
 __global__ __launch_bounds__(256) void k_lines_pass1(ModelDev m, const SlotDev* slots,
                                                      const double* Q, const double* cutc,
                                                      const int32_t* cutm, StatesView st,
                                                      LinesView ln, int32_t* key,
+                                                     LinePack* lpack,
                                                      unsigned long long* smax,
                                                      unsigned long long* stats) {
   __shared__ double smx[256];
@@ -148,6 +171,18 @@ __global__ __launch_bounds__(256) void k_lines_pass1(ModelDev m, const SlotDev* 
       int64_t bk = kc < 0 ? 0 : kc / m.bucket_bins;
       kk = (int32_t)(bk < m.n_buckets - 1 ? bk : m.n_buckets - 1);
       ++kept;
+      LinePack lp;
+      lp.Eu = st.E[u];
+      lp.El = st.E[l];
+      lp.gu = st.g[u];
+      lp.u = u;
+      lp.l = l;
+      lp.A = ln.A[i];
+      lp.gref = ln.gref ? ln.gref[i] : (float)ln.gref_scalar;
+      lp.nexp = ln.nexp ? ln.nexp[i] : (float)ln.nexp_scalar;
+      lp.lscale = ln.lscale ? ln.lscale[i] : 0.0f;
+      lp.pad[0] = lp.pad[1] = lp.pad[2] = lp.pad[3] = 0;
+      lpack[i] = lp;
       for (int q = 0; q < m.n_cut_classes; ++q) {
         if (line_window(nu, cutc[q], m.nu0, m.dnu, m.n_bins, a, b))
           pairs += (unsigned long long)(b - a + 1) * (unsigned long long)cutm[q];
@@ -206,7 +241,7 @@ void launch_lines_pass1(const ModelDev& m, const Work& w, const StatesView& st,
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_lines_pass1, dim3((unsigned)blocks), dim3(256), 0, s, m, w.slot, w.Q,
-                     w.cut_class, w.cut_mult, st, ln, w.key, w.smax, w.stats);
+                     w.cut_class, w.cut_mult, st, ln, w.key, w.lpack, w.smax, w.stats);
   hipLaunchKernelGGL(k_scale_final, dim3(1), dim3(256), 0, s, m, w.smax, w.sb);
 }
 
@@ -379,7 +414,8 @@ __global__ __launch_bounds__(256) void k_offsets(const int32_t* skeys, int64_t n
 }
 
 __global__ __launch_bounds__(256) void k_records(ModelDev m, const SlotDev* slots, const double* Q,
-                                                 const double* sb, StatesView st, LinesView ln,
+                                                 const double* sb, StatesView st,
+                                                 const LinePack* lpack,
                                                  const int32_t* svals, const int32_t* off,
                                                  int64_t max_lines, double* rnu, float* rgref,
                                                  float* rnexp, double* rgpre, int32_t* ridx, void* rS,
@@ -389,11 +425,12 @@ __global__ __launch_bounds__(256) void k_records(ModelDev m, const SlotDev* slot
   for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < nk;
        p += (int64_t)gridDim.x * 256) {
     const int32_t i = svals[p];
-    const int32_t u = ln.up[i], l = ln.lo[i];
-    const double nu = st.E[u] - st.E[l];
+    const LinePack lp = lpack[i];
+    const int32_t u = lp.u, l = lp.l;
+    const double nu = lp.Eu - lp.El;
     rnu[p] = nu;
-    rgref[p] = ln.gref ? ln.gref[i] : (float)ln.gref_scalar;
-    rnexp[p] = ln.nexp ? ln.nexp[i] : (float)ln.nexp_scalar;
+    rgref[p] = lp.gref;
+    rnexp[p] = lp.nexp;
     if (rgpre) {
       // natural width of a predissociating upper state: HWHM 1/(4 pi c tau)
       const double tau = st.tau[u];
@@ -413,9 +450,9 @@ __global__ __launch_bounds__(256) void k_records(ModelDev m, const SlotDev* slot
       rwin[((int64_t)q * max_lines + p) * 2] = (int32_t)klo;
       rwin[((int64_t)q * max_lines + p) * 2 + 1] = (int32_t)khi;
     }
-    const LineState ls = line_state(st, u, l, m.pop);
-    const double A = (double)ln.A[i];
-    const double sc = ln.lscale ? (double)ln.lscale[i] : 0.0;
+    const LineState ls = line_state(st, lp, m.pop);
+    const double A = (double)lp.A;
+    const double sc = (double)lp.lscale;
     for (int q = 0; q < m.n_slots; ++q) {
       const SlotDev sd = slots[q];
       int sg;
@@ -436,7 +473,7 @@ void launch_offsets_records(const ModelDev& m, const Work& w, const StatesView& 
   hipLaunchKernelGGL(k_offsets, dim3((unsigned)blocks), dim3(256), 0, s, skeys, n, m.n_buckets,
                      w.off);
   hipLaunchKernelGGL(k_records, dim3((unsigned)blocks), dim3(256), 0, s, m, w.slot, w.Q, w.sb, st,
-                     ln, svals, w.off, w.max_lines, w.rnu, w.rgref, w.rnexp, w.rgpre, w.ridx, w.rS,
+                     w.lpack, svals, w.off, w.max_lines, w.rnu, w.rgref, w.rnexp, w.rgpre, w.ridx, w.rS,
                      w.cut_class, w.rkc, w.rdel, w.rwin);
 }
 

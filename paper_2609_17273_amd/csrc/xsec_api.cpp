@@ -320,6 +320,7 @@ size_t layout(xs_plan* p, char* base, Work* w) {
   x.rnexp = (float*)take(4 * L);
   x.rgpre = (double*)take(8 * L);
   x.ridx = (int32_t*)take(4 * L);
+  x.lpack = (LinePack*)take(sizeof(LinePack) * L);
   x.rkc = (int32_t*)take(4 * L);
   x.rdel = (float*)take(4 * L);
   x.rwin = (int32_t*)take(8 * (size_t)d.n_cut_classes * L);
@@ -435,7 +436,9 @@ int xs_plan_create(xs_plan** out, const xs_model* model, const xs_grid* grid, in
   p->conds.assign(conds, conds + n_cond);
   p->max_lines = max_lines;
   p->stream = (hipStream_t)stream;
-  p->bucket_bins = 256;
+  // narrow Gaussians reach few buckets beyond their tile, so finer buckets
+  // stage fewer lines per tile; the other profiles reach a whole cut-off
+  p->bucket_bins = (model->profile == XS_DOPPLER || model->profile == XS_GAUSSIAN) ? 64 : 256;
   if ((rc = hip_check(hipGetDevice(&p->device), "hipGetDevice"))) {
     delete p;
     return rc;

@@ -82,6 +82,17 @@ struct LinesView {
   double gref_scalar, nexp_scalar;
 };
 
+// One line's inputs and the energies and degeneracy of its states, packed
+// by the first line pass in input order, so that the record pass, which
+// visits the lines in wavenumber order, fetches one 64-byte block per line
+// instead of a cache line from each input array and state table.
+struct __attribute__((aligned(64))) LinePack {
+  double Eu, El, gu;
+  float A, gref, nexp, lscale;
+  int32_t u, l;
+  int32_t pad[4];
+};
+
 // Workspace pointers (carved by the host runtime from the caller's buffer).
 struct Work {
   CondDev* cond;            // [n_cond]
@@ -106,6 +117,7 @@ struct Work {
   double* rgpre;            //                 lifetime HWHM of the upper state, 1/(4 pi c tau) or 0
                             //                 (kernels get null when the states carry no lifetimes)
   int32_t* ridx;            //                 original line index
+  LinePack* lpack;          // [max_lines] line inputs in input order (first pass -> record pass)
   int32_t* rkc;             //                 home bin k_c = rint((nu - nu0)/dnu)
   float* rdel;              //                 nu - nu_{k_c}
   int32_t* rwin;            //                 [n_cut_classes][max_lines][2] window (klo, khi), klo > khi if empty
