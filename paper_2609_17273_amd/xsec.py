@@ -444,9 +444,14 @@ class ChunkStreamer:
     The copies are plumbing: every computation runs in the library's kernels.
     """
 
-    def __init__(self, plan: "Plan", max_chunk_lines: int):
+    def __init__(self, plan: "Plan", max_chunk_lines: int, copy_threads: int = 8):
         import torch
+        from concurrent.futures import ThreadPoolExecutor
         self.torch, self.plan, self.cap = torch, plan, int(max_chunk_lines)
+        # host copies into the pinned buffers, split over threads (numpy
+        # releases the GIL while copying): one thread copies ~10 GB/s, too
+        # slow to keep up with the device on chunks of 1e8 lines
+        self.pool = ThreadPoolExecutor(max_workers=max(1, int(copy_threads)))
         n = self.cap
         self.copy_stream = torch.cuda.Stream()  # default priority
         self.host = [self._buffers(n, pinned=True) for _ in range(2)]
@@ -476,14 +481,10 @@ class ChunkStreamer:
             h, d = self.host[b], self.dev[b]
             if j >= 2:
                 self.copied[b].synchronize()          # the pinned buffer's last upload has left it
-            for k in ("upper", "lower", "einstein_a"):
-                h[k][:n].numpy()[:] = getattr(ch, k)
             has_g = ch.gamma_ref is not None
             has_n = ch.n_exp is not None
-            if has_g:
-                h["gamma_ref"][:n].numpy()[:] = ch.gamma_ref
-            if has_n:
-                h["n_exp"][:n].numpy()[:] = ch.n_exp
+            names = ["upper", "lower", "einstein_a"] + (["gamma_ref"] if has_g else []) + (["n_exp"] if has_n else [])
+            self._copy([(h[k][:n].numpy(), getattr(ch, k)) for k in names])
             with t.cuda.stream(self.copy_stream):
                 if j >= 2:
                     self.copy_stream.wait_event(self.done[b])  # chunk j-2 no longer reads this buffer
@@ -505,6 +506,18 @@ class ChunkStreamer:
             total += n
         compute.synchronize()
         return total
+
+    def _copy(self, pairs, piece: int = 1 << 22):
+        jobs = []
+        for dst, src in pairs:
+            src = np.ascontiguousarray(src, dtype=dst.dtype)
+            for a in range(0, dst.shape[0], piece):
+                jobs.append(self.pool.submit(np.copyto, dst[a:a + piece], src[a:a + piece]))
+        for f in jobs:
+            f.result()
+
+    def close(self):
+        self.pool.shutdown(wait=True)
 
 
 def _make_xsec_function():
