@@ -35,24 +35,28 @@ sys.path.insert(0, ROOT)
 # needs at that evaluation (FMA = 2; add, mul, reciprocal, division, exp2 = 1),
 # by the Voigt region rho = x^2 + y^2 of the evaluation (the same regions the
 # kernels use).  (rho threshold, flops) from the outermost region inward:
-#   forward FP32: 1 node pair: x = fma(r,a,-b) 2, u 1, u+q 1, d = fma 2, rcp 1,
-#                 numerator fma 2, accumulate fma 2 = 11; 2 pairs 19;
+#   forward FP32: 1 node pair: x = fma(r,a,-b) 2, s = fma(x,x,h) 2,
+#                 d = fma(s,s,c) 2, rcp 1, numerator fma 2, accumulate fma 2
+#                 = 11; 2 pairs: x 2, per pair s, d, rcp, numerator, product 8,
+#                 sum and accumulate 2 = 20;
 #                 core: Weideman's rational approximation with N = 24 terms in
 #                 FP64 (q and Z 14, 23 complex Horner steps x 7 = 161, Re w 11,
 #                 x, scale and accumulate 4) = 190.
 #   forward FP64: 1 pair 11; 2 pairs (one division) 19; 3/4/6 pairs 30/39/57;
 #                 core N = 40: 14 + 39 x 7 + 11 + 4 = 302.
-#   adjoint FP32: 1 pair: x 2, u 1, pair terms 18 (u+q, d, rcp, e, s, t),
-#                 three accumulations 6 = 27; 2 pairs 54; core: w (N = 24, both
+#   adjoint FP32: 1 pair: x 2, u 1, d 3, rcp 1, e 2, t 6, accumulations of
+#                 g e, g t, g/d, g e^2 8 = 23; 2 pairs: x 2, u 1, per pair
+#                 d, rcp, e, t 12 and their K-weighted sums 8, four
+#                 accumulations 8 = 51; core: w (N = 24, both
 #                 parts: 14 + 161 + 17), w' = -2zw + 2i/sqrt(pi) and Re G 13,
 #                 x, |z|^2 5, three accumulations 6 = 216.
-#   adjoint FP64: 1/2/3 pairs 27/54/78; 4/6 pairs (general form) 113/161;
+#   adjoint FP64: 1/2/3 pairs 23/51/71; 4/6 pairs (general form) 113/161;
 #                 core N = 40: 14 + 273 + 17 + 24 = 328.
 FLOP_REGIONS = {
-    ("fwd", "f32"): [(900.0, 11), (64.0, 19), (0.0, 190)],
+    ("fwd", "f32"): [(900.0, 11), (64.0, 20), (0.0, 190)],
     ("fwd", "f64"): [(9.0e6, 11), (6400.0, 19), (400.0, 30), (144.0, 39), (64.0, 57), (0.0, 302)],
-    ("adj", "f32"): [(900.0, 27), (64.0, 54), (0.0, 216)],
-    ("adj", "f64"): [(9.0e6, 27), (6400.0, 54), (400.0, 78), (144.0, 113), (64.0, 161), (0.0, 328)],
+    ("adj", "f32"): [(900.0, 23), (64.0, 51), (0.0, 216)],
+    ("adj", "f64"): [(9.0e6, 23), (6400.0, 51), (400.0, 71), (144.0, 113), (64.0, 161), (0.0, 328)],
 }
 # MI355X vector peaks, no packed-FP32 (the kernels are compiled without packed FP32):
 # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP32

@@ -156,13 +156,16 @@ __device__ __forceinline__ double arcp(double d) {
 //   Re w = y sum_j K_j (u + p_j)/d_j,  d_j = u (u + q_j) + p_j^2,
 //   p_j = y^2 + tau_j,  q_j = 2 y^2 - 2 tau_j,  K_j = 2 W_j / pi,  u = x^2,
 // and its derivatives, with e = (u + p)/d:
-//   dRe w/dy  = sum_j K_j [(u + p + 2 y^2)/d - 4 y^2 e^2]
+//   dRe w/dy  = sum_j K_j [e + 2 y^2 / d - 4 y^2 e^2]
 //   x dRe w/dx = 2 y sum_j K_j (u/d) [(p^2 - p q)/d - (u/d)(u + 2 p)]
-// Every product is formed from ratios of size <= 1/u, so FP32 neither
-// overflows nor underflows for |x|, y < 1e9.
+//              = 2 y sum_j K_j (u/d) [4 tau_j (p - u)/d - 1]
+// (the last form from d = u^2 + q u + p^2 and 2p - q = 4 tau).  The fast
+// loops accumulate g e, g / d and g e^2 separately and form dRe w/dy from
+// them once per block.  Every product is formed from ratios of size <= 1/u,
+// so FP32 neither overflows nor underflows for |x|, y < 1e9.
 template <typename R>
 struct PairD {
-  R q, p2, p, c3, K;
+  R q, p2, p, k1, k2, K;  // k1 = 4 tau p, k2 = -4 tau
 };
 template <typename R>
 __device__ __forceinline__ PairD<R> pair_d(double y, double tau, double W) {
@@ -171,26 +174,23 @@ __device__ __forceinline__ PairD<R> pair_d(double y, double tau, double W) {
   r.q = (R)q;
   r.p2 = (R)(p * p);
   r.p = (R)p;
-  r.c3 = (R)(p * (p - q));
+  r.k1 = (R)(4.0 * tau * p);
+  r.k2 = (R)(-4.0 * tau);
   r.K = (R)(2.0 * W / kPI);
   return r;
 }
 template <typename R>
-__device__ __forceinline__ void pair_adj(const PairD<R>& P, R u, R ty2, R fy2, R& e, R& s, R& t) {
+__device__ __forceinline__ void pair_adj(const PairD<R>& P, R u, R& e, R& rd, R& t) {
   const R d = fma(u, u + P.q, P.p2);
-  const R rd = arcp(d);
-  const R n1 = u + P.p;
-  e = n1 * rd;
-  s = fma(-fy2 * e, e, fma(ty2, rd, e));
-  const R ur = u * rd;
-  t = ur * fma(-ur, n1 + P.p, P.c3 * rd);
+  rd = arcp(d);
+  e = (u + P.p) * rd;
+  t = (u * rd) * fma(rd, fma(u, P.k2, P.k1), (R)-1);
 }
 
 // Per-lane state of one line under one condition.
 template <typename R>
 struct AdjLine {
   R a, nb;            // x = r a + nb, r = k - k_c
-  R ty2, fy2;         // 2 y^2, 4 y^2
   PairD<R> P[3];      // node pairs of the far-region levels (Voigt)
   double ad, bd, y;   // FP64 copies for the general path
   int kc, rlo, rhi;   // home bin; window in r
@@ -289,11 +289,16 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
   const unsigned long long act = __ballot(1);
   const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(act >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)act, 0u));
   const int nact = __popcll(act);
+  // x at r = rb + j4 + jj as fma(rb + j4, a, nb + jj a): one conversion per
+  // four points (nb + jj a rounds once, relative 6e-8 of at most 3.5 a, so x
+  // keeps a relative error below 5e-7 for every r != 0)
+  R nbj[4];
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) nbj[jj] = fma((R)jj, L.a, L.nb);
   for (int rb = r0; rb <= r1; rb += kFlush) {
     const int n = min(kFlush, r1 - rb + 1);
-    R s1 = 0, s2 = 0, s3 = 0;
-    auto body = [&](int j, R gk) {
-      const R x = fma((R)(rb + j), L.a, L.nb);
+    R s1 = 0, s2 = 0, s3 = 0, s4 = 0;
+    auto body = [&](R x, R gk) {
       const R u = x * x;
       if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
         R e;
@@ -307,26 +312,41 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
         const R gi = gk * iq;
         s1 += gi;
         s2 = fma(gi, iq, s2);
-      } else {
-        R e, s, t;
-        pair_adj<R>(L.P[0], u, L.ty2, L.fy2, e, s, t);
-        if constexpr (NP >= 2) {
-          e *= L.P[0].K;
-          s *= L.P[0].K;
-          t *= L.P[0].K;
-#pragma unroll
-          for (int q = 1; q < NP; ++q) {
-            R e2, sq, t2;
-            pair_adj<R>(L.P[q], u, L.ty2, L.fy2, e2, sq, t2);
-            e = fma(L.P[q].K, e2, e);
-            s = fma(L.P[q].K, sq, s);
-            t = fma(L.P[q].K, t2, t);
-          }
-        }
-        s1 = fma(gk, e, s1);
+      } else if constexpr (NP == 1) {
+        // s1 = sum g e, s2 = sum g t, s3 = sum g / d, s4 = sum g e^2
+        R e, rd, t;
+        pair_adj<R>(L.P[0], u, e, rd, t);
+        const R ge = gk * e;
+        s1 += ge;
         s2 = fma(gk, t, s2);
-        s3 = fma(gk, s, s3);
+        s3 = fma(gk, rd, s3);
+        s4 = fma(ge, e, s4);
+      } else {
+        R E = 0, RD = 0, E2 = 0, T = 0;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          R e, rd, t;
+          pair_adj<R>(L.P[q], u, e, rd, t);
+          const R Ke = L.P[q].K * e;
+          E += Ke;
+          RD = fma(L.P[q].K, rd, RD);
+          E2 = fma(Ke, e, E2);
+          T = fma(L.P[q].K, t, T);
+        }
+        s1 = fma(gk, E, s1);
+        s2 = fma(gk, T, s2);
+        s3 = fma(gk, RD, s3);
+        s4 = fma(gk, E2, s4);
       }
+    };
+    auto run = [&](auto gsrc) {
+      int j = 0;
+      for (; j + 4 <= n; j += 4) {
+        const R rf = (R)(rb + j);
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) body(fma(rf, L.a, nbj[jj]), gsrc(j + jj));
+      }
+      for (; j < n; ++j) body(fma((R)(rb + j), L.a, L.nb), gsrc(j));
     };
     if (G.lds) {
       // refill the wave's slice with g[kcmin + rb + t], t < 2 kFlush
@@ -341,12 +361,10 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const R* gl = G.buf + (L.kc - G.kcmin);
-#pragma unroll 4
-      for (int j = 0; j < n; ++j) body(j, gl[j]);
+      run([&](int j) { return gl[j]; });
     } else {
       const double* gp = G.gc + (L.kc + rb);
-#pragma unroll 4
-      for (int j = 0; j < n; ++j) body(j, (R)gp[j]);
+      run([&](int j) { return (R)gp[j]; });
     }
     // to the general-path convention
     if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
@@ -357,7 +375,9 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
       sC += (double)s1 - 2.0 * (double)s2;
     } else {
       const double k = (NP == 1) ? (double)L.P[0].K : 1.0;
-      const double e = k * (double)s1, t = k * (double)s2, w = k * (double)s3;
+      const double y2 = L.y * L.y;
+      const double e = k * (double)s1, t = k * (double)s2;
+      const double w = k * ((double)s1 + 2.0 * y2 * (double)s3 - 4.0 * y2 * (double)s4);  // dRe w/dy
       sA += L.y * e;                      // Re w
       sB += L.y * (e + 2.0 * t) + L.y * w; // Re w + x dRe w/dx + y dRe w/dy
       sC -= w;                            // Im w' = -dRe w/dy
@@ -412,8 +432,6 @@ __device__ __forceinline__ Sums3 window_sums(bool on, int64_t klo, int64_t khi, 
   L.y = y;
   L.a = (R)L.ad;
   L.nb = (R)(-L.bd);
-  L.ty2 = (R)(2.0 * y * y);
-  L.fy2 = (R)(4.0 * y * y);
   bool wide = false;
   if (PROF == XS_VOIGT) {
     L.P[0] = pair_d<R>(y, GH::t2[0], GH::w2[0]);

@@ -114,6 +114,19 @@ constexpr int kRowSkip = 0, kRowF1 = 1, kRowGeneral = 2, kRowF2 = 3, kRowF1M = 4
 // FP64 form only: third uniform formula (three node pairs), plain and masked.
 constexpr int kRowF3 = 6, kRowF3M = 7;
 
+// FP32 far-region node pair in shifted form.  With h = y^2 - tau and
+// s = u + h = |z|^2 - tau (positive wherever a node rule is used),
+//   cW (u + p)/d = cW (s + 2 tau)/(s^2 + 4 y^2 tau),
+// so a pair costs three FMAs and a reciprocal from x, with no separate
+// u = x^2; every term is positive, so nothing cancels.
+struct PairS {
+  float cw, cwt, h, c;  // cW, cW 2 tau, y^2 - tau, 4 y^2 tau
+};
+__device__ __forceinline__ float pair_term_s(const PairS& P, float x) {
+  const float s = fmaf(x, x, P.h);
+  return fmaf(P.cw, s, P.cwt) * __builtin_amdgcn_rcpf(fmaf(s, s, P.c));
+}
+
 // FP32 form.  The first-formula fields come first (two 16-byte LDS reads);
 // the second formula reads a, nb, jfb and B1, B2.
 //   rB: bins that are not far-wing (one node pair) -- for the Gaussian, the
@@ -122,8 +135,8 @@ constexpr int kRowF3 = 6, kRowF3M = 7;
 //       three; a chunk that meets rD takes the rational approximation).
 struct __attribute__((aligned(16))) RecF {
   float a, nb, jfb, c0;  // x = (jfb + offset of the bin in the tile) a + nb; jfb = tlo - k_c
-  Pair<float> A;         // one node pair
-  Pair<float> B1, B2;    // two node pairs
+  PairS A;               // one node pair
+  PairS B1, B2;          // two node pairs
   int klo, khi, flag, kc;
   KRange rB, rC;
   KRange rD;
@@ -306,12 +319,12 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, const LineIn<L
     } else if (PROF == XS_VOIGT) {
       const float y2 = y * y;
       auto make = [&](double tau, double W) {
-        const float p2 = y2 + (float)tau, cw = c0 * (float)(2.0 / kPI) * y * (float)W;
-        return Pair<float>{cw, cw * p2, 2.0f * y2 - 2.0f * (float)tau, p2 * p2};
+        const float cw = c0 * (float)(2.0 / kPI) * y * (float)W;
+        return PairS{cw, cw * (float)(2.0 * tau), y2 - (float)tau, 4.0f * y2 * (float)tau};
       };
       r.A = make(GH::t2[0], GH::w2[0]);
       r.rB = x_range_f(sqrtf(fmaxf(900.9f - y2, 0.0f)), a, b, kc, klo, khi);
-      // FP32 keeps u (u + q) + p^2 finite for |x|, y < ~1e9; lines beyond that
+      // FP32 keeps s^2 + 4 y^2 tau finite for |x|, y < ~1e9; lines beyond that
       // (nu of a few 1e-3 cm^-1 or less) are evaluated in FP64.
       const float xmax = fmaxf(fabsf((float)(klo - kc) * a - b), fabsf((float)(khi - kc) * a - b));
       if (!(xmax <= 1.0e9f) || !(y <= 1.0e9f)) r.flag = 1;
@@ -1143,16 +1156,16 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
                 acc32[j] = fmaf(c0, __builtin_amdgcn_exp2f(-(x * x)), acc32[j]);
               }
             } else {
-              const float cw = rr.A.cw, cwp = rr.A.cwp, q = rr.A.q, p2 = rr.A.p2;
+              const PairS A = rr.A;
 #pragma unroll
               for (int j = 0; j < M; ++j) {
                 const float x = fmaf(jf0 + (float)(64 * j), a, nb);
-                const float u = x * x;
+                const float s = fmaf(x, x, A.h);
                 if (!masked) {
-                  acc32[j] = fmaf(fmaf(cw, u, cwp), rcp32(fmaf(u, u + q, p2)), acc32[j]);
+                  acc32[j] = fmaf(fmaf(A.cw, s, A.cwt), rcp32(fmaf(s, s, A.c)), acc32[j]);
                 } else {
                   const int k = my0 + 64 * j;
-                  const float t = fmaf(cw, u, cwp) * rcp32(fmaf(u, u + q, p2));
+                  const float t = fmaf(A.cw, s, A.cwt) * rcp32(fmaf(s, s, A.c));
                   acc32[j] += (k >= klo && k <= khi) ? t : 0.0f;
                 }
               }
@@ -1167,7 +1180,7 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
             for (int l = l0; l < l1; ++l) {
               const RecF& rr = srec[l];
               const float a = rr.a, nb = rr.nb, jf0 = rr.jfb + lane_off;
-              const Pair<float> B1 = rr.B1, B2 = rr.B2;
+              const PairS B1 = rr.B1, B2 = rr.B2;
               int klo = 0, khi = 0;
               if (masked) {
                 klo = uni(rr.klo);
@@ -1176,8 +1189,7 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
 #pragma unroll
               for (int j = 0; j < M; ++j) {
                 const float x = fmaf(jf0 + (float)(64 * j), a, nb);
-                const float u = x * x;
-                const float t = pair_term<float>(B1, u) + pair_term<float>(B2, u);
+                const float t = pair_term_s(B1, x) + pair_term_s(B2, x);
                 const int k = my0 + 64 * j;
                 acc32[j] += (!masked || (k >= klo && k <= khi)) ? t : 0.0f;
               }
@@ -1213,12 +1225,9 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g) {
               const double xd = (double)(k - rr.kc) * (double)a + (double)nb;
               v = (full || (k >= klo && k <= khi)) ? (float)((double)rr.c0 * re_w_f64(xd, (double)rr.y)) : 0.0f;
             } else if (!meets(cl, ch, rB)) {
-              const float u = x * x;
-              const Pair<float> A = rr.A;
-              v = fmaf(A.cw, u, A.cwp) * rcp32(fmaf(u, u + A.q, A.p2));
+              v = pair_term_s(rr.A, x);
             } else if (!meets(cl, ch, rC)) {
-              const float u = x * x;
-              v = pair_term<float>(rr.B1, u) + pair_term<float>(rr.B2, u);
+              v = pair_term_s(rr.B1, x) + pair_term_s(rr.B2, x);
             } else if (!meets(cl, ch, rD)) {
               v = gh3_f32(x * x, rr.y, rr.c0);
             } else if constexpr (CQ) {
