@@ -1,5 +1,6 @@
 """Properties of the GPU pipeline through the C-ABI: the captured graph
-replays the eager result; the FP64 gather is bitwise repeatable; every kernel
+replays the eager result; the FP64 gather is bitwise repeatable (and both
+forms on narrow Doppler lines, which take the LDS row path); every kernel
 configuration the autotuner may pick gives the same sigma (within the
 tolerance of the form); chunked accumulation equals the whole line list;
 batched conditions equal separate runs; edge cases (no lines, all lines
@@ -53,6 +54,29 @@ def test_gather_fp64_bitwise_repeatable_and_scatter_close():
     e, _, _ = rel_err(s[0].cpu().numpy(), a[0].cpu().numpy())
     log(f"[repeat] fp64 gather bitwise repeatable; scatter vs gather {e:.2e}")
     assert e < 1e-12
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_gaussian_rows_repeatable_and_replayed(prec):
+    """Narrow Doppler lines go through the per-lane LDS row adds: two eager
+    runs are bitwise equal, and so are three graph replays."""
+    import torch
+    wl = workload(5, n_states=20000, n_lines=30000, n_chunks=1, nu_hi=2000.0)
+    ln = wl.lines()
+    plan = make_plan(wl, prec, ln.n)
+    ds, dl = gpu_inputs(wl, ln)
+    a = plan.cross_section(ds, dl).clone()
+    b = plan.cross_section(ds, dl).clone()
+    assert torch.equal(a, b)
+    out = torch.full_like(a, -1.0)
+    plan.capture(ds, dl, out)
+    for rep in range(3):
+        out.fill_(-1.0)
+        plan.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, a), f"replay {rep} differs"
+    log(f"[gauss rows] prec={prec}: eager runs and 3 replays bitwise equal")
+    plan.close()
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
