@@ -159,7 +159,25 @@ def time_steps(plan, ds, dl, sig, w, target, steps, warmup):
         per["forward"] += e[1].elapsed_time(e[2]) / steps
         per["loss_grad"] += e[2].elapsed_time(e[3]) / steps
         per["adjoint"] += e[3].elapsed_time(e[4]) / steps
-    return (t1 - t0) * 1e3 / max(steps, 1), per
+    # per-step device times (first to last event of each step)
+    tot = sorted(e[0].elapsed_time(e[4]) for e in evs[:steps])
+    dist = {"median": round(tot[len(tot) // 2], 3), "min": round(tot[0], 3), "max": round(tot[-1], 3)} if tot else {}
+    return (t1 - t0) * 1e3 / max(steps, 1), per, dist
+
+
+def device_state():
+    """Clocks and power as rocm-smi reports them right after the timed steps
+    (a child process; best effort)."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--json"], capture_output=True,
+                           text=True, timeout=30)
+        d = json.loads(r.stdout)
+        card = next(iter(d.values())) if d else {}
+        keep = {k: v for k, v in card.items() if any(s in k.lower() for s in ("sclk", "mclk", "fclk", "power"))}
+        return keep or {"raw": r.stdout[-500:]}
+    except Exception as e:  # noqa: BLE001 - reporting only
+        return {"error": str(e)[:200]}
 
 
 def cpu_baseline(wl, lines, cond, n_sample=40000):
@@ -180,10 +198,23 @@ def cpu_baseline(wl, lines, cond, n_sample=40000):
     t0 = time.perf_counter()
     oracle.sigma(nu, S, alpha, gamma, wl.profile, wl.grid, cond.cutoff, bins)
     dt = time.perf_counter() - t0
-    return {"value": evals / dt, "unit": "profile evals/s", "cores": oracle.threads(), "kind": "oracle",
+    cores = oracle.threads()
+    # the per-core rate: one thread on the first 1,000 of the sampled points
+    b1 = bins[:1000]
+    nuk1 = wl.grid.nu0 + b1 * wl.grid.dnu
+    evals1 = int(np.sum(np.searchsorted(snu, nuk1 + cond.cutoff, side="right")
+                        - np.searchsorted(snu, nuk1 - cond.cutoff, side="left")))
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.sigma(nu, S, alpha, gamma, wl.profile, wl.grid, cond.cutoff, b1)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(cores)
+    return {"value": evals / dt, "unit": "profile evals/s", "cores": cores, "kind": "oracle",
             "sample": (f"sigma at {n_sample} random grid points of the 2,000,001-point grid over all "
                        f"1e7 lines ({evals:.3e} evaluations, {dt:.1f} s including the oracle's sort of "
-                       f"the lines by wavenumber)")}
+                       f"the lines by wavenumber)"),
+            "one_thread": {"value": evals1 / dt1, "unit": "profile evals/s",
+                           "sample": f"the first 1000 of those points ({evals1:.3e} evaluations, {dt1:.1f} s)"}}
 
 
 def batched_48(X, wl, ds, dl, n_lines):
@@ -549,7 +580,8 @@ def main():
     p32 = plan_for(X.XS_FP32)
     cfg = p32.autotune(ds, dl, sig, cache_path=os.path.join("/tmp", "xsec_autotune.json"))
     log(f"autotuned: {cfg}")
-    ms32, per32 = time_steps(p32, ds, dl, sig, w, target, args.steps, args.warmup)
+    ms32, per32, dist32 = time_steps(p32, ds, dl, sig, w, target, args.steps, args.warmup)
+    dev_state = device_state()
     st = p32.stats()
     pairs = st["window_pairs"]
     log(f"fp32 step {ms32:.2f} ms {per32} pairs {pairs:.3e}")
@@ -558,7 +590,7 @@ def main():
     if not args.no_extras:
         p64 = plan_for(X.XS_FP64)
         p64.set_config(**cfg)
-        ms64, per64 = time_steps(p64, ds, dl, sig, w, target, max(2, args.steps // 2), 1)
+        ms64, per64, _ = time_steps(p64, ds, dl, sig, w, target, max(2, args.steps // 2), 1)
         log(f"fp64 step {ms64:.2f} ms {per64}")
         extras["fp64"] = {"ms_per_step": round(ms64, 3), "stage_ms": {k: round(v, 3) for k, v in per64.items()},
                           "evals_per_s": 2 * pairs / (ms64 / 1e3)}
@@ -626,6 +658,8 @@ def main():
                    "lines": lines.n, "states": wl.states.n, "grid_points": wl.grid.n_bins,
                    "lines_kept": st["lines_kept"], "window_pairs": pairs, "kernel_config": cfg},
         "stage_ms": {k: round(v, 3) for k, v in per32.items()},
+        "step_ms_device": dist32,
+        "device_state": dev_state,
         "forward_evals_per_s": pairs / (per32["forward"] / 1e3),
         "lines_per_s": lines.n / (ms32 / 1e3),
         "adj_over_fwd": round(per32["adjoint"] / per32["forward"], 3),

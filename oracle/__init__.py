@@ -55,6 +55,8 @@ def lib():
         d, i64, i32, p = C.c_double, C.c_int64, C.c_int, C.c_void_p
         L.or_c2.restype = d
         L.or_max_threads.restype = i32
+        L.or_set_threads.argtypes = [i32]
+        L.or_set_threads.restype = None
         L.or_constants.argtypes = [p]
         L.or_partition.argtypes = [i64, p, p, p, p, p, i32, d, d, d, p, p]
         L.or_intensities.argtypes = [i64, p, p, p, p, p, p, p, p, p, i32, i32, d, d, d, d, p, p, p]
@@ -97,6 +99,11 @@ def constants() -> np.ndarray:
 
 def threads() -> int:
     return lib().or_max_threads()
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's later parallel loops (timing only)."""
+    lib().or_set_threads(int(n))
 
 
 def faddeeva(x: float, y: float) -> complex:

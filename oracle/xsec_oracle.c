@@ -61,6 +61,8 @@ enum { OR_LTE = 0, OR_NLTE_2T = 1, OR_NLTE_DENSITY = 2 };
 
 double or_c2(void) { return OR_H * OR_C / OR_KB; }
 int or_max_threads(void) { return omp_get_max_threads(); }
+/* Thread count of later parallel regions (timing only; results do not depend on it). */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 void or_constants(double* out5) {
   out5[0] = OR_H; out5[1] = OR_C; out5[2] = OR_KB; out5[3] = OR_AMU; out5[4] = or_c2();
 }
