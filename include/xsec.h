@@ -163,7 +163,8 @@ typedef struct {
 } xs_lines;
 
 /* Kernel configuration.  The gather cuts the grid into tiles of tile_bins
- * points (256, 512 or 1024; one wave of 64 lanes, each lane every 64th point).
+ * points (256, 512 or 1024, 256 in a new plan; one wave of 64 lanes, each lane
+ * every 64th point).
  * A work item is one (tile, condition) and a slice of at most chunk_lines of
  * the tile's candidate lines; a tile split over several items is summed from
  * their partial rows in item order, so results do not depend on scheduling.

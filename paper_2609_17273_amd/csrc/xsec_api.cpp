@@ -451,7 +451,7 @@ int xs_plan_create(xs_plan** out, const xs_model* model, const xs_grid* grid, in
   p->n_cu = prop.multiProcessorCount;
   p->arch = prop.gcnArchName;
   derive(p);
-  tiling_for(p, 512, 1, 16, 0);
+  tiling_for(p, 256, 1, 16, 0);  // the autotuner's usual pick for every profile measured
   std::memset(&p->w, 0, sizeof(p->w));
   *out = p;
   g_err.clear();

@@ -339,7 +339,7 @@ class Plan:
                 raise
             self._bind()
 
-    def set_config(self, tile_bins=512, bucket_bins=256, persistent=1, waves_per_cu=16, chunk_lines=0):
+    def set_config(self, tile_bins=256, bucket_bins=256, persistent=1, waves_per_cu=16, chunk_lines=0):
         cfg = xs_config(tile_bins, bucket_bins, persistent, waves_per_cu, chunk_lines)
         try:
             xs_plan_set_config(self.h, cfg)
