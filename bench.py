@@ -419,7 +419,8 @@ def stream_2t(X, n_lines=50_000_000, n_chunks=5):
     T_rot) pairs, Doppler at T_rot, grid 0-30000 cm^-1 step 0.05): chunks held
     in host memory are uploaded on a copy stream while the previous chunk
     runs (FP32 form).  Reported with the uploads (PCIe-inclusive) and, for
-    comparison, with the same chunks already resident on the device."""
+    comparison, with the same chunks already resident on the device, in the
+    FP32 and FP64 forms."""
     import torch
     import synth
     wl = synth.config(5, n_lines=n_lines, n_chunks=n_chunks)
@@ -441,14 +442,27 @@ def stream_2t(X, n_lines=50_000_000, n_chunks=5):
         plan.cross_section(ds, dl, out=sig, accumulate=j > 0)
     torch.cuda.synchronize()
     ms_res = (time.perf_counter() - t0) * 1e3
+    # the FP64 form on the same resident chunks
+    p64 = X.Plan(wl.profile, wl.mode, wl.population, X.XS_FP64, wl.grid, wl.conditions, max(sizes),
+                 mass_amu=wl.mass_amu)
+    for j, dl in enumerate(dls):
+        p64.cross_section(ds, dl, out=sig, accumulate=j > 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j, dl in enumerate(dls):
+        p64.cross_section(ds, dl, out=sig, accumulate=j > 0)
+    torch.cuda.synchronize()
+    ms_res64 = (time.perf_counter() - t0) * 1e3
+    p64.close()
     nbytes = sum(4 * 2 + 4 + (4 if c.gamma_ref is not None else 0) + (4 if c.n_exp is not None else 0)
                  for c in chunks[:1]) * n
     out = {"lines": n, "chunks": n_chunks, "conditions": len(wl.conditions),
            "ms_streamed": round(ms_stream, 2), "ms_resident": round(ms_res, 2),
+           "ms_resident_f64": round(ms_res64, 2), "fp32_over_fp64_speedup_resident": round(ms_res64 / ms_res, 3),
            "line_conditions_per_s_streamed": n * len(wl.conditions) / (ms_stream / 1e3),
            "line_conditions_per_s_resident": n * len(wl.conditions) / (ms_res / 1e3),
            "upload_bytes": nbytes}
-    log(f"stream 2T: {n} lines, streamed {ms_stream:.1f} ms, resident {ms_res:.1f} ms")
+    log(f"stream 2T: {n} lines, streamed {ms_stream:.1f} ms, resident {ms_res:.1f} ms (FP64 {ms_res64:.1f} ms)")
     plan.close()
     return out
 
@@ -457,7 +471,7 @@ def full_configs(X):
     """The batched opacity grid (48 conditions) at its full 1e8 lines in one
     captured graph, FP32 and FP64; and the two-temperature emission workload
     at its full 1e9 lines, streamed from host memory in 10 chunks of 1e8
-    (chunks generated into host memory first), FP32."""
+    (chunks generated into host memory first), FP32 and FP64."""
     import torch
     import synth
     out = {}
@@ -510,11 +524,23 @@ def full_configs(X):
     n = st.run(ds, chunks, sig)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3
-    out["stream_2t_full"] = {"lines": n, "chunks": len(chunks), "conditions": len(wl.conditions),
-                             "ms_streamed": round(ms, 1),
-                             "line_conditions_per_s": n * len(wl.conditions) / (ms / 1e3)}
     log(f"stream 1e9: {ms:.0f} ms")
     plan.close()
+    del st
+    p64 = X.Plan(wl.profile, wl.mode, wl.population, X.XS_FP64, wl.grid, wl.conditions, max(sizes),
+                 mass_amu=wl.mass_amu)
+    st64 = X.ChunkStreamer(p64, max(sizes))
+    st64.run(ds, chunks[:1], sig)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st64.run(ds, chunks, sig)
+    torch.cuda.synchronize()
+    ms64 = (time.perf_counter() - t0) * 1e3
+    log(f"stream 1e9 FP64: {ms64:.0f} ms")
+    p64.close()
+    out["stream_2t_full"] = {"lines": n, "chunks": len(chunks), "conditions": len(wl.conditions),
+                             "ms_streamed": round(ms, 1), "ms_streamed_f64": round(ms64, 1),
+                             "line_conditions_per_s": n * len(wl.conditions) / (ms / 1e3)}
     return out
 
 

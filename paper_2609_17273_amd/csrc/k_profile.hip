@@ -700,7 +700,13 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
   // has at most kLaneSpan such points, else 64 points per wave step.
   constexpr bool GN = PROF == XS_DOPPLER || PROF == XS_GAUSSIAN;
   constexpr int kLaneSpan = 96;
-  __shared__ Real gbuf[GN ? ROWB : 1];
+  // The row is FP64 in both forms.  With an FP32 row the lanes' LDS float
+  // adds held the FP32 waves three quarters of the time (about 16 cycles per
+  // LDS instruction, against 2.8 for the FP64 form's double adds; spreading
+  // the lanes over four copies of the row did not help), and the pass took
+  // 3.7 ms on a 1e7-line chunk of the two-temperature workload, 0.7 ms with
+  // double adds.  An FP64 row also needs no per-batch fold.
+  __shared__ double gbuf[GN ? ROWB : 1];
 
   const int lane = threadIdx.x;
   const ModelDev& m = g.m;
@@ -744,7 +750,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
       acc32[j] = 0.0f;
       if (!F32) nuk[j] = nu_of_bin(m.nu0, m.dnu, my0 + 64 * j);
       if constexpr (CQ) rowbuf[lane + 64 * j] = 0.0f;
-      if constexpr (GN) gbuf[lane + 64 * j] = (Real)0;
+      if constexpr (GN) gbuf[lane + 64 * j] = 0.0;
     }
     // ring of queued core points: qn entries from qh (wave-uniform).  The
     // block is one wave, whose LDS accesses complete in issue order, so a
@@ -799,7 +805,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
                 }
                 v = rr.c0 * exp2(-(x * x));
               }
-              atomicAdd(&gbuf[k - row_lo], v);
+              atomicAdd(&gbuf[k - row_lo], (double)v);
             }
           }
         }
@@ -849,18 +855,8 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
               }
               v = r.c0 * exp2(-(x * x));
             }
-            atomicAdd(&gbuf[k - row_lo], v);
+            atomicAdd(&gbuf[k - row_lo], (double)v);
             i = (i + 1 == n) ? 0 : i + 1;
-          }
-          if constexpr (F32) {
-            // at most one line per lane went into this batch's FP32 row
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-              acc64[j] += (double)gbuf[lane + 64 * j];
-              gbuf[lane + 64 * j] = 0.0f;
-            }
-            __syncthreads();
           }
         }
       }
@@ -1268,17 +1264,6 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
           acc64[j] += (double)acc32[j];
           acc32[j] = 0.0f;
         }
-        if constexpr (GN) {
-          if (eg > e3m) {
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-              acc64[j] += (double)gbuf[lane + 64 * j];
-              gbuf[lane + 64 * j] = 0.0f;
-            }
-            __syncthreads();
-          }
-        }
       } else {
         // FP64 form: x from the exact difference nu_k - nu_i
         auto uniform = [&](int l0, int l1, auto masked, auto npairs) {
@@ -1371,7 +1356,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
       }
     }
 
-    if constexpr (GN && !F32) {
+    if constexpr (GN) {
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < M; ++j) acc64[j] += gbuf[lane + 64 * j];
