@@ -414,6 +414,35 @@ def density_2t(X, n_lines=50_000_000, n_chunks=5):
             "line_conditions_per_s": n * len(wl.conditions) / (ms / 1e3)}
 
 
+def binned_doppler_2t(X, n_lines=50_000_000, n_chunks=5):
+    """The streaming workload's lines with the binned Doppler profile (bin
+    means of the Gaussian), resident, FP32 and FP64: prepare + profile pass
+    over the 5 chunks."""
+    import torch
+    import synth
+    wl = synth.config(5, n_lines=n_lines, n_chunks=n_chunks, profile=synth.BIN_DOPPLER)
+    sizes = wl.chunk_sizes()
+    ds = X.DeviceStates.from_numpy(wl.states)
+    dls = [X.DeviceLines.from_numpy(wl.chunk(j)) for j in range(n_chunks)]
+    sig = torch.zeros((len(wl.conditions), wl.grid.n_bins), dtype=torch.float64, device="cuda")
+    out = {"lines": sum(sizes), "chunks": n_chunks, "conditions": len(wl.conditions)}
+    for prec, name in ((X.XS_FP32, "f32"), (X.XS_FP64, "f64")):
+        plan = X.Plan(wl.profile, wl.mode, wl.population, prec, wl.grid, wl.conditions, max(sizes),
+                      mass_amu=wl.mass_amu)
+        plan.cross_section(ds, dls[0], out=sig)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for j, dl in enumerate(dls):
+            plan.cross_section(ds, dl, out=sig, accumulate=j > 0)
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"ms_resident_{name}"] = round(e0.elapsed_time(e1), 2)
+        plan.close()
+    log(f"binned Doppler 2T: FP32 {out['ms_resident_f32']:.1f} ms, FP64 {out['ms_resident_f64']:.1f} ms")
+    return out
+
+
 def stream_2t(X, n_lines=50_000_000, n_chunks=5):
     """Chunk streaming of the two-temperature emission workload (4 (T_vib,
     T_rot) pairs, Doppler at T_rot, grid 0-30000 cm^-1 step 0.05): chunks held
@@ -645,6 +674,7 @@ def main():
         extras["batched_48"] = batched_48(X, wl, ds, dl, lines.n)
         extras["stream_2t"] = stream_2t(X)
         extras["density_2t"] = density_2t(X)
+        extras["binned_doppler_2t"] = binned_doppler_2t(X)
 
     # roofline of the dominant kernel (events around each launch, same stream)
     fracs = region_fractions(wl, lines, cond)

@@ -698,7 +698,8 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
   // tens of nonzero points) add their nonzero points into an LDS row instead
   // of testing every chunk of the row per line: one line per lane where it
   // has at most kLaneSpan such points, else 64 points per wave step.
-  constexpr bool GN = PROF == XS_DOPPLER || PROF == XS_GAUSSIAN;
+  constexpr bool GBIN = PROF == XS_BIN_DOPPLER || PROF == XS_BIN_GAUSSIAN;
+  constexpr bool GN = PROF == XS_DOPPLER || PROF == XS_GAUSSIAN || GBIN;
   constexpr int kLaneSpan = 96;
   // The row is FP64 in both forms.  With an FP32 row the lanes' LDS float
   // adds held the FP32 waves three quarters of the time (about 16 cycles per
@@ -771,6 +772,33 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
         qn -= n;
       }
     };
+    // value of a Gaussian line at point k of the row: the profile (sampled)
+    // or the mean over the point's bin (binned), times the line's constant
+    auto gval = [&](const Rec& rr, int k) -> double {
+      if constexpr (GBIN) {
+        if constexpr (F32) {
+          const float x = fmaf(rr.jfb + (float)(k - row_lo), rr.a, rr.nb);
+          return (double)(rr.c0 * erf_bin<float>(x, 0.5f * rr.a));
+        } else {
+          double x;
+          {
+#pragma clang fp contract(off)
+            x = (nu_of_bin(m.nu0, m.dnu, k) - rr.nu) * rr.inv;
+          }
+          return rr.c0 * erf_bin<double>(x, 0.5 * (m.dnu * rr.inv));
+        }
+      } else if constexpr (F32) {
+        const float x = fmaf(rr.jfb + (float)(k - row_lo), rr.a, rr.nb);
+        return (double)(rr.c0 * __builtin_amdgcn_exp2f(-(x * x)));
+      } else {
+        double x;
+        {
+#pragma clang fp contract(off)
+          x = (nu_of_bin(m.nu0, m.dnu, k) - rr.nu) * rr.inv;
+        }
+        return rr.c0 * exp2(-(x * x));
+      }
+    };
     // general-class Gaussian lines wider than kLaneSpan points: the points of
     // the row inside both the window and the range where 2^{-x^2} is not
     // zero, 64 at a time; every point outside that range would add an exact
@@ -792,21 +820,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
           kh = min(kh, row_lo + ROWB - 1);
           for (int k0 = kl; k0 <= kh; k0 += 64) {
             const int k = k0 + lane;
-            if (k <= kh) {
-              Real v;
-              if constexpr (F32) {
-                const float x = fmaf(rr.jfb + (float)(k - row_lo), rr.a, rr.nb);
-                v = rr.c0 * __builtin_amdgcn_exp2f(-(x * x));
-              } else {
-                double x;
-                {
-#pragma clang fp contract(off)
-                  x = (nu_of_bin(m.nu0, m.dnu, k) - rr.nu) * rr.inv;
-                }
-                v = rr.c0 * exp2(-(x * x));
-              }
-              atomicAdd(&gbuf[k - row_lo], (double)v);
-            }
+            if (k <= kh) atomicAdd(&gbuf[k - row_lo], gval(rr, k));
           }
         }
       }
@@ -843,19 +857,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
           int i = n > 0 ? lane % n : 0;
           for (int it = 0; it < n; ++it) {
             const int k = kl + i;
-            Real v;
-            if constexpr (F32) {
-              const float x = fmaf(r.jfb + (float)(k - row_lo), r.a, r.nb);
-              v = r.c0 * __builtin_amdgcn_exp2f(-(x * x));
-            } else {
-              double x;
-              {
-#pragma clang fp contract(off)
-                x = (nu_of_bin(m.nu0, m.dnu, k) - r.nu) * r.inv;
-              }
-              v = r.c0 * exp2(-(x * x));
-            }
-            atomicAdd(&gbuf[k - row_lo], (double)v);
+            atomicAdd(&gbuf[k - row_lo], gval(r, k));
             i = (i + 1 == n) ? 0 : i + 1;
           }
         }
@@ -1048,7 +1050,8 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
         }
         // general path: band per chunk (nearest point of each bin), the exact
         // angle where the series does not hold
-        for (int l = e3m; l < eg; ++l) {
+        if constexpr (GBIN) gauss_rows(e3m, eg);
+        else for (int l = e3m; l < eg; ++l) {
           const Rec& rr = srec[l];
           const Real h = hof(rr), hh = (Real)0.5 * h, c0 = rr.c0, y = rr.y, y2 = y * y, yh = y * h;
           const int klo = uni(rr.klo), khi = uni(rr.khi);

@@ -257,15 +257,19 @@ void derive(xs_plan* p) {
     cd.pfac = c.P / m.P_ref;
     cd.slot = slot;
     cd.wbins = (int32_t)std::ceil(c.cutoff / p->grid.dnu) + 2;
-    if (m.profile == XS_DOPPLER || m.profile == XS_GAUSSIAN) {
-      // 2^{-(dnu/alpha)^2} is exactly zero in the working precision once
-      // (dnu/alpha)^2 exceeds 160 (FP32) or 1100 (FP64), and a kept line has
-      // nu <= grid end + cut-off, so no line reaches a tile from farther
-      // than X alpha_max: the gather need not stage it.
-      const double X = (m.precision == XS_FP32) ? std::sqrt(160.0) : std::sqrt(1100.0);
+    if (base_profile(m.profile) == XS_DOPPLER || base_profile(m.profile) == XS_GAUSSIAN) {
+      // 2^{-(d/alpha)^2} is exactly zero in the working precision once
+      // (d/alpha)^2 exceeds 160 (FP32) or 1100 (FP64), and a bin mean once
+      // its nearer edge lies beyond 10.1 (FP32) or 27.3 (FP64) in units of
+      // alpha/sqrt(ln2); a kept line has nu <= grid end + cut-off, so no line
+      // reaches a tile from farther than that: the gather need not stage it.
+      const bool binned = m.profile >= XS_BIN_DOPPLER;
+      const bool f32 = m.precision == XS_FP32;
       const double nu_end = p->grid.nu0 + (double)(p->grid.n_bins - 1) * p->grid.dnu;
-      const double amax = (m.profile == XS_GAUSSIAN) ? m.hwhm_fixed : (nu_end + c.cutoff) * cd.dop;
-      const double reach = std::ceil(X * amax / p->grid.dnu) + 2.0;
+      const double amax = (base_profile(m.profile) == XS_GAUSSIAN) ? m.hwhm_fixed : (nu_end + c.cutoff) * cd.dop;
+      const double dmax = binned ? (f32 ? 10.1 : 27.3) / std::sqrt(kLN2) * amax + 0.5 * p->grid.dnu
+                                 : (f32 ? std::sqrt(160.0) : std::sqrt(1100.0)) * amax;
+      const double reach = std::ceil(dmax / p->grid.dnu) + 2.0;
       if (std::isfinite(reach) && reach < (double)cd.wbins) cd.wbins = (int32_t)reach;
     }
     maxcut = std::max(maxcut, c.cutoff);
@@ -438,7 +442,7 @@ int xs_plan_create(xs_plan** out, const xs_model* model, const xs_grid* grid, in
   p->stream = (hipStream_t)stream;
   // narrow Gaussians reach few buckets beyond their tile, so finer buckets
   // stage fewer lines per tile; the other profiles reach a whole cut-off
-  p->bucket_bins = (model->profile == XS_DOPPLER || model->profile == XS_GAUSSIAN) ? 64 : 256;
+  p->bucket_bins = (base_profile(model->profile) == XS_DOPPLER || base_profile(model->profile) == XS_GAUSSIAN) ? 64 : 256;
   if ((rc = hip_check(hipGetDevice(&p->device), "hipGetDevice"))) {
     delete p;
     return rc;

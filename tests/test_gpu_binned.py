@@ -133,3 +133,19 @@ def test_binned_voigt_full_size_sampled(prec):
     log(f"[binned full] prec={prec} max_rel={e:.3e} L1={l1:.3e} over {n} sampled points; {st}")
     assert n > 500
     assert e <= TOL[prec]
+
+
+@pytest.mark.parametrize("hwhm", [0.002, 0.3])
+@pytest.mark.parametrize("tile", [256, 1024])
+def test_binned_gaussian_widths(hwhm, tile):
+    """Fixed-width binned Gaussian at step 0.01 with a few nonzero bins per
+    line (one line per lane) and with more than a tile of them (whole-row
+    and 64-point wave steps)."""
+    wl = synth.config(2, n_states=5000, n_lines=3000, nu_hi=400.0, profile=synth.BIN_GAUSSIAN)
+    wl.hwhm_fixed = hwhm
+    ln = wl.lines()
+    ref = oracle.run_condition(wl, ln, wl.conditions[0]).sigma
+    for prec in (FP64, FP32):
+        got, st, _ = gpu_sigma(wl, ln, prec, config=dict(tile_bins=tile, bucket_bins=64, persistent=1,
+                                                         waves_per_cu=16))
+        _check(f"gaussian hwhm={hwhm} tile={tile}", got[0], ref, prec, st)
