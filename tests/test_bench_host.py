@@ -1,0 +1,71 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU refusal, the Voigt region
+fractions behind the flop counts, and the traffic figures' source check."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+
+
+def test_region_fractions_partition_the_evaluations():
+    wl = synth.config(2, n_states=20000, n_lines=20000, nu_hi=5000.0)
+    ln = wl.lines()
+    fr = bench.region_fractions(wl, ln, wl.conditions[0])
+    for kind, f in fr.items():
+        assert len(f) == len(bench.FLOP_REGIONS[kind])
+        assert all(x >= 0.0 for x in f)
+        assert abs(sum(f) - 1.0) < 1e-12, kind
+    # the same thresholds give the same split in both forms' outer regions
+    assert fr[("fwd", "f32")] == fr[("adj", "f32")]
+
+
+def test_region_fractions_match_a_brute_force_count():
+    """The closed form against counting |x|^2 + y^2 per grid point of the
+    windows of a few lines (grid clipping excluded: lines in the middle)."""
+    wl = synth.config(2, n_states=20000, n_lines=40, nu_hi=3000.0)
+    ln = wl.lines()
+    cond = wl.conditions[0]
+    E = wl.states.energy
+    nu = E[ln.upper] - E[ln.lower]
+    keep = (nu > 100.0) & (nu < 2900.0)
+    ln = ln.take(np.flatnonzero(keep))
+    nu = nu[keep]
+    fr = bench.region_fractions(wl, ln, cond)[("fwd", "f32")]
+    c, kb, amu = 2.99792458e10, 1.380649e-16, 1.66053906660e-24
+    alpha = nu / c * np.sqrt(2.0 * kb * cond.T * np.log(2.0) / (wl.mass_amu * amu))
+    s = alpha / np.sqrt(np.log(2.0))
+    y = ln.gamma_ref.astype(np.float64) * (296.0 / cond.T) ** ln.n_exp.astype(np.float64) * cond.P / s
+    counts = np.zeros(3)
+    step = 1e-3
+    for i in range(len(nu)):
+        d = np.arange(-cond.cutoff, cond.cutoff, step)
+        rho = (d / s[i]) ** 2 + y[i] ** 2
+        counts += [np.sum(rho >= 900.0), np.sum((rho < 900.0) & (rho >= 64.0)), np.sum(rho < 64.0)]
+    brute = counts / counts.sum()
+    assert np.allclose(fr, brute, atol=2e-4), (fr, brute)
+
+
+def test_traffic_only_for_the_current_sources():
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    with open(path) as f:
+        d = json.load(f)
+    for key in ("gather_c2_f32", "adjoint_c2_f32"):
+        got = bench.traffic_from_profiles(key)
+        if d[key]["source_hash"] == bench.source_hash():
+            assert got == d[key]["hbm_bytes_per_launch"] and got > 0
+        else:
+            assert got is None
