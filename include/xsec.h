@@ -306,9 +306,13 @@ int xs_plan_capture(xs_plan* plan, const xs_states* states, const xs_lines* line
 int xs_plan_replay(xs_plan* plan);
 
 /* Time the candidate kernel configurations on these inputs (sigma is used as
- * scratch and overwritten), keep the fastest, and cache it under cache_path
- * (JSON, keyed by device, profile, precision, window size and line count;
- * NULL: no file).  A cached entry is reused without timing. */
+ * scratch and overwritten): the plan's bucket size and the other of 64 and
+ * 256 points (the lines are re-bucketed in the plan's workspace), each with
+ * 256-, 512- and 1024-point tiles and three launch modes.  Keeps the fastest
+ * and caches it under cache_path (JSON, keyed by device, profile, precision,
+ * window size and line count; NULL: no file).  A cached entry is reused
+ * without timing.  When the chosen bucket size is not the last one tried, the
+ * next xs_cross_section re-buckets the lines. */
 int xs_plan_autotune(xs_plan* plan, const xs_states* states, const xs_lines* lines,
                      double* sigma, const char* cache_path);
 

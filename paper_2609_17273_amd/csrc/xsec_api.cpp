@@ -318,7 +318,9 @@ size_t layout(xs_plan* p, char* base, Work* w) {
   x.valB = (int32_t*)take(4 * L);
   x.hist = (int32_t*)take(4 * (size_t)256 * nsb);
   x.hsum = (int32_t*)take(4 * ((size_t)256 * nsb / 1024 + 2));
-  x.off = (int32_t*)take(4 * (size_t)(d.n_buckets + 2));
+  // sized for the finest bucket (64 points), so a change of bucket size never
+  // needs a larger workspace
+  x.off = (int32_t*)take(4 * (size_t)((p->grid.n_bins + 63) / 64 + 2));
   x.rnu = (double*)take(8 * L);
   x.rgref = (float*)take(4 * L);
   x.rnexp = (float*)take(4 * L);
@@ -783,13 +785,25 @@ int xs_plan_autotune(xs_plan* p, const xs_states* st, const xs_lines* ln, double
     (void)hipEventDestroy(e0);
     return rc;
   }
-  // candidates: tile width x launch mode (persistent queue with two grid sizes, or one block per item)
+  // candidates: bucket size (the plan's own first) x tile width x launch mode
+  // (persistent queue with two grid sizes, or one block per item)
+  const int buckets[2] = {p->bucket_bins, p->bucket_bins == 64 ? 256 : 64};
   const int tiles[3] = {256, 512, 1024};
   const int modes[3][2] = {{0, 16}, {1, 16}, {1, 32}};
   double best_ms = 1e300;
   xs_config cur;
-  cur.bucket_bins = p->bucket_bins;
   cur.chunk_lines = 0;
+  for (int bi = 0; bi < 2 && !rc; ++bi) {
+  if (buckets[bi] != p->bucket_bins) {
+    // re-bucket the lines (the workspace holds any bucket size)
+    p->bucket_bins = buckets[bi];
+    p->prepared = false;
+    derive(p);
+    layout(p, (char*)p->ws, &p->w);
+    if ((rc = upload(p))) break;
+    if ((rc = preprocess(p, st, ln))) break;
+  }
+  cur.bucket_bins = p->bucket_bins;
   for (int si = 0; si < 3 && !rc; ++si) {
     for (int mi = 0; mi < 3 && !rc; ++mi) {
       cur.tile_bins = tiles[si];
@@ -813,10 +827,13 @@ int xs_plan_autotune(xs_plan* p, const xs_states* st, const xs_lines* ln, double
       }
     }
   }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  tiling_for(p, best.tile_bins, best.persistent, best.waves_per_cu, best.chunk_lines);
+  // the best bucket size (re-bucketed on the next prepare when it is not
+  // the last one tried) and tiling
+  if ((rc = xs_plan_set_config(p, &best))) return rc;
   cache_store(cache_path, key, best, best_ms);
   return XS_OK;
 }

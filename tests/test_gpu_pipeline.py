@@ -103,6 +103,28 @@ def test_all_configurations_agree(prec):
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
+def test_autotuned_doppler_plan(prec):
+    """The autotuner also tries a second bucket size (here 256 points after the
+    Doppler plan's 64), re-bucketing the lines in place; the tuned plan still
+    matches the oracle."""
+    import torch
+    wl = workload(5, n_states=20000, n_lines=30000, n_chunks=1, nu_hi=2000.0)
+    ln = wl.lines()
+    plan = make_plan(wl, prec, ln.n)
+    ds, dl = gpu_inputs(wl, ln)
+    assert plan.get_config()["bucket_bins"] == 64
+    cfg = plan.autotune(ds, dl, torch.empty((len(wl.conditions), wl.grid.n_bins), dtype=torch.float64,
+                                            device="cuda"))
+    got = plan.cross_section(ds, dl).cpu().numpy()
+    for c, cond in enumerate(wl.conditions):
+        ref = oracle.run_condition(wl, ln, cond).sigma
+        e, _, _ = rel_err(got[c], ref)
+        assert e <= (1e-10 if prec == FP64 else 1e-4), (c, cfg, e)
+    log(f"[autotune doppler] prec={prec} {cfg}")
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
 def test_chunked_accumulation_equals_whole(prec):
     import torch
     wl = workload(5, n_states=20000, n_lines=40000, n_chunks=4, nu_hi=2000.0)
