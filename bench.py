@@ -44,19 +44,21 @@ sys.path.insert(0, ROOT)
 #                 x, scale and accumulate 4) = 190.
 #   forward FP64: 1 pair 11; 2 pairs (one division) 19; 3/4/6 pairs 30/39/57;
 #                 core N = 40: 14 + 39 x 7 + 11 + 4 = 302.
-#   adjoint FP32: 1 pair: x 2, u 1, d 3, rcp 1, e 2, t 6, accumulations of
-#                 g e, g t, g/d, g e^2 8 = 23; 2 pairs: x 2, u 1, per pair
+#   adjoint FP32: 1 pair, as every line of this workload has y^2 <= 90: x 2,
+#                 u 1, d 3, rcp 1, e 2, products g e and g/d 2, sums of g e,
+#                 g/d, g e^2, g e/d, g/d^2 8 = 19 (the per-point form used for
+#                 larger y: t 6 and four sums 8 instead, 23); 2 pairs: x 2, u 1, per pair
 #                 d, rcp, e, t 12 and their K-weighted sums 8, four
 #                 accumulations 8 = 51; core: w (N = 24, both
 #                 parts: 14 + 161 + 17), w' = -2zw + 2i/sqrt(pi) and Re G 13,
 #                 x, |z|^2 5, three accumulations 6 = 216.
-#   adjoint FP64: 1/2/3 pairs 23/51/71; 4/6 pairs (general form) 113/161;
+#   adjoint FP64: 1/2/3 pairs 19/51/71; 4/6 pairs (general form) 113/161;
 #                 core N = 40: 14 + 273 + 17 + 24 = 328.
 FLOP_REGIONS = {
     ("fwd", "f32"): [(900.0, 11), (64.0, 20), (0.0, 190)],
     ("fwd", "f64"): [(9.0e6, 11), (6400.0, 19), (400.0, 30), (144.0, 39), (64.0, 57), (0.0, 302)],
-    ("adj", "f32"): [(900.0, 23), (64.0, 51), (0.0, 216)],
-    ("adj", "f64"): [(9.0e6, 23), (6400.0, 51), (400.0, 71), (144.0, 113), (64.0, 161), (0.0, 328)],
+    ("adj", "f32"): [(900.0, 19), (64.0, 51), (0.0, 216)],
+    ("adj", "f64"): [(9.0e6, 19), (6400.0, 51), (400.0, 71), (144.0, 113), (64.0, 161), (0.0, 328)],
 }
 # MI355X vector peaks, no packed-FP32 (the kernels are compiled without packed FP32):
 # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP32
