@@ -741,6 +741,12 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
     const int64_t q1 = min(phi, q0 + chunk);
     const int row_lo = (int)tlo;
     const int my0 = row_lo + lane;  // bin of chunk 0 of this lane
+    // a masked row skips its 64-point chunks that lie wholly outside the
+    // window (a uniform branch): about 3 of a window's 80 chunks
+    auto off_chunk = [&](auto masked, int j, int klo, int khi) {
+      const int cl = row_lo + 64 * j;
+      return masked && (cl + 63 < klo || cl > khi);
+    };
 
     double acc64[M];
     float acc32[M];
@@ -914,6 +920,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
             }
 #pragma unroll
             for (int j = 0; j < M; ++j) {
+              if (off_chunk(masked, j, klo, khi)) continue;
               const Real x = xv(rr, j);
               const Real t = c0 * rcp_r<Real>(fma(x, x, (Real)1));
               const int k = my0 + 64 * j;
@@ -997,6 +1004,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
               for (int q = 0; q < NP; ++q) cp[q] = (BASE == XS_LORENTZ) ? fma(-hh, hh, (Real)1) : y2 + ((Real)tau[q] - hh * hh);
 #pragma unroll
               for (int j = 0; j < M; ++j) {
+                if (off_chunk(masked, j, klo, khi)) continue;
                 const Real x = xof(rr, j);
                 Real t;
                 if constexpr (GAU) {
@@ -1141,6 +1149,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
               const float c0 = rr.c0;
 #pragma unroll
               for (int j = 0; j < M; ++j) {
+                if (off_chunk(masked, j, klo, khi)) continue;
                 const float x = fmaf(jf0 + (float)(64 * j), a, nb);
                 if (!masked) {
                   acc32[j] = fmaf(c0, rcp32(fmaf(x, x, 1.0f)), acc32[j]);
@@ -1161,6 +1170,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
               const PairS A = rr.A;
 #pragma unroll
               for (int j = 0; j < M; ++j) {
+                if (off_chunk(masked, j, klo, khi)) continue;
                 const float x = fmaf(jf0 + (float)(64 * j), a, nb);
                 const float s = fmaf(x, x, A.h);
                 if (!masked) {
@@ -1190,6 +1200,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
               }
 #pragma unroll
               for (int j = 0; j < M; ++j) {
+                if (off_chunk(masked, j, klo, khi)) continue;
                 const float x = fmaf(jf0 + (float)(64 * j), a, nb);
                 const float t = pair_term_s(B1, x) + pair_term_s(B2, x);
                 const int k = my0 + 64 * j;
