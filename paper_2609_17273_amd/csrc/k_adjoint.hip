@@ -282,13 +282,21 @@ struct GSrc {
   R* buf;            // [2 kFlush] LDS slice of the wave
 };
 
-// SY (one node pair, every line of the wave with y^2 <= 90): the sum of
-// g x dRe w/dx terms is formed once per block from sums of g e, g/d, g e/d and
-// g/d^2 (x dRe w/dx = 2yK[4 tau ((p+q) e/d - p q/d^2 - 1/d) - (e - p/d)], from
-// u/d = e - p/d and u^2 = d - q u - p^2), two instructions per point fewer
-// than forming it per point.  With y^2 <= 90 the far region has u >= 810, so
-// p/d stays below an eighth of e and nothing cancels; for larger y (u << p
-// possible) the per-point form is kept.
+// SY (one node pair, every line of the wave with y^2 <= 450): in the shifted
+// variable s = u + h, h = y^2 - tau, the pair has d = s^2 + c, c = 4 y^2 tau,
+// and u + p = s + m, m = 2 tau, p - u = 2 y^2 - s.  Every sum the block needs
+// is then a combination of four sums
+//   S0 = sum g/d,  S1 = sum g s/d,  S2 = sum g/d^2,  S3 = sum g s/d^2
+// (with s^2/d^2 = 1/d - c/d^2):
+//   sum g e   = S1 + m S0,      sum g e^2 = (S0 - c S2) + 2 m S3 + m^2 S2,
+//   sum g (u/d)[4 tau (p - u)/d - 1]
+//             = 4 tau [-(S0 - c S2) + (2 y^2 + h) S3 - 2 y^2 h S2] - (S1 - h S0),
+// formed once per block in FP64; a point costs s, d, 1/d, g/d, g/d^2 and four
+// sums.  The only difference of like terms is S1 - h S0 = sum g u/d: in the
+// far region (rho >= 900) y^2 <= 450 gives u = rho - y^2 >= 450 >= h, so it
+// loses at most a factor 2.  Per point the other combinations are sums of
+// positive terms (bar -c/d^2 <= 1e-3/d) or enter scaled by 4 tau/d against
+// it.  For larger y (u may reach 0) the per-point form is kept.
 template <typename R, int PROF, int NP, bool SY = false>
 __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G, int r0, int r1,
                                            double& sA, double& sB, double& sC) {
@@ -302,9 +310,11 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
   R nbj[4];
 #pragma unroll
   for (int jj = 0; jj < 4; ++jj) nbj[jj] = fma((R)jj, L.a, L.nb);
+  // SY: h = q/2 (exact) and c = 4 y^2 tau = -k2 y^2
+  const R hS = (R)0.5 * L.P[0].q, cS = (R)(-(double)L.P[0].k2 * L.y * L.y);
   for (int rb = r0; rb <= r1; rb += kFlush) {
     const int n = min(kFlush, r1 - rb + 1);
-    R s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0, s6 = 0;
+    R s1 = 0, s2 = 0, s3 = 0, s4 = 0;
     auto body = [&](R x, R gk) {
       const R u = x * x;
       if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
@@ -320,16 +330,14 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
         s1 += gi;
         s2 = fma(gi, iq, s2);
       } else if constexpr (NP == 1 && SY) {
-        // s1 = sum g e, s3 = sum g / d, s4 = sum g e^2, s5 = sum g e/d, s6 = sum g/d^2
-        const R d = fma(u, u + L.P[0].q, L.P[0].p2);
-        const R rd = arcp(d);
-        const R e = (u + L.P[0].p) * rd;
-        const R ge = gk * e, grd = gk * rd;
-        s1 += ge;
-        s3 += grd;
-        s4 = fma(ge, e, s4);
-        s5 = fma(ge, rd, s5);
-        s6 = fma(grd, rd, s6);
+        // s1..s4 = S0..S3
+        const R sx = fma(x, x, hS);
+        const R rd = arcp(fma(sx, sx, cS));
+        const R grd = gk * rd, v = grd * rd;
+        s1 += grd;
+        s2 = fma(grd, sx, s2);
+        s3 += v;
+        s4 = fma(v, sx, s4);
       } else if constexpr (NP == 1) {
         // s1 = sum g e, s2 = sum g t, s3 = sum g / d, s4 = sum g e^2
         R e, rd, t;
@@ -394,13 +402,19 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
     } else {
       const double k = (NP == 1) ? (double)L.P[0].K : 1.0;
       const double y2 = L.y * L.y;
-      double ts = (double)s2;
+      // sums of g e, g t, g/d, g e^2
+      double ge = (double)s1, gt = (double)s2, gd = (double)s3, ge2 = (double)s4;
       if constexpr (SY) {
-        const double pp = (double)L.P[0].p, qq = (double)L.P[0].q, c4 = -(double)L.P[0].k2;  // 4 tau
-        ts = c4 * ((pp + qq) * (double)s5 - pp * qq * (double)s6 - (double)s3) - ((double)s1 - pp * (double)s3);
+        const double t4 = -(double)L.P[0].k2, m = 0.5 * t4, h = (double)hS, c = (double)cS;
+        const double S0 = (double)s1, S1 = (double)s2, S2 = (double)s3, S3 = (double)s4;
+        const double sq = S0 - c * S2;  // sum g s^2/d^2
+        ge = S1 + m * S0;
+        gd = S0;
+        ge2 = sq + 2.0 * m * S3 + m * m * S2;
+        gt = t4 * ((2.0 * y2 + h) * S3 - sq - 2.0 * y2 * h * S2) - (S1 - h * S0);
       }
-      const double e = k * (double)s1, t = k * ts;
-      const double w = k * ((double)s1 + 2.0 * y2 * (double)s3 - 4.0 * y2 * (double)s4);  // dRe w/dy
+      const double e = k * ge, t = k * gt;
+      const double w = k * (ge + 2.0 * y2 * gd - 4.0 * y2 * ge2);  // dRe w/dy
       sA += L.y * e;                      // Re w
       sB += L.y * (e + 2.0 * t) + L.y * w; // Re w + x dRe w/dx + y dRe w/dy
       sC -= w;                            // Im w' = -dRe w/dy
@@ -497,7 +511,7 @@ __device__ __forceinline__ Sums3 window_sums(bool on, int64_t klo, int64_t khi, 
   G.lds = (int64_t)wave_max(on ? L.kc : -0x7fffffff) - G.kcmin <= kFlush;
   G.buf = gbuf;
   // every line of the wave narrow enough in y for the block-summed far form
-  const bool small_y = __ballot(on && !(y * y <= 90.0)) == 0;
+  const bool small_y = __ballot(on && !(y * y <= 450.0)) == 0;
   if (on) {
     int r = Rmin;
     while (r <= Rmax) {
