@@ -44,29 +44,28 @@ sys.path.insert(0, ROOT)
 #                 x, scale and accumulate 4) = 190.
 #   forward FP64: 1 pair 11; 2 pairs (one division) 19; 3/4/6 pairs 30/39/57;
 #                 core N = 40: 14 + 39 x 7 + 11 + 4 = 302.
-#   adjoint FP32: 1 pair, in a wave whose lines all have y^2 <= 450 (the
-#                 block-summed form): x 2, s 2, d 2, rcp 1, g/d and g/d^2 2,
-#                 sums of g/d, g s/d, g/d^2, g s/d^2 6 = 15; in the other
-#                 waves (per-point form): x 2, u 1, d 3, rcp 1, e 2, t 6, four
-#                 sums 8 = 23; the table's figure is the block-summed one and
-#                 flops_per_eval weights the two by the share of waves
-#                 (ADJ_FAR_FLOPS); 2 pairs: x 2, u 1, per pair
+#   adjoint FP32: in a wave whose lines all have y^2 at most half the
+#                 region's rho bound (the block-summed form), x 2 and per
+#                 pair s 2, d 2, rcp 1, g/d and g/d^2 2, sums of g/d, g s/d,
+#                 g/d^2, g s/d^2 6 = 13: 1 pair 15, 2 pairs 28 (3 pairs 41);
+#                 in the other waves (per-point form) 1 pair: x 2, u 1, d 3,
+#                 rcp 1, e 2, t 6, four sums 8 = 23; 2 pairs: x 2, u 1, per pair
 #                 d, rcp, e, t 12 and their K-weighted sums 8, four
 #                 accumulations 8 = 51; core: w (N = 24, both
 #                 parts: 14 + 161 + 17), w' = -2zw + 2i/sqrt(pi) and Re G 13,
 #                 x, |z|^2 5, three accumulations 6 = 216.
-#   adjoint FP64: 1/2/3 pairs 15 (or 23)/51/71; 4/6 pairs (general form) 113/161;
+#   adjoint FP64: 1/2/3 pairs 15/28/41 (per-point form 23/51/71); 4/6 pairs
+#                 (general form) 113/161;
 #                 core N = 40: 14 + 273 + 17 + 24 = 328.
 FLOP_REGIONS = {
     ("fwd", "f32"): [(900.0, 11), (64.0, 20), (0.0, 190)],
     ("fwd", "f64"): [(9.0e6, 11), (6400.0, 19), (400.0, 30), (144.0, 39), (64.0, 57), (0.0, 302)],
-    ("adj", "f32"): [(900.0, 15), (64.0, 51), (0.0, 216)],
-    ("adj", "f64"): [(9.0e6, 15), (6400.0, 51), (400.0, 71), (144.0, 113), (64.0, 161), (0.0, 328)],
+    ("adj", "f32"): [(900.0, 15), (64.0, 28), (0.0, 216)],
+    ("adj", "f64"): [(9.0e6, 15), (6400.0, 28), (400.0, 41), (144.0, 113), (64.0, 161), (0.0, 328)],
 }
-# adjoint, outermost region: (block-summed form, per-point form), and the y^2
-# bound of the block-summed form
-ADJ_FAR_FLOPS = (15, 23)
-ADJ_BLOCK_Y2 = 450.0
+# adjoint regions with a block-summed form (the table's figure): the flops of
+# the per-point form used in the other waves
+ADJ_POINT_FLOPS = {"f32": [23, 51], "f64": [23, 51, 71]}
 # MI355X vector peaks, no packed-FP32 (the kernels are compiled without packed FP32):
 # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP32
 # and FP64 alike.  The published 157.3 TFLOP/s FP32 figure needs packed math.
@@ -107,11 +106,11 @@ def region_fractions(wl, lines, cond):
     return out
 
 
-def adj_block_share(wl, lines, cond):
+def adj_block_share(wl, lines, cond, y2max):
     """Share of the adjoint's waves (64 neighbouring lines in wavenumber order)
-    whose lines all have y^2 <= ADJ_BLOCK_Y2, i.e. that take the block-summed
-    far form.  Every line has the same window, so it is also (up to the
-    lines' core regions) the share of the far-region evaluations."""
+    whose lines all have y^2 <= y2max, i.e. that take the block-summed form of
+    a region whose rho bound is 2 y2max.  Every line has the same window, so
+    it also approximates the share of that region's evaluations."""
     import numpy as np
     c, kb, amu = 2.99792458e10, 1.380649e-16, 1.66053906660e-24
     E = wl.states.energy
@@ -125,13 +124,23 @@ def adj_block_share(wl, lines, cond):
     n = len(y)
     pad = np.zeros((-n) % 64)
     wmax = np.concatenate([y * y, pad]).reshape(-1, 64).max(axis=1)
-    return float(np.mean(wmax <= ADJ_BLOCK_Y2))
+    return float(np.mean(wmax <= y2max))
 
 
-def flops_per_eval(fracs, kind, block_share=1.0):
+def adj_block_shares(wl, lines, cond, prec="f32"):
+    """adj_block_share for each adjoint region with a block-summed form."""
+    regs = FLOP_REGIONS[("adj", prec)]
+    return [adj_block_share(wl, lines, cond, 0.5 * regs[j][0]) for j in range(len(ADJ_POINT_FLOPS[prec]))]
+
+
+def flops_per_eval(fracs, kind, block_shares=None):
+    """Flops per evaluation averaged over the regions; for the adjoint the
+    regions with a block-summed form weight it and the per-point form by the
+    share of waves taking each (all block-summed when no shares are given)."""
     fl = [f for _, f in FLOP_REGIONS[kind]]
-    if kind[0] == "adj":
-        fl[0] = block_share * ADJ_FAR_FLOPS[0] + (1.0 - block_share) * ADJ_FAR_FLOPS[1]
+    if kind[0] == "adj" and block_shares is not None:
+        for j, (sh, pt) in enumerate(zip(block_shares, ADJ_POINT_FLOPS[kind[1]])):
+            fl[j] = sh * fl[j] + (1.0 - sh) * pt
     return sum(f * x for f, x in zip(fracs[kind], fl))
 
 
@@ -711,10 +720,10 @@ def main():
 
     # roofline of the dominant kernel (events around each launch, same stream)
     fracs = region_fractions(wl, lines, cond)
-    share = adj_block_share(wl, lines, cond)
+    shares = adj_block_shares(wl, lines, cond)
     rl = {}
     for kind, ms in (("fwd", per32["forward"]), ("adj", per32["adjoint"])):
-        fpe = flops_per_eval(fracs, (kind, "f32"), share)
+        fpe = flops_per_eval(fracs, (kind, "f32"), shares)
         flops = fpe * pairs
         ach = flops / (ms / 1e3) / 1e12
         key = "gather_c2_f32" if kind == "fwd" else "adjoint_c2_f32"
@@ -725,7 +734,7 @@ def main():
                     "region_fractions": [round(f, 5) for f in fracs[(kind, "f32")]],
                     "evals_per_launch": pairs}
         if kind == "adj":
-            rl[kind]["block_summed_wave_share"] = round(share, 4)
+            rl[kind]["block_summed_wave_share"] = [round(x, 4) for x in shares]
     dom = "adj" if per32["adjoint"] >= per32["forward"] else "fwd"
     other = "fwd" if dom == "adj" else "adj"
 

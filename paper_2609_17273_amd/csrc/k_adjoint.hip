@@ -282,21 +282,23 @@ struct GSrc {
   R* buf;            // [2 kFlush] LDS slice of the wave
 };
 
-// SY (one node pair, every line of the wave with y^2 <= 450): in the shifted
-// variable s = u + h, h = y^2 - tau, the pair has d = s^2 + c, c = 4 y^2 tau,
-// and u + p = s + m, m = 2 tau, p - u = 2 y^2 - s.  Every sum the block needs
-// is then a combination of four sums
+// SY, the block-summed form of a level (every line of the wave with y^2 at
+// most half the level's rho bound): in the shifted variable s = u + h,
+// h = y^2 - tau, a node pair has d = s^2 + c, c = 4 y^2 tau, and
+// u + p = s + m, m = 2 tau, p - u = 2 y^2 - s.  Every sum the block needs is
+// then, pair by pair, a combination of four sums
 //   S0 = sum g/d,  S1 = sum g s/d,  S2 = sum g/d^2,  S3 = sum g s/d^2
 // (with s^2/d^2 = 1/d - c/d^2):
 //   sum g e   = S1 + m S0,      sum g e^2 = (S0 - c S2) + 2 m S3 + m^2 S2,
 //   sum g (u/d)[4 tau (p - u)/d - 1]
 //             = 4 tau [-(S0 - c S2) + (2 y^2 + h) S3 - 2 y^2 h S2] - (S1 - h S0),
-// formed once per block in FP64; a point costs s, d, 1/d, g/d, g/d^2 and four
-// sums.  The only difference of like terms is S1 - h S0 = sum g u/d: in the
-// far region (rho >= 900) y^2 <= 450 gives u = rho - y^2 >= 450 >= h, so it
-// loses at most a factor 2.  Per point the other combinations are sums of
-// positive terms (bar -c/d^2 <= 1e-3/d) or enter scaled by 4 tau/d against
-// it.  For larger y (u may reach 0) the per-point form is kept.
+// formed once per block in FP64 and weighted by K; a point costs, per pair,
+// s, d, 1/d, g/d, g/d^2 and four sums.  The only difference of like terms is
+// S1 - h S0 = sum g u/d: in a level's region (rho >= R) y^2 <= R/2 gives
+// u = rho - y^2 >= R/2 >= h, so it loses at most a factor 2.  Per point the
+// other combinations are sums of positive terms (bar -c/d^2, with c/d below
+// 0.09 for every level) or enter scaled by 4 tau/d against it.  For larger y
+// (u may reach 0) the per-point form is kept.
 template <typename R, int PROF, int NP, bool SY = false>
 __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G, int r0, int r1,
                                            double& sA, double& sB, double& sC) {
@@ -310,11 +312,19 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
   R nbj[4];
 #pragma unroll
   for (int jj = 0; jj < 4; ++jj) nbj[jj] = fma((R)jj, L.a, L.nb);
-  // SY: h = q/2 (exact) and c = 4 y^2 tau = -k2 y^2
-  const R hS = (R)0.5 * L.P[0].q, cS = (R)(-(double)L.P[0].k2 * L.y * L.y);
+  // SY: per pair h = q/2 (exact) and c = 4 y^2 tau = -k2 y^2
+  R hS[NP], cS[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    hS[q] = (R)0.5 * L.P[q].q;
+    cS[q] = (R)(-(double)L.P[q].k2 * L.y * L.y);
+  }
   for (int rb = r0; rb <= r1; rb += kFlush) {
     const int n = min(kFlush, r1 - rb + 1);
     R s1 = 0, s2 = 0, s3 = 0, s4 = 0;
+    R B[SY ? NP : 1][4];  // SY: S0..S3 per pair
+#pragma unroll
+    for (int q = 0; q < (SY ? NP : 1); ++q) B[q][0] = B[q][1] = B[q][2] = B[q][3] = 0;
     auto body = [&](R x, R gk) {
       const R u = x * x;
       if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
@@ -329,15 +339,17 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
         const R gi = gk * iq;
         s1 += gi;
         s2 = fma(gi, iq, s2);
-      } else if constexpr (NP == 1 && SY) {
-        // s1..s4 = S0..S3
-        const R sx = fma(x, x, hS);
-        const R rd = arcp(fma(sx, sx, cS));
-        const R grd = gk * rd, v = grd * rd;
-        s1 += grd;
-        s2 = fma(grd, sx, s2);
-        s3 += v;
-        s4 = fma(v, sx, s4);
+      } else if constexpr (SY) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          const R sx = fma(x, x, hS[q]);
+          const R rd = arcp(fma(sx, sx, cS[q]));
+          const R grd = gk * rd, v = grd * rd;
+          B[q][0] += grd;
+          B[q][1] = fma(grd, sx, B[q][1]);
+          B[q][2] += v;
+          B[q][3] = fma(v, sx, B[q][3]);
+        }
       } else if constexpr (NP == 1) {
         // s1 = sum g e, s2 = sum g t, s3 = sum g / d, s4 = sum g e^2
         R e, rd, t;
@@ -400,18 +412,24 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
       sA += (double)s1;
       sC += (double)s1 - 2.0 * (double)s2;
     } else {
-      const double k = (NP == 1) ? (double)L.P[0].K : 1.0;
+      const double k = (NP == 1 && !SY) ? (double)L.P[0].K : 1.0;
       const double y2 = L.y * L.y;
-      // sums of g e, g t, g/d, g e^2
+      // sums of g e, g t, g/d, g e^2 (K-weighted over the pairs but for the
+      // one-pair per-point form)
       double ge = (double)s1, gt = (double)s2, gd = (double)s3, ge2 = (double)s4;
       if constexpr (SY) {
-        const double t4 = -(double)L.P[0].k2, m = 0.5 * t4, h = (double)hS, c = (double)cS;
-        const double S0 = (double)s1, S1 = (double)s2, S2 = (double)s3, S3 = (double)s4;
-        const double sq = S0 - c * S2;  // sum g s^2/d^2
-        ge = S1 + m * S0;
-        gd = S0;
-        ge2 = sq + 2.0 * m * S3 + m * m * S2;
-        gt = t4 * ((2.0 * y2 + h) * S3 - sq - 2.0 * y2 * h * S2) - (S1 - h * S0);
+        ge = gt = gd = ge2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          const double K = (double)L.P[q].K, t4 = -(double)L.P[q].k2, m = 0.5 * t4;
+          const double h = (double)hS[q], c = (double)cS[q];
+          const double S0 = (double)B[q][0], S1 = (double)B[q][1], S2 = (double)B[q][2], S3 = (double)B[q][3];
+          const double sq = S0 - c * S2;  // sum g s^2/d^2
+          ge += K * (S1 + m * S0);
+          gd += K * S0;
+          ge2 += K * (sq + 2.0 * m * S3 + m * m * S2);
+          gt += K * (t4 * ((2.0 * y2 + h) * S3 - sq - 2.0 * y2 * h * S2) - (S1 - h * S0));
+        }
       }
       const double e = k * ge, t = k * gt;
       const double w = k * (ge + 2.0 * y2 * gd - 4.0 * y2 * ge2);  // dRe w/dy
@@ -424,9 +442,14 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
 
 template <typename R, int PROF>
 __device__ __forceinline__ void fast_level(int level, const AdjLine<R>& L, const GSrc<R>& G, int r0, int r1,
-                                           double& sA, double& sB, double& sC, bool small_y = false) {
-  if (PROF == XS_VOIGT && level == 0 && small_y) fast_range<R, PROF, 1, true>(L, G, r0, r1, sA, sB, sC);
-  else if (PROF != XS_VOIGT || level == 0) fast_range<R, PROF, 1>(L, G, r0, r1, sA, sB, sC);
+                                           double& sA, double& sB, double& sC, bool blocksum = false) {
+  if (PROF == XS_VOIGT && blocksum) {
+    if (level == 0) fast_range<R, PROF, 1, true>(L, G, r0, r1, sA, sB, sC);
+    else if (level == 1) fast_range<R, PROF, 2, true>(L, G, r0, r1, sA, sB, sC);
+    else if constexpr (sizeof(R) == 8) fast_range<R, PROF, 3, true>(L, G, r0, r1, sA, sB, sC);
+    return;
+  }
+  if (PROF != XS_VOIGT || level == 0) fast_range<R, PROF, 1>(L, G, r0, r1, sA, sB, sC);
   else if (level == 1) fast_range<R, PROF, 2>(L, G, r0, r1, sA, sB, sC);
   else if constexpr (sizeof(R) == 8) fast_range<R, PROF, 3>(L, G, r0, r1, sA, sB, sC);
 }
@@ -510,8 +533,12 @@ __device__ __forceinline__ Sums3 window_sums(bool on, int64_t klo, int64_t khi, 
   G.kcmin = wave_min(on ? L.kc : 0x7fffffff);
   G.lds = (int64_t)wave_max(on ? L.kc : -0x7fffffff) - G.kcmin <= kFlush;
   G.buf = gbuf;
-  // every line of the wave narrow enough in y for the block-summed far form
-  const bool small_y = __ballot(on && !(y * y <= 450.0)) == 0;
+  // levels whose block-summed form every line of the wave allows (bit l:
+  // y^2 at most half of level l's rho bound)
+  int blk = 0;
+#pragma unroll
+  for (int q = 0; q < NL; ++q)
+    if (__ballot(on && !(y * y <= 0.5 * Levels<R>::rho[q])) == 0) blk |= 1 << q;
   if (on) {
     int r = Rmin;
     while (r <= Rmax) {
@@ -549,15 +576,15 @@ __device__ __forceinline__ Sums3 window_sums(bool on, int64_t klo, int64_t khi, 
           L3.P[0] = pair_d<R>(y, GH::t6[0], GH::w6[0]);
           L3.P[1] = pair_d<R>(y, GH::t6[1], GH::w6[1]);
           L3.P[2] = pair_d<R>(y, GH::t6[2], GH::w6[2]);
-          fast_level<R, PROF>(2, L3, G, r, end, sA, sB, sC);
+          fast_level<R, PROF>(2, L3, G, r, end, sA, sB, sC, (blk >> 2) & 1);
         } else if (PROF == XS_VOIGT && mode == 0) {
           AdjLine<R> L1 = L;
-          fast_level<R, PROF>(0, L1, G, r, end, sA, sB, sC, small_y);
+          fast_level<R, PROF>(0, L1, G, r, end, sA, sB, sC, blk & 1);
         } else if (PROF == XS_VOIGT && mode == 1) {
           AdjLine<R> L2 = L;
           L2.P[0] = L.P[1];
           L2.P[1] = L.P[2];
-          fast_level<R, PROF>(1, L2, G, r, end, sA, sB, sC);
+          fast_level<R, PROF>(1, L2, G, r, end, sA, sB, sC, (blk >> 1) & 1);
         } else {
           fast_level<R, PROF>(0, L, G, r, end, sA, sB, sC);
         }

@@ -72,15 +72,22 @@ def test_traffic_only_for_the_current_sources():
 
 
 def test_adjoint_block_share_limits():
-    """The share of adjoint waves in the block-summed form: all of them at a
-    vanishing pressure, none at a huge one, and falling as y grows with P."""
+    """The share of adjoint waves in a block-summed form: all of them at a
+    vanishing pressure, none at a huge one, and falling as y grows with P;
+    the flop average moves between the two forms with it."""
     wl = synth.config(2, n_states=20000, n_lines=5000, nu_hi=3000.0)
     ln = wl.lines()
-    share = [bench.adj_block_share(wl, ln, synth.Condition(2000.0, P, 25.0)) for P in (1e-6, 0.3, 3.0, 1e4)]
+    share = [bench.adj_block_share(wl, ln, synth.Condition(2000.0, P, 25.0), 450.0) for P in (1e-6, 0.3, 3.0, 1e4)]
     assert share[0] == 1.0 and share[-1] == 0.0
     assert share[0] >= share[1] >= share[2] >= share[3]
     assert 0.0 < share[1] < 1.0
-    fr = bench.region_fractions(wl, ln, wl.conditions[0])
-    lo, hi = (bench.flops_per_eval(fr, ("adj", "f32"), s) for s in (1.0, 0.0))
-    d = bench.ADJ_FAR_FLOPS[1] - bench.ADJ_FAR_FLOPS[0]
-    assert abs((hi - lo) - fr[("adj", "f32")][0] * d) < 1e-12
+    cond = wl.conditions[0]
+    sh = bench.adj_block_shares(wl, ln, cond)
+    assert len(sh) == 2 and sh[0] >= sh[1]    # the inner region asks for a smaller y
+    fr = bench.region_fractions(wl, ln, cond)
+    k = ("adj", "f32")
+    lo, hi = bench.flops_per_eval(fr, k, [1.0, 1.0]), bench.flops_per_eval(fr, k, [0.0, 0.0])
+    assert lo == bench.flops_per_eval(fr, k)
+    want = sum(f * (pt - bl) for f, pt, bl in zip(fr[k], bench.ADJ_POINT_FLOPS["f32"],
+                                                  [x for _, x in bench.FLOP_REGIONS[k]]))
+    assert abs((hi - lo) - want) < 1e-12
