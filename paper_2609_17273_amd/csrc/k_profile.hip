@@ -57,20 +57,23 @@ __device__ __forceinline__ LineParams line_params(const ModelDev& m, const CondD
   return lp;
 }
 
-// Far-region pair constants (cW, cW p, q, p^2) for node pair (tau, W).
+// Far-region constants of node pair (tau, W) in the shifted variable
+// s = x^2 + h, h = y^2 - tau: the pair's term is cW (s + 2 tau)/(s^2 + c),
+// c = 4 y^2 tau (the same fraction as cW (u + p)/(u^2 + q u + p^2) with
+// u = x^2, p = y^2 + tau, q = 2 y^2 - 2 tau, one operation fewer).
 template <typename R>
 struct Pair {
-  R cw, cwp, q, p2;
+  R cw, cwt, h, c;  // cW, cW 2 tau, y^2 - tau, 4 y^2 tau
 };
 template <typename R>
 __device__ __forceinline__ Pair<R> make_pair(double c0, double y, double tau, double W) {
-  const double y2 = y * y, p = y2 + tau;
+  const double y2 = y * y;
   const double cw = c0 * (2.0 * y / kPI) * W;
   Pair<R> r;
   r.cw = (R)cw;
-  r.cwp = (R)(cw * p);
-  r.q = (R)(2.0 * y2 - 2.0 * tau);
-  r.p2 = (R)(p * p);
+  r.cwt = (R)(cw * (2.0 * tau));
+  r.h = (R)(y2 - tau);
+  r.c = (R)(4.0 * y2 * tau);
   return r;
 }
 
@@ -625,16 +628,18 @@ __device__ __forceinline__ double rcp64(double d) {
 }
 
 template <typename R>
-__device__ __forceinline__ R pair_term(const Pair<R>& P, R u) {
-  const R n = fma(P.cw, u, P.cwp);
-  const R d = fma(u, u + P.q, P.p2);
+__device__ __forceinline__ R pair_term(const Pair<R>& P, R x) {
+  const R s = fma(x, x, P.h);
+  const R n = fma(P.cw, s, P.cwt);
+  const R d = fma(s, s, P.c);
   if constexpr (sizeof(R) == 4) return n * rcp32(d);
   else return n * rcp64(d);
 }
 // two pairs as one fraction (FP64 only: the product of the d_j stays finite)
-__device__ __forceinline__ double pair2_term(const Pair<double>& P, const Pair<double>& Q, double u) {
-  const double n1 = fma(P.cw, u, P.cwp), d1 = fma(u, u + P.q, P.p2);
-  const double n2 = fma(Q.cw, u, Q.cwp), d2 = fma(u, u + Q.q, Q.p2);
+__device__ __forceinline__ double pair2_term(const Pair<double>& P, const Pair<double>& Q, double x) {
+  const double s1 = fma(x, x, P.h), s2 = fma(x, x, Q.h);
+  const double n1 = fma(P.cw, s1, P.cwt), d1 = fma(s1, s1, P.c);
+  const double n2 = fma(Q.cw, s2, Q.cwt), d2 = fma(s2, s2, Q.c);
   return fma(n1, d2, n2 * d1) * rcp64(d1 * d2);
 }
 // NP node pairs from y (near-core chunks of the FP64 form; out of line, rare)
@@ -1307,9 +1312,9 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
               const double u = xs[j] * xs[j];
               if (PROF == XS_LORENTZ) t = rr.c0 * rcp64(fma(xs[j], xs[j], 1.0));
               else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) t = rr.c0 * exp2(-u);
-              else if (NP == 1) t = pair_term<double>(rr.A, u);
-              else if (NP == 2) t = pair2_term(rr.B1, rr.B2, u);
-              else t = pair_term<double>(C[0], u) + pair2_term(C[1], C[2], u);
+              else if (NP == 1) t = pair_term<double>(rr.A, xs[j]);
+              else if (NP == 2) t = pair2_term(rr.B1, rr.B2, xs[j]);
+              else t = pair_term<double>(C[0], xs[j]) + pair2_term(C[1], C[2], xs[j]);
               const int k = my0 + 64 * j;
               if (!masked || (k >= klo && k <= khi)) acc64[j] += t;
             }
@@ -1351,9 +1356,9 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
             } else {
               const double u = x * x;
               if (!meets(cl, ch, KRange{uni(rr.r[0].lo), uni(rr.r[0].hi)})) {
-                v = pair_term<double>(rr.A, u);
+                v = pair_term<double>(rr.A, x);
               } else if (!meets(cl, ch, KRange{uni(rr.r[1].lo), uni(rr.r[1].hi)})) {
-                v = pair2_term(rr.B1, rr.B2, u);
+                v = pair2_term(rr.B1, rr.B2, x);
               } else if (!meets(cl, ch, KRange{uni(rr.r[2].lo), uni(rr.r[2].hi)})) {
                 v = gh_pairs_y<3>(rr.c0, rr.y, u);
               } else if (!meets(cl, ch, KRange{uni(rr.r[3].lo), uni(rr.r[3].hi)})) {
