@@ -340,15 +340,28 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
         s1 += gi;
         s2 = fma(gi, iq, s2);
       } else if constexpr (SY) {
+        R sx[NP], rd[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) sx[q] = fma(x, x, hS[q]);
+        if constexpr (sizeof(R) == 8 && NP >= 2) {
+          // FP64: one reciprocal (and Newton step) for the first two pairs,
+          // 1/d0 = d1/(d0 d1) and 1/d1 = d0/(d0 d1); d0 d1 stays finite
+          const R d0 = fma(sx[0], sx[0], cS[0]), d1 = fma(sx[1], sx[1], cS[1]);
+          const R r = arcp(d0 * d1);
+          rd[0] = d1 * r;
+          rd[1] = d0 * r;
+          if constexpr (NP == 3) rd[2] = arcp(fma(sx[2], sx[2], cS[2]));
+        } else {
+#pragma unroll
+          for (int q = 0; q < NP; ++q) rd[q] = arcp(fma(sx[q], sx[q], cS[q]));
+        }
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-          const R sx = fma(x, x, hS[q]);
-          const R rd = arcp(fma(sx, sx, cS[q]));
-          const R grd = gk * rd, v = grd * rd;
+          const R grd = gk * rd[q], v = grd * rd[q];
           B[q][0] += grd;
-          B[q][1] = fma(grd, sx, B[q][1]);
+          B[q][1] = fma(grd, sx[q], B[q][1]);
           B[q][2] += v;
-          B[q][3] = fma(v, sx, B[q][3]);
+          B[q][3] = fma(v, sx[q], B[q][3]);
         }
       } else if constexpr (NP == 1) {
         // s1 = sum g e, s2 = sum g t, s3 = sum g / d, s4 = sum g e^2
