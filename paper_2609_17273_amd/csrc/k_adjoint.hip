@@ -243,9 +243,16 @@ __device__ __forceinline__ void general_eval(const AdjLine<R>& L, bool wide, int
       const R y = (R)L.y;
       const R rho = x * x + y * y;
       int band;
-      if (sizeof(R) == 4) band = rho >= (R)(900.0 * 1.001) ? 1 : rho >= (R)(64.0 * 1.001) ? 2
-                               : rho >= (R)(36.0 * 1.001) ? 3 : 0;
-      else band = rho >= (R)(9.0e6 * 1.001) ? 1 : rho >= (R)(6400.0 * 1.001) ? 2 : rho >= (R)(400.0 * 1.001) ? 3
+      if (sizeof(R) == 4) {
+        band = rho >= (R)(900.0 * 1.001) ? 1 : rho >= (R)(64.0 * 1.001) ? 2 : rho >= (R)(36.0 * 1.001) ? 3 : 0;
+        // when a lane of the wave needs the rational approximation, the lanes
+        // of the three-pair band (rho < 64) take it too, so the wave does not
+        // run both; there w and w' = -2zw + 2i/sqrt(pi) keep absolute errors
+        // below 5e-9, as in the core (further out, the cancellation in w'
+        // grows with |z|^2, so the two-pair band keeps its own formula)
+        const bool core_in_wave = __ballot(band == 0) != 0;  // every active lane votes
+        if (band == 3 && core_in_wave) band = 0;
+      } else band = rho >= (R)(9.0e6 * 1.001) ? 1 : rho >= (R)(6400.0 * 1.001) ? 2 : rho >= (R)(400.0 * 1.001) ? 3
                 : rho >= (R)(144.0 * 1.001) ? 4 : rho >= (R)(64.0 * 1.001) ? 6 : 0;
       const Grad3<R> v = voigt_grad<R>(x, y, band);
       f = (double)v.f;
