@@ -719,6 +719,9 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
   const int n_items = uni(g.ib[g.n_ct]);
   const int64_t chunk = *(const int64_t*)(g.counter + 4);
   const float lane_off = (float)lane;
+  float lane_j[M];  // lane + 64 j: a point's offset from the tile's first point
+#pragma unroll
+  for (int j = 0; j < M; ++j) lane_j[j] = (float)(lane + 64 * j);
   int item = blockIdx.x;
   for (;;) {
     if (g.persistent) {
@@ -873,21 +876,26 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
           }
         }
       }
-      // LDS order: F1 | F1M | F2 | F2M | F3 | F3M (FP64) | general
-      const unsigned long long b1 = __ballot(cls == kRowF1);
+      // LDS order: F1 (FP32 Voigt: those taking x from the tile's first
+      // point, then the others) | F1M | F2 | F2M | F3 | F3M (FP64) | general
+      bool xb_ok = false;
+      if constexpr (F32 && PROF == XS_VOIGT) xb_ok = cls == kRowF1 && r.a <= 2.0f;
+      const unsigned long long b1x = __ballot(xb_ok);
+      const unsigned long long b1 = __ballot(cls == kRowF1 && !xb_ok);
       const unsigned long long b1m = __ballot(cls == kRowF1M);
       const unsigned long long b2 = __ballot(cls == kRowF2);
       const unsigned long long b2m = __ballot(cls == kRowF2M);
       const unsigned long long b3 = F32 ? 0ull : __ballot(cls == kRowF3);
       const unsigned long long b3m = F32 ? 0ull : __ballot(cls == kRowF3M);
       const unsigned long long bg = __ballot(cls == kRowGeneral);
-      const int e1 = __popcll(b1), e1m = e1 + __popcll(b1m), e2 = e1m + __popcll(b2);
+      const int e1x = __popcll(b1x), e1 = e1x + __popcll(b1), e1m = e1 + __popcll(b1m), e2 = e1m + __popcll(b2);
       const int e2m = e2 + __popcll(b2m), e3 = e2m + __popcll(b3), e3m = e3 + __popcll(b3m);
       const int eg = e3m + __popcll(bg);
       if (eg == 0) continue;
       unsigned long long mine = bg;
       int base = e3m;
-      if (cls == kRowF1) { mine = b1; base = 0; }
+      if (xb_ok) { mine = b1x; base = 0; }
+      else if (cls == kRowF1) { mine = b1; base = e1x; }
       else if (cls == kRowF1M) { mine = b1m; base = e1; }
       else if (cls == kRowF2) { mine = b2; base = e1m; }
       else if (cls == kRowF2M) { mine = b2m; base = e2; }
@@ -1141,7 +1149,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
         // x = (k - k_c) a - b, with k - k_c = (tlo - k_c) + (offset in tile):
         // integers, exact in FP32 within a window
         // ---- first formula; then the same under the window mask ----
-        auto first = [&](int l0, int l1, auto masked) {
+        auto first = [&](int l0, int l1, auto masked, auto from_xb) {
           for (int l = l0; l < l1; ++l) {
             const RecF& rr = srec[l];
             const float a = rr.a, nb = rr.nb, jf0 = rr.jfb + lane_off;
@@ -1173,24 +1181,41 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
               }
             } else {
               const PairS A = rr.A;
+              // x from the tile's first point xb = x(tlo) (rows sorted first
+              // by the compaction): one operation per line instead of one per
+              // chunk.  Rounding xb costs an absolute error eps |xb| <=
+              // eps (|x| + 255 a) in x; in the one-pair region
+              // (s = x^2 + h >= 899.5) that moves s by a relative
+              // 2 eps (1 + 255 a/30) at most, below 2.2e-6 for a <= 2.  Wider
+              // steps (a > 2: lines narrower than half a bin) keep the exact
+              // fma over the integer offset.
+              auto run = [&](auto xof) {
 #pragma unroll
-              for (int j = 0; j < M; ++j) {
-                if (off_chunk(masked, j, klo, khi)) continue;
-                const float x = fmaf(jf0 + (float)(64 * j), a, nb);
-                const float s = fmaf(x, x, A.h);
-                if (!masked) {
-                  acc32[j] = fmaf(fmaf(A.cw, s, A.cwt), rcp32(fmaf(s, s, A.c)), acc32[j]);
-                } else {
-                  const int k = my0 + 64 * j;
-                  const float t = fmaf(A.cw, s, A.cwt) * rcp32(fmaf(s, s, A.c));
-                  acc32[j] += (k >= klo && k <= khi) ? t : 0.0f;
+                for (int j = 0; j < M; ++j) {
+                  if (off_chunk(masked, j, klo, khi)) continue;
+                  const float x = xof(j);
+                  const float s = fmaf(x, x, A.h);
+                  if (!masked) {
+                    acc32[j] = fmaf(fmaf(A.cw, s, A.cwt), rcp32(fmaf(s, s, A.c)), acc32[j]);
+                  } else {
+                    const int k = my0 + 64 * j;
+                    const float t = fmaf(A.cw, s, A.cwt) * rcp32(fmaf(s, s, A.c));
+                    acc32[j] += (k >= klo && k <= khi) ? t : 0.0f;
+                  }
                 }
+              };
+              if constexpr (decltype(from_xb)::value) {
+                const float xb = fmaf(rr.jfb, a, nb);
+                run([&](int j) { return fmaf(lane_j[j], a, xb); });
+              } else {
+                run([&](int j) { return fmaf(jf0 + (float)(64 * j), a, nb); });
               }
             }
           }
         };
-        first(0, e1, std::false_type());
-        first(e1, e1m, std::true_type());
+        first(0, e1x, std::false_type(), std::true_type());
+        first(e1x, e1, std::false_type(), std::false_type());
+        first(e1, e1m, std::true_type(), std::false_type());
         // ---- second formula (Voigt: two node pairs), unmasked then masked ----
         if (PROF == XS_VOIGT) {
           auto second = [&](int l0, int l1, auto masked) {
