@@ -29,10 +29,12 @@ def _norm_err(a, b):
 
 _ORACLE = {}
 _WIDE = (synth.Condition(1900.0, 0.7, 25.0), synth.Condition(2500.0, 3.0, 25.0))
-# low pressures: of the waves of 64 neighbouring lines, about 89% (0.05 bar)
-# and 56% (0.2 bar) have every y^2 <= 90, and 6% and 23% every y^2 in
-# (90, 450], the two ranges of the adjoint's block-summed far form; at 0.7 bar
-# 22% lie in (90, 450] and the rest above it
+# low pressures, for the adjoint's block-summed forms (a level's form when
+# every line of a wave of 64 neighbouring lines has y^2 at most half the
+# level's rho bound).  Waves with every y^2 <= 32 / 450 (FP32 two- / one-pair
+# levels): 81% / 95% at 0.05 bar, 24% / 79% at 0.2 bar, 0% / 22% at 0.7 bar;
+# FP64 (<= 200 / 3200 for the three- / two-pair levels): 92% / 98%, 70% / 92%
+# and 1% / 70%
 _NARROW = (synth.Condition(2200.0, 0.05, 25.0), synth.Condition(2200.0, 0.2, 25.0))
 
 
