@@ -1012,6 +1012,26 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
             const int nt = GAU ? 4 : uni(rr.pad0);
             auto run = [&](auto nterms) {
               constexpr int NT = decltype(nterms)::value;
+              if constexpr (BASE == XS_VOIGT && NP == 1 && NT == 1) {
+                // one node pair, first series term: c0 2 y h (W/pi) P/D with
+                // P = x^2 + y^2 + tau - hh^2 and D = P^2 - 4 tau x^2, in the
+                // shifted variable s = x^2 + (y^2 - tau - hh^2):
+                // P = s + 2 tau, D = s^2 + 4 tau (y^2 - hh^2) (the same
+                // fraction; the per-point work of the sampled far form)
+                const double t0 = tau[0];
+                const Real sh = y2 - (Real)t0 - hh * hh, cc = (Real)(4.0 * t0) * (y2 - hh * hh);
+                const Real K = c0 * (Real)2 * yh * (Real)(gh_w<1>()[0] / kPI), K2 = K * (Real)(2.0 * t0);
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                  if (off_chunk(masked, j, klo, khi)) continue;
+                  const Real x = xof(rr, j);
+                  const Real sv = fma(x, x, sh);
+                  const Real v = fma(K, sv, K2) * rcp_r<Real>(fma(sv, sv, cc));
+                  const int k = my0 + 64 * j;
+                  add(j, (!masked || (k >= klo && k <= khi)) ? v : (Real)0);
+                }
+                return;
+              }
               Real cp[NP];
 #pragma unroll
               for (int q = 0; q < NP; ++q) cp[q] = (BASE == XS_LORENTZ) ? fma(-hh, hh, (Real)1) : y2 + ((Real)tau[q] - hh * hh);
