@@ -259,7 +259,11 @@ int xs_cross_section(xs_plan* plan, const xs_states* states, const xs_lines* lin
  * alpha ~ sqrt(T) and the pressure width gamma = gamma_ref (T_ref/T)^n P/P_ref.
  * The profile windows are recomputed; no (line, bin) pairs are stored.
  * dL_dgamma_ref and dL_dn_exp may be NULL.  With per-line gamma_ref/n_exp NULL
- * (scalars), their gradients are still returned per line. */
+ * (scalars), their gradients are still returned per line.  The FP32 form sums
+ * window blocks of g/d and g/d^2 terms in FP32 (d >= 64^2 in the far wing), so
+ * it keeps its accuracy for cotangents |dL_dsigma| above about 1e-26 (below,
+ * terms leave the FP32 normal range: scale the loss); the FP64 form has no
+ * such limit. */
 int xs_cross_section_adjoint(xs_plan* plan, const xs_states* states, const xs_lines* lines,
                              const double* dL_dsigma, double* dL_dT, double* dL_dP,
                              double* dL_dgamma_ref, double* dL_dn_exp, double* dL_dlog_scale);
