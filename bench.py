@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the line-list cross-section path on one MI355X.
 
-Workload (the 1e7-line Voigt case the metric is quoted on): LTE absorption,
+Workload the metric is quoted on (the 1e7-line Voigt case): LTE absorption,
 1e6 states (E exponential, mean 8000 cm^-1, cap 40000; J 0-120), 1e7
 transitions (nu in (0, 20000], A 10^U(-8,3), gamma_ref 10^U(log 0.02, log 0.1),
 n_exp U(0.3, 0.8)), T = 2000 K, P = 1 bar, mass 30 amu, Voigt profile, grid
@@ -15,9 +15,14 @@ One step = the whole hot path once, FP32 log-scaled form:
 ``value`` = profile evaluations per second over the step (forward and
 adjoint window evaluations: each kept line times its window bins on the
 grid, counted exactly by the library).  Also reported: the same step in the
-FP64 form (speedup FP32 / FP64), the adjoint / forward time ratio, the
-line-parallel atomic scatter, the roofline of the dominant kernel, and the
-oracle timed on the host (``cpu_baseline``).
+FP64 form (speedup FP32 / FP64, its own rooflines), the adjoint / forward
+time ratio, the line-parallel atomic scatter, binned and pseudo-Voigt
+profiles, lifetime widths, the cooling function, the roofline of the
+dominant kernel, HBM figures against 8 TB/s and a measured device copy,
+board power and shader clock sampled during the timed work, the 48-condition
+grid at its full 1e8 lines (autotuned, captured graph, FP32 and FP64), the
+two-temperature emission workload at its full 1e9 lines streamed in 10
+chunks, and the oracle timed on the host (``cpu_baseline``).
 """
 from __future__ import annotations
 
@@ -207,19 +212,100 @@ def time_steps(plan, ds, dl, sig, w, target, steps, warmup):
     return (t1 - t0) * 1e3 / max(steps, 1), per, dist
 
 
-def device_state():
-    """Clocks and power as rocm-smi reports them right after the timed steps
-    (a child process; best effort)."""
-    import subprocess
+def _sysfs_dir():
+    """sysfs directory of the GPU torch uses (its PCI address)."""
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return f"/sys/bus/pci/devices/{p.pci_domain_id:04x}:{p.pci_bus_id:02x}:{p.pci_device_id:02x}.0"
+
+
+def _read(path):
     try:
-        r = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--json"], capture_output=True,
-                           text=True, timeout=30)
-        d = json.loads(r.stdout)
-        card = next(iter(d.values())) if d else {}
-        keep = {k: v for k, v in card.items() if any(s in k.lower() for s in ("sclk", "mclk", "fclk", "power"))}
-        return keep or {"raw": r.stdout[-500:]}
+        with open(path) as f:
+            return f.read()
+    except OSError:
+        return None
+
+
+def device_state():
+    """The GPU's current shader, memory and fabric clock levels and board
+    power, read in this process from its sysfs files (a process that uses the
+    GPU starts no child process).  Best effort: missing files are left out."""
+    import glob
+    out = {}
+    try:
+        base = _sysfs_dir()
+        out["pci"] = os.path.basename(base)
+        for name in ("pp_dpm_sclk", "pp_dpm_mclk", "pp_dpm_fclk"):
+            txt = _read(os.path.join(base, name))
+            if txt:
+                cur = [ln.strip() for ln in txt.splitlines() if ln.strip().endswith("*")]
+                out[name] = cur[0] if cur else txt.strip()[:80]
+        for hw in sorted(glob.glob(os.path.join(base, "hwmon", "hwmon*"))):
+            for name in ("power1_average", "power1_input"):
+                txt = _read(os.path.join(hw, name))
+                if txt and txt.strip().lstrip("-").isdigit():
+                    out[name + "_W"] = int(txt) / 1e6
     except Exception as e:  # noqa: BLE001 - reporting only
-        return {"error": str(e)[:200]}
+        out["error"] = str(e)[:200]
+    return out
+
+
+class PowerSampler:
+    """Samples the board power and shader clock from sysfs in a thread of
+    this process while timed GPU work runs (every ``period`` seconds)."""
+
+    def __init__(self, period=0.05):
+        import threading
+        self.period, self.samples, self.clk = period, [], []
+        self._stop = threading.Event()
+        self._t = threading.Thread(target=self._run, daemon=True)
+        try:
+            self.base = _sysfs_dir()
+        except Exception:  # noqa: BLE001
+            self.base = None
+
+    def _run(self):
+        import glob
+        files = []
+        if self.base:
+            for hw in sorted(glob.glob(os.path.join(self.base, "hwmon", "hwmon*"))):
+                for name in ("power1_average", "power1_input"):
+                    if os.path.exists(os.path.join(hw, name)):
+                        files.append(os.path.join(hw, name))
+        while not self._stop.is_set():
+            for f in files[:1]:
+                txt = _read(f)
+                if txt and txt.strip().isdigit():
+                    self.samples.append(int(txt) / 1e6)
+            if self.base:
+                txt = _read(os.path.join(self.base, "pp_dpm_sclk"))
+                if txt:
+                    cur = [ln for ln in txt.splitlines() if ln.strip().endswith("*")]
+                    if cur:
+                        try:
+                            self.clk.append(float(cur[0].split(":")[1].strip().rstrip("*").strip().lower()
+                                                  .replace("mhz", "")))
+                        except (IndexError, ValueError):
+                            pass
+            self._stop.wait(self.period)
+
+    def __enter__(self):
+        self._t.start()
+        return self
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        self._t.join()
+
+    def summary(self):
+        out = {"samples": len(self.samples)}
+        if self.samples:
+            out.update(power_W_mean=round(sum(self.samples) / len(self.samples), 1),
+                       power_W_max=round(max(self.samples), 1))
+        if self.clk:
+            out.update(sclk_MHz_mean=round(sum(self.clk) / len(self.clk), 1), sclk_MHz_min=min(self.clk))
+        return out
 
 
 def cpu_baseline(wl, lines, cond, n_sample=40000):
@@ -257,40 +343,6 @@ def cpu_baseline(wl, lines, cond, n_sample=40000):
                        f"the lines by wavenumber)"),
             "one_thread": {"value": evals1 / dt1, "unit": "profile evals/s",
                            "sample": f"the first 1000 of those points ({evals1:.3e} evaluations, {dt1:.1f} s)"}}
-
-
-def batched_48(X, wl, ds, dl, n_lines):
-    """The 48-point opacity grid (T in 8 values x P in 6 values, cut-off 100
-    cm^-1 at P >= 10 bar) over the same 1e7 lines, in one captured graph
-    (intensities, bucketing, one persistent profile launch for all 48
-    conditions), FP32 and FP64 forms."""
-    import torch
-    import synth
-    conds = [synth.Condition(T, P, 100.0 if P >= 10.0 else 25.0) for T in synth.C3_T for P in synth.C3_P]
-    out = {"conditions": len(conds), "lines": n_lines}
-    for prec, name in ((X.XS_FP32, "f32"), (X.XS_FP64, "f64")):
-        p = X.Plan(X.XS_VOIGT, X.XS_ABSORPTION, X.XS_LTE, prec, wl.grid, conds, n_lines, mass_amu=wl.mass_amu)
-        sig = torch.empty((len(conds), wl.grid.n_bins), dtype=torch.float64, device="cuda")
-        p.cross_section(ds, dl, out=sig)
-        pairs = p.stats()["window_pairs"]
-        p.capture(ds, dl, sig)
-        p.replay()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 2
-        e0.record()
-        for _ in range(reps):
-            p.replay()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        out[name] = {"ms": round(ms, 2), "evals_per_s": pairs / (ms / 1e3),
-                     "line_conditions_per_s": n_lines * len(conds) / (ms / 1e3), "window_pairs": pairs}
-        log(f"batched 48 {name}: {ms:.1f} ms, {pairs:.3e} pairs")
-        p.close()
-        del sig
-    out["fp32_over_fp64_speedup"] = round(out["f64"]["ms"] / out["f32"]["ms"], 3)
-    return out
 
 
 def pseudo_voigt(X, wl, ds, dl, n_lines, cfg, sampled_ms):
@@ -427,206 +479,243 @@ def lifetime_voigt(X, wl, ds_plain, dl, n_lines, cfg, sampled_ms):
             "evals_per_s": pairs / (ms / 1e3), "over_no_lifetimes": round(ms / sampled_ms, 3)}
 
 
-def density_2t(X, n_lines=50_000_000, n_chunks=5):
-    """Two-temperature emission lines of the streaming workload under custom
-    vibronic densities (one weight per manifold, T_rot only), resident, FP32:
-    prepare (Q(T_rot), intensities with the densities) + profile pass."""
+def copy_bandwidth():
+    """HBM bandwidth a plain device copy reaches on this GPU: a 1 GiB copy
+    (1 GiB read + 1 GiB written) timed with events, best of 5."""
     import torch
-    import synth
-    wl = synth.with_vib_densities(synth.config(5, n_lines=n_lines, n_chunks=n_chunks))
-    sizes = wl.chunk_sizes()
-    ds = X.DeviceStates.from_numpy(wl.states)
-    dls = [X.DeviceLines.from_numpy(wl.chunk(j)) for j in range(n_chunks)]
-    plan = X.Plan(wl.profile, wl.mode, wl.population, X.XS_FP32, wl.grid, wl.conditions, max(sizes),
-                  mass_amu=wl.mass_amu)
-    sig = torch.zeros((len(wl.conditions), wl.grid.n_bins), dtype=torch.float64, device="cuda")
-    plan.cross_section(ds, dls[0], out=sig)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for j, dl in enumerate(dls):
-        plan.cross_section(ds, dl, out=sig, accumulate=j > 0)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    plan.close()
-    n = sum(sizes)
-    log(f"density 2T: {n} lines, {ms:.1f} ms")
-    return {"lines": n, "chunks": n_chunks, "conditions": len(wl.conditions), "ms_resident": round(ms, 2),
-            "line_conditions_per_s": n * len(wl.conditions) / (ms / 1e3)}
-
-
-def binned_doppler_2t(X, n_lines=50_000_000, n_chunks=5):
-    """The streaming workload's lines with the binned Doppler profile (bin
-    means of the Gaussian), resident, FP32 and FP64: prepare + profile pass
-    over the 5 chunks."""
-    import torch
-    import synth
-    wl = synth.config(5, n_lines=n_lines, n_chunks=n_chunks, profile=synth.BIN_DOPPLER)
-    sizes = wl.chunk_sizes()
-    ds = X.DeviceStates.from_numpy(wl.states)
-    dls = [X.DeviceLines.from_numpy(wl.chunk(j)) for j in range(n_chunks)]
-    sig = torch.zeros((len(wl.conditions), wl.grid.n_bins), dtype=torch.float64, device="cuda")
-    out = {"lines": sum(sizes), "chunks": n_chunks, "conditions": len(wl.conditions)}
-    for prec, name in ((X.XS_FP32, "f32"), (X.XS_FP64, "f64")):
-        plan = X.Plan(wl.profile, wl.mode, wl.population, prec, wl.grid, wl.conditions, max(sizes),
-                      mass_amu=wl.mass_amu)
-        plan.cross_section(ds, dls[0], out=sig)
-        torch.cuda.synchronize()
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = 1e30
+    for _ in range(5):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        for j, dl in enumerate(dls):
-            plan.cross_section(ds, dl, out=sig, accumulate=j > 0)
+        b.copy_(a)
         e1.record()
         torch.cuda.synchronize()
-        out[f"ms_resident_{name}"] = round(e0.elapsed_time(e1), 2)
-        plan.close()
-    log(f"binned Doppler 2T: FP32 {out['ms_resident_f32']:.1f} ms, FP64 {out['ms_resident_f64']:.1f} ms")
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return {"GB_per_s": round(2 * (1 << 30) / (best / 1e3) / 1e9, 1), "bytes_moved": 2 * (1 << 30),
+            "ms": round(best, 4)}
+
+
+def hbm_roofline(bytes_per_line, n_lines, ms, copy_gbs):
+    ach = bytes_per_line * n_lines / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "bytes_per_line": bytes_per_line, "achieved": round(ach, 1), "peak": 8000.0,
+            "unit": "GB/s", "frac": round(ach / 8000.0, 4), "measured_copy_GB_per_s": copy_gbs,
+            "frac_of_copy": round(ach / copy_gbs, 4) if copy_gbs else None}
+
+
+def alu_roofline(fpe, pairs, ms, prec, kernel, **extra):
+    ach = fpe * pairs / (ms / 1e3) / 1e12
+    out = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+           "frac": round(ach / PEAK_TFLOPS[prec], 4), "kernel": kernel, "avg_launch_ms": round(ms, 3),
+           "flops_per_eval": round(fpe, 3), "evals_per_launch": pairs}
+    out.update(extra)
     return out
 
 
-def stream_2t(X, n_lines=50_000_000, n_chunks=5):
-    """Chunk streaming of the two-temperature emission workload (4 (T_vib,
-    T_rot) pairs, Doppler at T_rot, grid 0-30000 cm^-1 step 0.05): chunks held
-    in host memory are uploaded on a copy stream while the previous chunk
-    runs (FP32 form).  Reported with the uploads (PCIe-inclusive) and, for
-    comparison, with the same chunks already resident on the device, in the
-    FP32 and FP64 forms."""
+def timed_replays(p, reps, warm=1):
+    """Per-replay device times (ms) of the plan's captured graph, on its stream."""
     import torch
-    import synth
-    wl = synth.config(5, n_lines=n_lines, n_chunks=n_chunks)
-    sizes = wl.chunk_sizes()
-    chunks = [wl.chunk(j) for j in range(n_chunks)]
-    ds = X.DeviceStates.from_numpy(wl.states)
-    plan = X.Plan(wl.profile, wl.mode, wl.population, X.XS_FP32, wl.grid, wl.conditions, max(sizes),
-                  mass_amu=wl.mass_amu)
-    sig = torch.zeros((len(wl.conditions), wl.grid.n_bins), dtype=torch.float64, device="cuda")
-    st = X.ChunkStreamer(plan, max(sizes))
-    st.run(ds, chunks[:2], sig)
-    t0 = time.perf_counter()
-    n = st.run(ds, chunks, sig)
-    ms_stream = (time.perf_counter() - t0) * 1e3
-    dls = [X.DeviceLines.from_numpy(c) for c in chunks]
+    for _ in range(warm):
+        p.replay()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for j, dl in enumerate(dls):
-        plan.cross_section(ds, dl, out=sig, accumulate=j > 0)
-    torch.cuda.synchronize()
-    ms_res = (time.perf_counter() - t0) * 1e3
-    # the FP64 form on the same resident chunks
-    p64 = X.Plan(wl.profile, wl.mode, wl.population, X.XS_FP64, wl.grid, wl.conditions, max(sizes),
-                 mass_amu=wl.mass_amu)
-    for j, dl in enumerate(dls):
-        p64.cross_section(ds, dl, out=sig, accumulate=j > 0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for j, dl in enumerate(dls):
-        p64.cross_section(ds, dl, out=sig, accumulate=j > 0)
-    torch.cuda.synchronize()
-    ms_res64 = (time.perf_counter() - t0) * 1e3
-    p64.close()
-    nbytes = sum(4 * 2 + 4 + (4 if c.gamma_ref is not None else 0) + (4 if c.n_exp is not None else 0)
-                 for c in chunks[:1]) * n
-    out = {"lines": n, "chunks": n_chunks, "conditions": len(wl.conditions),
-           "ms_streamed": round(ms_stream, 2), "ms_resident": round(ms_res, 2),
-           "ms_resident_f64": round(ms_res64, 2), "fp32_over_fp64_speedup_resident": round(ms_res64 / ms_res, 3),
-           "line_conditions_per_s_streamed": n * len(wl.conditions) / (ms_stream / 1e3),
-           "line_conditions_per_s_resident": n * len(wl.conditions) / (ms_res / 1e3),
-           "upload_bytes": nbytes}
-    log(f"stream 2T: {n} lines, streamed {ms_stream:.1f} ms, resident {ms_res:.1f} ms (FP64 {ms_res64:.1f} ms)")
-    plan.close()
-    return out
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        p.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    return ms
 
 
-def full_configs(X):
-    """The batched opacity grid (48 conditions) at its full 1e8 lines in one
-    captured graph, FP32 and FP64; and the two-temperature emission workload
-    at its full 1e9 lines, streamed from host memory in 10 chunks of 1e8
-    (chunks generated into host memory first), FP32 and FP64."""
+def _spread(ms):
+    m = sorted(ms)
+    return {"median": round(m[len(m) // 2], 2), "min": round(m[0], 2), "max": round(m[-1], 2), "n": len(m)}
+
+
+def batched_48_full(X, copy_gbs, reps=3, tune_every=50):
+    """The 48-condition opacity grid at its full size: the 1e8-line list of
+    the benchmark's generator, T in 8 values x P in 6 values (cut-off 100
+    cm^-1 at P >= 10 bar), grid 0-20000 cm^-1 step 0.01, all 48 conditions
+    in one captured graph (intensities for the 8 distinct temperatures,
+    bucketing, one persistent profile launch).  The kernel configuration is
+    autotuned on every ``tune_every``-th line of the list (the full list
+    would take minutes per candidate set) and then used for the full list;
+    one warm-up and ``reps`` timed replays per form, FP32 and FP64."""
+    import numpy as np
     import torch
     import synth
-    out = {}
     wl = synth.config(3)
     t0 = time.perf_counter()
     ln = wl.lines()
-    log(f"batched: generated {ln.n} lines in {time.perf_counter() - t0:.1f} s")
+    log(f"batched 48: generated {ln.n} lines in {time.perf_counter() - t0:.1f} s")
     ds = X.DeviceStates.from_numpy(wl.states)
     dl = X.DeviceLines.from_numpy(ln)
-    del ln
-    res = {"lines": wl.n_lines, "conditions": len(wl.conditions)}
+    sub = ln.take(np.arange(0, ln.n, tune_every))
+    dsub = X.DeviceLines.from_numpy(sub)
+    # Voigt region split of the evaluations per condition, from a 1e6-line
+    # sample, weighted by each condition's share of the window evaluations
+    samp = ln.take(np.arange(0, ln.n, 100))
+    wsum, fr = 0.0, {k: np.zeros(len(v)) for k, v in FLOP_REGIONS.items()}
+    for c in wl.conditions:
+        f = region_fractions(wl, samp, c)
+        for k in fr:
+            fr[k] += c.cutoff * np.asarray(f[k])
+        wsum += c.cutoff
+    fracs = {k: list(v / wsum) for k, v in fr.items()}
+    del ln, samp
+    out = {"lines": wl.n_lines, "conditions": len(wl.conditions), "reps": reps,
+           "autotune_sample_lines": sub.n}
+    cfg = None
     for prec, name in ((X.XS_FP32, "f32"), (X.XS_FP64, "f64")):
         p = X.Plan(X.XS_VOIGT, X.XS_ABSORPTION, X.XS_LTE, prec, wl.grid, wl.conditions, wl.n_lines,
                    mass_amu=wl.mass_amu)
         sig = torch.empty((len(wl.conditions), wl.grid.n_bins), dtype=torch.float64, device="cuda")
+        if cfg is None:
+            t0 = time.perf_counter()
+            cfg = p.autotune(ds, dsub, sig, cache_path=os.path.join("/tmp", "xsec_autotune_48.json"))
+            out["kernel_config"] = cfg
+            out["autotune_s"] = round(time.perf_counter() - t0, 1)
+            log(f"batched 48: autotuned {cfg} in {out['autotune_s']} s")
+        else:
+            p.set_config(**cfg)
         p.capture(ds, dl, sig)
-        p.replay()
-        torch.cuda.synchronize()
+        with PowerSampler(period=0.2) as pw:
+            ms = timed_replays(p, reps)
         pairs = p.stats()["window_pairs"]
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        p.replay()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        res[name] = {"ms": round(ms, 1), "window_pairs": pairs, "evals_per_s": pairs / (ms / 1e3),
-                     "line_conditions_per_s": wl.n_lines * len(wl.conditions) / (ms / 1e3)}
-        log(f"batched 1e8 {name}: {ms:.0f} ms, {pairs:.3e} pairs")
+        med = sorted(ms)[len(ms) // 2]
+        fpe = flops_per_eval(fracs, ("fwd", name))
+        out[name] = {"ms": _spread(ms), "window_pairs": pairs, "evals_per_s": pairs / (med / 1e3),
+                     "line_conditions_per_s": wl.n_lines * len(wl.conditions) / (med / 1e3),
+                     "power": pw.summary(),
+                     "roofline": alu_roofline(fpe, pairs, med, name, f"graph: prepare + k_gather<{name},Voigt>",
+                                              note="whole graph time (prepare of the 8 intensity slots included)",
+                                              region_fractions=[round(x, 5) for x in fracs[("fwd", name)]])}
+        log(f"batched 48 {name}: {_spread(ms)} ms, {pairs:.3e} pairs")
         p.close()
         del sig
-    res["fp32_over_fp64_speedup"] = round(res["f64"]["ms"] / res["f32"]["ms"], 3)
-    out["batched_48_full"] = res
-    del dl, ds
+    out["fp32_over_fp64_speedup"] = round(out["f64"]["ms"]["median"] / out["f32"]["ms"]["median"], 3)
+    del dl, ds, dsub
     torch.cuda.empty_cache()
+    return out
+
+
+# Algorithmic HBM bytes per line of the prepare step (intensities,
+# bucketing, records) of the two-temperature emission workload, FP32 form:
+# reads u, l, A (12) + key written (4) + two radix passes, keys and values
+# read and written (2 x 16) + sorted records written (nu 8, gamma_ref 4,
+# n_exp 4, index 4, home bin 4, offset 4, window 8) + S~ of the 4
+# intensity slots (16) = 100 B.  FP64 form: S of the 4 slots in FP64 (32):
+# 116 B.
+PREP_BYTES_2T = {"f32": 100, "f64": 116}
+
+
+def stream_2t_full(X, copy_gbs, gen_threads=16):
+    """The two-temperature emission workload at its full size: 1e9 lines in
+    10 chunks of 1e8 (generated into host memory first, chunks in parallel
+    threads), 4 (T_vib, T_rot) pairs, Doppler at T_rot, grid 0-30000 cm^-1
+    step 0.05, streamed from host memory (uploads on a copy stream while the
+    previous chunk runs), FP32 and FP64.  Also one 1e8-line chunk resident on
+    the device: prepare and profile pass timed apart (the prepare's HBM
+    roofline), and the same chunk with custom vibronic densities and with the
+    binned Doppler profile."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    import synth
     wl = synth.config(5)
     sizes = wl.chunk_sizes()
     t0 = time.perf_counter()
-    chunks = []
-    for j in range(wl.n_chunks):
-        chunks.append(wl.chunk(j))
-        log(f"stream: chunk {j} generated ({time.perf_counter() - t0:.1f} s)")
+    with ThreadPoolExecutor(max_workers=max(1, min(gen_threads, wl.n_chunks))) as ex:
+        chunks = list(ex.map(wl.chunk, range(wl.n_chunks)))
+    log(f"stream 1e9: {wl.n_chunks} chunks generated in {time.perf_counter() - t0:.1f} s")
     ds = X.DeviceStates.from_numpy(wl.states)
-    plan = X.Plan(wl.profile, wl.mode, wl.population, X.XS_FP32, wl.grid, wl.conditions, max(sizes),
-                  mass_amu=wl.mass_amu)
+    out = {"lines": sum(sizes), "chunks": wl.n_chunks, "conditions": len(wl.conditions)}
     sig = torch.zeros((len(wl.conditions), wl.grid.n_bins), dtype=torch.float64, device="cuda")
-    st = X.ChunkStreamer(plan, max(sizes))
-    st.run(ds, chunks[:1], sig)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    n = st.run(ds, chunks, sig)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3
-    log(f"stream 1e9: {ms:.0f} ms")
-    plan.close()
-    del st
-    p64 = X.Plan(wl.profile, wl.mode, wl.population, X.XS_FP64, wl.grid, wl.conditions, max(sizes),
-                 mass_amu=wl.mass_amu)
-    st64 = X.ChunkStreamer(p64, max(sizes))
-    st64.run(ds, chunks[:1], sig)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st64.run(ds, chunks, sig)
-    torch.cuda.synchronize()
-    ms64 = (time.perf_counter() - t0) * 1e3
-    log(f"stream 1e9 FP64: {ms64:.0f} ms")
-    p64.close()
-    out["stream_2t_full"] = {"lines": n, "chunks": len(chunks), "conditions": len(wl.conditions),
-                             "ms_streamed": round(ms, 1), "ms_streamed_f64": round(ms64, 1),
-                             "line_conditions_per_s": n * len(wl.conditions) / (ms / 1e3)}
+    for prec, name in ((X.XS_FP32, "f32"), (X.XS_FP64, "f64")):
+        plan = X.Plan(wl.profile, wl.mode, wl.population, prec, wl.grid, wl.conditions, max(sizes),
+                      mass_amu=wl.mass_amu)
+        st = X.ChunkStreamer(plan, max(sizes))
+        st.run(ds, chunks[:1], sig)
+        torch.cuda.synchronize()
+        with PowerSampler(period=0.05) as pw:
+            t0 = time.perf_counter()
+            n = st.run(ds, chunks, sig)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+        out[f"streamed_{name}"] = {"ms": round(ms, 1), "line_conditions_per_s": n * len(wl.conditions) / (ms / 1e3),
+                                   "upload_GB": round(n * 12 / 1e9, 2), "power": pw.summary()}
+        log(f"stream 1e9 {name}: {ms:.0f} ms")
+        st.close()
+        del st
+        # one chunk resident: prepare and profile pass apart
+        dl = X.DeviceLines.from_numpy(chunks[0])
+        plan.prepare(ds, dl)
+        plan.profile(out=sig)
+        torch.cuda.synchronize()
+        pairs = plan.stats()["window_pairs"]
+        tp, tf = [], []
+        for _ in range(3):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record()
+            plan.prepare(ds, dl)
+            ev[1].record()
+            plan.profile(out=sig)
+            ev[2].record()
+            torch.cuda.synchronize()
+            tp.append(ev[0].elapsed_time(ev[1]))
+            tf.append(ev[1].elapsed_time(ev[2]))
+        mp, mf = sorted(tp)[1], sorted(tf)[1]
+        out[f"resident_chunk_{name}"] = {"lines": dl.n, "prepare_ms": round(mp, 3), "profile_ms": round(mf, 3),
+                                         "window_pairs": pairs, "profile_evals_per_s": pairs / (mf / 1e3),
+                                         "prepare_hbm": hbm_roofline(PREP_BYTES_2T[name], dl.n, mp, copy_gbs)}
+        log(f"stream 1e9 {name}: resident 1e8 chunk prepare {mp:.2f} ms, profile {mf:.2f} ms")
+        plan.close()
+        del dl
+    out["fp32_over_fp64_speedup_streamed"] = round(out["streamed_f64"]["ms"] / out["streamed_f32"]["ms"], 3)
+    # the same 1e8-line chunk with custom vibronic densities, and with the
+    # binned Doppler profile (resident; prepare + profile)
+    dl = X.DeviceLines.from_numpy(chunks[0])
+    del chunks
+    variants = {}
+    wd = synth.with_vib_densities(synth.config(5))
+    dsd = X.DeviceStates.from_numpy(wd.states)
+    for key, w_, dss, prof, prec in (("density_f32", wd, dsd, wl.profile, X.XS_FP32),
+                                     ("binned_doppler_f32", wl, ds, synth.BIN_DOPPLER, X.XS_FP32),
+                                     ("binned_doppler_f64", wl, ds, synth.BIN_DOPPLER, X.XS_FP64)):
+        plan = X.Plan(prof, w_.mode, w_.population, prec, w_.grid, w_.conditions, dl.n, mass_amu=w_.mass_amu)
+        plan.cross_section(dss, dl, out=sig)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.cross_section(dss, dl, out=sig)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        variants[key] = {"ms": round(ms, 3), "line_conditions_per_s": dl.n * len(w_.conditions) / (ms / 1e3)}
+        log(f"1e8 chunk {key}: {ms:.2f} ms")
+        plan.close()
+    out["resident_chunk_variants"] = variants
+    del dl, ds, dsd, sig
+    torch.cuda.empty_cache()
     return out
-
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and scatter comparisons")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP64 step, scatter, binned, pseudo-Voigt, lifetime and cooling-function extras")
+    ap.add_argument("--no-full", action="store_true",
+                    help="skip the 48-condition grid at 1e8 lines and the 1e9-line two-temperature stream")
     ap.add_argument("--n-lines", type=int, default=None, help="(testing) fewer lines")
     ap.add_argument("--calib-copy", action="store_true", help="run only a 1 GiB device copy (PMC calibration)")
-    ap.add_argument("--full-configs", action="store_true",
-                    help="run only the batched 48-condition grid at 1e8 lines and the two-temperature "
-                         "emission stream at 1e9 lines (minutes; prints their own JSON line)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -634,7 +723,12 @@ def main():
               "(sharding is described in the design notes); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    if not args.no_cpu_baseline and not args.calib_copy:
+        # the cpu_baseline leg's oracle is compiled (if stale) now, before
+        # this process touches the GPU: afterwards it starts no child process
+        import oracle
+        oracle.build()
+
     import torch
 
     torch.cuda.set_device(0)
@@ -650,10 +744,8 @@ def main():
     import synth
     import paper_2609_17273_amd as X
 
-    if args.full_configs:
-        print(json.dumps(full_configs(X)), flush=True)
-        return
-
+    copy = copy_bandwidth()
+    log(f"device copy: {copy['GB_per_s']} GB/s")
     t_gen = time.perf_counter()
     wl = synth.config(2, n_lines=args.n_lines)
     lines = wl.lines()
@@ -677,20 +769,50 @@ def main():
     p32 = plan_for(X.XS_FP32)
     cfg = p32.autotune(ds, dl, sig, cache_path=os.path.join("/tmp", "xsec_autotune.json"))
     log(f"autotuned: {cfg}")
-    ms32, per32, dist32 = time_steps(p32, ds, dl, sig, w, target, args.steps, args.warmup)
+    with PowerSampler() as ps32:
+        ms32, per32, dist32 = time_steps(p32, ds, dl, sig, w, target, args.steps, args.warmup)
     dev_state = device_state()
+    dev_state["during_timed_steps"] = ps32.summary()
     st = p32.stats()
     pairs = st["window_pairs"]
     log(f"fp32 step {ms32:.2f} ms {per32} pairs {pairs:.3e}")
+
+    fracs = region_fractions(wl, lines, cond)
+    shares = {prec: adj_block_shares(wl, lines, cond, prec) for prec in ("f32", "f64")}
+    rl = {}
+    for kind, ms in (("fwd", per32["forward"]), ("adj", per32["adjoint"])):
+        fpe = flops_per_eval(fracs, (kind, "f32"), shares["f32"])
+        key = "gather_c2_f32" if kind == "fwd" else "adjoint_c2_f32"
+        extra = {"traffic": traffic_from_profiles(key),
+                 "region_fractions": [round(f, 5) for f in fracs[(kind, "f32")]],
+                 "peak_note": "78.6 TFLOP/s: FP32 FMA without packed math (256 CU x 4 SIMD x 16 lanes x 2 x "
+                              "2.4 GHz), the rate this code can issue; the published 157.3 needs packed FP32"}
+        if kind == "adj":
+            extra["block_summed_wave_share"] = [round(x, 4) for x in shares["f32"]]
+        rl[kind] = alu_roofline(fpe, pairs, ms, "f32",
+                                "k_gather<float,Voigt>" if kind == "fwd" else "k_adjoint<float,Voigt>", **extra)
+        rl[kind]["frac_of_published_157"] = round(rl[kind]["achieved"] / 157.3, 4)
+    dom = "adj" if per32["adjoint"] >= per32["forward"] else "fwd"
+    other = "fwd" if dom == "adj" else "adj"
 
     extras = {}
     if not args.no_extras:
         p64 = plan_for(X.XS_FP64)
         p64.set_config(**cfg)
-        ms64, per64, _ = time_steps(p64, ds, dl, sig, w, target, max(2, args.steps // 2), 1)
+        ms64, per64, dist64 = time_steps(p64, ds, dl, sig, w, target, max(3, args.steps // 2), 2)
         log(f"fp64 step {ms64:.2f} ms {per64}")
+        rl64 = {}
+        for kind, ms in (("fwd", per64["forward"]), ("adj", per64["adjoint"])):
+            fpe = flops_per_eval(fracs, (kind, "f64"), shares["f64"])
+            rl64[kind] = alu_roofline(fpe, pairs, ms, "f64",
+                                      "k_gather<double,Voigt>" if kind == "fwd" else "k_adjoint<double,Voigt>",
+                                      traffic=traffic_from_profiles("gather_c2_f64" if kind == "fwd"
+                                                                    else "adjoint_c2_f64"),
+                                      region_fractions=[round(f, 5) for f in fracs[(kind, "f64")]])
         extras["fp64"] = {"ms_per_step": round(ms64, 3), "stage_ms": {k: round(v, 3) for k, v in per64.items()},
-                          "evals_per_s": 2 * pairs / (ms64 / 1e3)}
+                          "step_ms_device": dist64, "evals_per_s": 2 * pairs / (ms64 / 1e3),
+                          "roofline_gather": rl64["fwd"], "roofline_adjoint": rl64["adj"],
+                          "prepare_hbm": hbm_roofline(100, lines.n, per64["prepare"], copy["GB_per_s"])}
         extras["fp32_over_fp64_speedup"] = {"step": round(ms64 / ms32, 3),
                                             "profile_pass": round(per64["forward"] / per32["forward"], 3),
                                             "adjoint": round(per64["adjoint"] / per32["adjoint"], 3)}
@@ -713,30 +835,12 @@ def main():
         extras["pseudo_voigt"] = pseudo_voigt(X, wl, ds, dl, lines.n, cfg, per32["forward"])
         extras["lifetime_voigt"] = lifetime_voigt(X, wl, ds, dl, lines.n, cfg, per32["forward"])
         extras["cooling_function"] = cooling_function(X, wl, ds, dl, lines)
-        extras["batched_48"] = batched_48(X, wl, ds, dl, lines.n)
-        extras["stream_2t"] = stream_2t(X)
-        extras["density_2t"] = density_2t(X)
-        extras["binned_doppler_2t"] = binned_doppler_2t(X)
-
-    # roofline of the dominant kernel (events around each launch, same stream)
-    fracs = region_fractions(wl, lines, cond)
-    shares = adj_block_shares(wl, lines, cond)
-    rl = {}
-    for kind, ms in (("fwd", per32["forward"]), ("adj", per32["adjoint"])):
-        fpe = flops_per_eval(fracs, (kind, "f32"), shares)
-        flops = fpe * pairs
-        ach = flops / (ms / 1e3) / 1e12
-        key = "gather_c2_f32" if kind == "fwd" else "adjoint_c2_f32"
-        rl[kind] = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
-                    "frac": round(ach / PEAK_TFLOPS["f32"], 4), "traffic": traffic_from_profiles(key),
-                    "kernel": "k_gather<float,Voigt>" if kind == "fwd" else "k_adjoint<float,Voigt>",
-                    "avg_launch_ms": round(ms, 3), "flops_per_eval": round(fpe, 3),
-                    "region_fractions": [round(f, 5) for f in fracs[(kind, "f32")]],
-                    "evals_per_launch": pairs}
-        if kind == "adj":
-            rl[kind]["block_summed_wave_share"] = [round(x, 4) for x in shares]
-    dom = "adj" if per32["adjoint"] >= per32["forward"] else "fwd"
-    other = "fwd" if dom == "adj" else "adj"
+    p32.close()
+    del ds, dl, w, sig, target
+    torch.cuda.empty_cache()
+    if not args.no_full:
+        extras["batched_48_full"] = batched_48_full(X, copy["GB_per_s"])
+        extras["stream_2t_full"] = stream_2t_full(X, copy["GB_per_s"])
 
     evals_step = 2 * pairs
     value = evals_step / (ms32 / 1e3)
@@ -761,17 +865,16 @@ def main():
         "stage_ms": {k: round(v, 3) for k, v in per32.items()},
         "step_ms_device": dist32,
         "device_state": dev_state,
+        "device_copy": copy,
         "forward_evals_per_s": pairs / (per32["forward"] / 1e3),
         "lines_per_s": lines.n / (ms32 / 1e3),
         "adj_over_fwd": round(per32["adjoint"] / per32["forward"], 3),
         # intensity pass and bucketing (HBM-bound): algorithmic bytes per line =
         # reads u, l, A, gamma_ref, n_exp (20) + key write (4) + two radix
         # passes (2 x 16) + sorted records written (nu 8, gamma_ref 4, n_exp 4,
-        # index 4, home bin 4, offset 4, window 8, S~ 4 = 40) = 96 B
-        "prepare_hbm": {"bound": "hbm", "bytes_per_line": 96,
-                        "achieved": round(96 * lines.n / (per32["prepare"] / 1e3) / 1e9, 1),
-                        "peak": 8000.0, "unit": "GB/s",
-                        "frac": round(96 * lines.n / (per32["prepare"] / 1e3) / 8e12, 4)},
+        # index 4, home bin 4, offset 4, window 8, S~ 4 = 40) = 96 B; the
+        # FP64 form writes S in 8 bytes: 100 B
+        "prepare_hbm": hbm_roofline(96, lines.n, per32["prepare"], copy["GB_per_s"]),
         "roofline": rl[dom],
         "roofline_other": rl[other],
         **extras,

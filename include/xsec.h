@@ -260,10 +260,11 @@ int xs_cross_section(xs_plan* plan, const xs_states* states, const xs_lines* lin
  * The profile windows are recomputed; no (line, bin) pairs are stored.
  * dL_dgamma_ref and dL_dn_exp may be NULL.  With per-line gamma_ref/n_exp NULL
  * (scalars), their gradients are still returned per line.  The FP32 form sums
- * window blocks of g/d and g/d^2 terms in FP32 (d >= 64^2 in the far wing), so
- * it keeps its accuracy for cotangents |dL_dsigma| above about 1e-26 (below,
- * terms leave the FP32 normal range: scale the loss); the FP64 form has no
- * such limit. */
+ * window blocks in FP32 with the cotangent of each condition scaled by the
+ * power of two that brings its largest magnitude into [1/2, 1), and removes
+ * the scale exactly in FP64, so its accuracy does not depend on the loss's
+ * magnitude (cotangents of 1e-30 and 1e+10 behave alike); a non-finite
+ * cotangent propagates into the results unscaled. */
 int xs_cross_section_adjoint(xs_plan* plan, const xs_states* states, const xs_lines* lines,
                              const double* dL_dsigma, double* dL_dT, double* dL_dP,
                              double* dL_dgamma_ref, double* dL_dn_exp, double* dL_dlog_scale);

@@ -36,9 +36,18 @@ ABSORPTION, EMISSION = 0, 1
 LTE, NLTE_2T, NLTE_DENSITY = 0, 1, 2
 
 
+def _stale() -> bool:
+    return not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (it is test infrastructure, built in-tree)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile the oracle with gcc (it is test infrastructure, built in-tree).
+
+    This starts a child process, so callers run it before their process
+    touches the GPU (the test session's configure hook, the start of
+    ``bench.py`` and ``smoke()``): a process that has initialised the GPU must
+    not start other programs."""
+    if force or _stale():
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", *_CFLAGS, "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
@@ -49,9 +58,14 @@ _lib = None
 
 
 def lib():
+    """Load the built oracle.  Never compiles: a missing or stale library
+    raises (build it with ``build()`` before any GPU work)."""
     global _lib
     if _lib is None:
-        L = C.CDLL(build())
+        if _stale():
+            raise RuntimeError(f"{_LIB} is missing or older than {_SRC}: call oracle.build() "
+                               "before the process uses the GPU")
+        L = C.CDLL(_LIB)
         d, i64, i32, p = C.c_double, C.c_int64, C.c_int, C.c_void_p
         L.or_c2.restype = d
         L.or_max_threads.restype = i32
@@ -74,6 +88,7 @@ def lib():
         L.or_window_counts.restype = i64
         L.or_sigma.argtypes = [i64, p, p, p, p, i32, d, d, i64, d, i64, p, p]
         L.or_adjoint_sums.argtypes = [i64, p, p, p, i32, d, d, i64, d, p, p, p, p]
+        L.or_adjoint_abs_sums.argtypes = [i64, p, p, p, i32, d, d, i64, d, p, p, p, p]
         _lib = L
     return _lib
 
@@ -244,15 +259,18 @@ def sigma(nu, S, alpha, gamma, prof: int, grid, cut: float,
     return out
 
 
-def adjoint_sums(nu, alpha, gamma, prof: int, grid, cut: float, g: np.ndarray):
+def adjoint_sums(nu, alpha, gamma, prof: int, grid, cut: float, g: np.ndarray, absolute: bool = False):
+    """Per-line window sums (A, B, C) of g against f, df/dsg and df/dgamma;
+    with ``absolute`` the sums of the terms' absolute values."""
     nu = _c(nu, np.float64)
     alpha = _c(alpha, np.float64)
     gamma = _c(gamma, np.float64)
     g = _c(g, np.float64)
     n = nu.shape[0]
     A, B, Cc = np.empty(n), np.empty(n), np.empty(n)
-    lib().or_adjoint_sums(n, _p(nu), _p(alpha), _p(gamma), prof, grid.nu0, grid.dnu,
-                          grid.n_bins, cut, _p(g), _p(A), _p(B), _p(Cc))
+    f = lib().or_adjoint_abs_sums if absolute else lib().or_adjoint_sums
+    f(n, _p(nu), _p(alpha), _p(gamma), prof, grid.nu0, grid.dnu, grid.n_bins, cut, _p(g),
+      _p(A), _p(B), _p(Cc))
     return A, B, Cc
 
 
@@ -330,3 +348,26 @@ def adjoint(wl, lines, cond, g: np.ndarray, log_scale: Optional[np.ndarray] = No
     dT = math.fsum(dT_terms)
     return dict(dT=dT, dP=dP, d_log_scale=d_s, d_gamma_ref=d_gref, d_n_exp=d_n,
                 A=A, B=B, C=Cs, S=S, nu=r.nu, alpha=r.alpha, gamma=r.gamma, Q=r.Q, dQdT=r.dQdT)
+
+
+def adjoint_bounds(wl, lines, cond, g: np.ndarray, log_scale: Optional[np.ndarray] = None):
+    """Per-line scales of the adjoint's per-line gradients: each gradient of
+    ``adjoint`` with its window sum replaced by the sum of the terms' absolute
+    values (``adjoint_sums(..., absolute=True)``) and every factor by its
+    absolute value.  |gradient_i| <= bound_i, and a relative error e in every
+    term of a window sum moves gradient_i by at most e bound_i: the error of a
+    per-line gradient is measured against this scale, since the signed sums
+    can cancel to any degree."""
+    if wl.population != LTE or wl.profile >= BIN_DOPPLER:
+        raise ValueError("oracle adjoint bounds: LTE, sampled profiles only")
+    T, P = cond.T, cond.P
+    r = run_condition(wl, lines, cond, log_scale=log_scale, with_sigma=False)
+    A, _, Cs = adjoint_sums(r.nu, r.alpha, r.gamma, wl.profile, wl.grid, cond.cutoff, g, absolute=True)
+    gref = (np.full(lines.n, lines.gamma_ref_scalar) if lines.gamma_ref is None
+            else lines.gamma_ref.astype(np.float64))
+    nexp = (np.full(lines.n, lines.n_exp_scalar) if lines.n_exp is None
+            else lines.n_exp.astype(np.float64))
+    S = np.abs(r.S)
+    scale = (wl.T_ref / T) ** nexp * (P / wl.P_ref)
+    return dict(d_log_scale=S * A, d_gamma_ref=S * Cs * scale,
+                d_n_exp=S * Cs * np.abs(gref) * scale * abs(np.log(wl.T_ref / T)))

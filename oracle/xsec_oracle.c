@@ -678,3 +678,36 @@ int or_adjoint_sums(int64_t nl, const double* nu, const double* alpha, const dou
   }
   return 0;
 }
+
+/* The same window sums with every term taken in absolute value,
+ *   A'_i = sum_k |g_k f_ik|,  B'_i = sum_k |g_k df/dsg|,  C'_i = sum_k |g_k df/dgamma|.
+ * They bound what rounding in the terms can do to the signed sums above: a
+ * relative error e in every term moves A_i by at most e A'_i (likewise B, C),
+ * so |A_i| <= A'_i and A'_i / |A_i| is the condition number of the sum.  The
+ * tests use them for the per-element error of the adjoint's per-line
+ * gradients, whose signed sums (cotangents of either sign, derivatives that
+ * change sign across a profile) can cancel to any degree. */
+int or_adjoint_abs_sums(int64_t nl, const double* nu, const double* alpha, const double* gamma,
+                        int profile, double nu0, double dnu, int64_t n_bins, double cut,
+                        const double* g, double* A, double* B, double* C) {
+  or_mr_init();
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t i = 0; i < nl; ++i) {
+    or_sum a = {0, 0}, b = {0, 0}, c = {0, 0};
+    int64_t klo, khi;
+    if (nu[i] > 0.0 && or_window(nu[i], cut, nu0, dnu, n_bins, &klo, &khi)) {
+      for (int64_t k = klo; k <= khi; ++k) {
+        double nuk = or_nu_k(nu0, dnu, k);
+        double f, dsg, dgam;
+        or_profile_grad(profile, nuk - nu[i], alpha[i], gamma[i], &f, &dsg, &dgam);
+        or_add(&a, fabs(g[k] * f));
+        or_add(&b, fabs(g[k] * dsg));
+        or_add(&c, fabs(g[k] * dgam));
+      }
+    }
+    A[i] = or_total(&a);
+    B[i] = or_total(&b);
+    C[i] = or_total(&c);
+  }
+  return 0;
+}

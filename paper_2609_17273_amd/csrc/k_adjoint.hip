@@ -121,6 +121,7 @@ struct AdjArgs {
   StatesView st;
   LinesView ln;
   const double* g;
+  const unsigned long long* gmax;  // [n_cond] bits of max_k |g_k| per condition
   double* dgref;
   double* dnexp;
   double* dls;
@@ -283,6 +284,7 @@ constexpr int kFlush = 256;
 template <typename R>
 struct GSrc {
   const double* gc;  // g of this condition
+  double gs;         // power-of-two scale applied to g (FP32 form: max |g gs| in [1/2, 1))
   int64_t nb;        // grid points
   int kcmin;         // smallest home bin of the wave's active lanes
   bool lds;
@@ -413,7 +415,7 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
       const int64_t kb = (int64_t)G.kcmin + rb;
       for (int t = rank; t < 2 * kFlush; t += nact) {
         const int64_t k = kb + t;
-        G.buf[t] = (k >= 0 && k < G.nb) ? (R)G.gc[k] : (R)0;
+        G.buf[t] = (k >= 0 && k < G.nb) ? (R)(G.gc[k] * G.gs) : (R)0;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -422,7 +424,8 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
       run([&](int j) { return gl[j]; });
     } else {
       const double* gp = G.gc + (L.kc + rb);
-      run([&](int j) { return (R)gp[j]; });
+      if constexpr (sizeof(R) == 4) run([&](int j) { return (R)(gp[j] * G.gs); });
+      else run([&](int j) { return (R)gp[j]; });
     }
     // to the general-path convention
     if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
@@ -501,7 +504,8 @@ struct Sums3 {
 
 template <typename R, int PROF>
 __device__ __forceinline__ Sums3 window_sums(bool on, int64_t klo, int64_t khi, double nu, double inv, double y,
-                                             const double* gc, double nu0, double dnu, int64_t nbins, R* gbuf) {
+                                             const double* gc, double gs, double nu0, double dnu, int64_t nbins,
+                                             R* gbuf) {
   const int64_t kc64 = home_bin(nu, nu0, dnu);
   const double delta = nu - nu_of_bin(nu0, dnu, kc64);
   AdjLine<R> L;
@@ -549,6 +553,7 @@ __device__ __forceinline__ Sums3 window_sums(bool on, int64_t klo, int64_t khi, 
   double sA = 0.0, sB = 0.0, sC = 0.0;
   GSrc<R> G;
   G.gc = gc;
+  G.gs = gs;
   G.nb = nbins;
   G.kcmin = wave_min(on ? L.kc : 0x7fffffff);
   G.lds = (int64_t)wave_max(on ? L.kc : -0x7fffffff) - G.kcmin <= kFlush;
@@ -611,7 +616,7 @@ __device__ __forceinline__ Sums3 window_sums(bool on, int64_t klo, int64_t khi, 
       } else if (mode == -1) {
         for (int rr = r; rr <= end; ++rr) {
           if (rr >= L.rlo && rr <= L.rhi) {
-            const double gk = gc[L.kc + rr];
+            const double gk = gc[L.kc + rr] * gs;
             general_eval<R, PROF>(L, wide, rr, gk, sA, sB, sC);
           }
         }
@@ -682,9 +687,25 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 4 : 3) void k_adjoint(AdjArgs
         inv = sqrt(kLN2) / alpha;
         y = gtot * inv;
       }
-      const Sums3 ws = window_sums<R, PROF>(on, klo, khi, nu, inv, y, a.g + (int64_t)c * m.n_bins, m.nu0, m.dnu,
-                                            m.n_bins, s_g[wave]);
-      const double sA = ws.A, sB = ws.B, sC = ws.C;
+      // FP32 form: the cotangent enters the window sums scaled by a power of
+      // two, gs, that brings its largest magnitude over the condition's grid
+      // into [1/2, 1), so the FP32 block sums of g/d and g/d^2 terms stay in
+      // the normal range whatever the loss's magnitude; the sums are
+      // unscaled exactly in FP64.  (FP64: gs = 1.)
+      double gs = 1.0, igs = 1.0;
+      if (sizeof(R) == 4) {
+        const double gm = __longlong_as_double((long long)a.gmax[c]);
+        if (gm > 0.0 && gm <= 1.7976931348623157e308) {
+          int e;
+          (void)frexp(gm, &e);
+          e = max(e, -1000);
+          gs = ldexp(1.0, -e);
+          igs = ldexp(1.0, e);
+        }
+      }
+      const Sums3 ws = window_sums<R, PROF>(on, klo, khi, nu, inv, y, a.g + (int64_t)c * m.n_bins, gs, m.nu0,
+                                            m.dnu, m.n_bins, s_g[wave]);
+      const double sA = ws.A * igs, sB = ws.B * igs, sC = ws.C * igs;
       // scale to the unit-area profile and its derivatives
       double A, B, C;
       if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
@@ -757,19 +778,44 @@ __global__ __launch_bounds__(256) void k_adj_final(const double* part, int n_con
   }
 }
 
-__global__ void k_zero3(double* a, double* b, double* c, int64_t n) {
+__global__ void k_zero3(double* a, double* b, double* c, int64_t n, unsigned long long* gmax, int n_cond) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     if (a) a[i] = 0.0;
     if (b) b[i] = 0.0;
     if (c) c[i] = 0.0;
   }
+  if (blockIdx.x == 0)
+    for (int q = threadIdx.x; q < n_cond; q += blockDim.x) gmax[q] = 0ull;
+}
+
+// Largest |g_k| of each condition's cotangent (FP32 form's scale).  The bit
+// patterns of non-negative doubles order like the values (a NaN above
+// infinity), so an unsigned integer max finds it.
+__global__ __launch_bounds__(256) void k_gmax(const double* g, int64_t n_bins, unsigned long long* gmax) {
+  const int c = blockIdx.y;
+  const double* gc = g + (int64_t)c * n_bins;
+  unsigned long long v = 0ull;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n_bins; k += (int64_t)gridDim.x * 256) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(gc[k]));
+    v = b > v ? b : v;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long w = (unsigned long long)__shfl_xor((long long)v, o, 64);
+    v = w > v ? w : v;
+  }
+  if ((threadIdx.x & 63) == 0 && v) atomicMax(gmax + c, v);
 }
 
 void launch_adjoint(const ModelDev& m, const Work& w, const StatesView& st, const LinesView& ln,
                     const double* g, double* dT, double* dP, double* dgref, double* dnexp,
                     double* dls, int64_t n_lines, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero3, dim3(2048), dim3(256), 0, s, dgref, dnexp, dls, n_lines);
+  hipLaunchKernelGGL(k_zero3, dim3(2048), dim3(256), 0, s, dgref, dnexp, dls, n_lines, w.gmax, m.n_cond);
+  if (m.prec == XS_FP32) {
+    const int64_t gb = std::min<int64_t>((m.n_bins + 1023) / 1024, 512);
+    hipLaunchKernelGGL(k_gmax, dim3((unsigned)gb, m.n_cond), dim3(256), 0, s, g, m.n_bins, w.gmax);
+  }
   AdjArgs a;
   a.m = m;
   a.cond = w.cond;
@@ -787,6 +833,7 @@ void launch_adjoint(const ModelDev& m, const Work& w, const StatesView& st, cons
   a.st = st;
   a.ln = ln;
   a.g = g;
+  a.gmax = w.gmax;
   a.dgref = dgref;
   a.dnexp = dnexp;
   a.dls = dls;

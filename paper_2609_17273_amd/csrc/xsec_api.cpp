@@ -344,6 +344,7 @@ size_t layout(xs_plan* p, char* base, Work* w) {
   }
   x.stats = (unsigned long long*)take(8 * 8);
   x.adjpart = (double*)take(sizeof(double) * d.n_cond * 2 * kAdjBlocks);
+  x.gmax = (unsigned long long*)take(sizeof(unsigned long long) * d.n_cond);
   x.cut_class = (double*)take(sizeof(double) * d.n_cut_classes);
   x.cut_mult = (int32_t*)take(sizeof(int32_t) * d.n_cut_classes);
   x.max_lines = L;

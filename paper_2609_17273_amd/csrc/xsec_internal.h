@@ -131,6 +131,7 @@ struct Work {
   int64_t item_target;      // work items aimed at when tiles are split
   unsigned long long* stats;// [8]
   double* adjpart;          // [n_cond][2][kAdjBlocks]
+  unsigned long long* gmax; // [n_cond] max |dL/dsigma| per condition (bits; FP32 adjoint's scale)
   double* cut_class;        // [n_cut_classes] distinct cut-offs
   int32_t* cut_mult;        // [n_cut_classes] conditions sharing each cut-off
   int64_t max_lines;

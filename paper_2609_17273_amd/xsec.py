@@ -520,6 +520,10 @@ class ChunkStreamer:
         self.pool.shutdown(wait=True)
 
 
+def _cond_tuple(conds) -> tuple:
+    return tuple((c.T, c.P, c.T_vib, c.T_rot, c.cutoff) for c in conds)
+
+
 def _make_xsec_function():
     import torch
 
@@ -537,11 +541,16 @@ def _make_xsec_function():
             ln = DeviceLines(lines.upper, lines.lower, lines.einstein_a, gamma_ref.detach().contiguous(),
                              n_exp.detach().contiguous(), log_scale.detach().contiguous())
             sigma = plan.cross_section(states, ln)
-            ctx.plan, ctx.states, ctx.ln = plan, states, ln
+            # the conditions of this forward: another apply on the same plan
+            # before backward replaces the plan's, and the adjoint must run at
+            # these
+            ctx.plan, ctx.states, ctx.ln, ctx.conds = plan, states, ln, conds
             return sigma
 
         @staticmethod
         def backward(ctx, g):
+            if _cond_tuple(ctx.plan.conds) != _cond_tuple(conditions_of(ctx.conds)):
+                ctx.plan.set_conditions(ctx.conds)
             r = ctx.plan.adjoint(ctx.states, ctx.ln, g.to(torch.float64))
             return (r["dT"], r["dP"], r["d_gamma_ref"].to(torch.float32), r["d_n_exp"].to(torch.float32),
                     r["d_log_scale"].to(torch.float32), None, None, None, None)

@@ -34,7 +34,7 @@ def test_header_declares_the_binding_names():
     assert names == sorted(X.SIGNATURES), (set(names) ^ set(X.SIGNATURES))
 
 
-def test_library_exports_every_declared_symbol():
+def test_library_exports_every_declared_symbol(no_gpu_in_process):
     X = _binding()
     lib = C.CDLL(X.LIB_PATH)
     missing = [n for n in _declared_functions() if not hasattr(lib, n)]
@@ -60,7 +60,7 @@ _STRUCTS = {
 }
 
 
-def test_struct_layout_matches_header(tmp_path):
+def test_struct_layout_matches_header(tmp_path, no_gpu_in_process):
     X = _binding()
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for s, fields in _STRUCTS.items():

@@ -14,7 +14,7 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-def test_more_than_one_gpu_is_refused():
+def test_more_than_one_gpu_is_refused(no_gpu_in_process):
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120, cwd=ROOT)
     assert r.returncode != 0

@@ -4,9 +4,11 @@ cache): 1e7 lines, 1e6 states, LTE Voigt absorption at T = 2000 K, P = 1 bar,
 grid 0-20000 cm^-1 step 0.01 (2,000,001 points), cut-off 25 cm^-1.
 
 * sigma (FP32 and FP64 forms) at sampled grid points, which the oracle
-  computes one by one over all 1e7 lines, plus the peak point;
+  computes one by one over all 1e7 lines: uniform draws and the points
+  around the strongest lines by the oracle's intensities;
 * per-line adjoint gradients (d/dlog_scale, d/dgamma_ref, d/dn_exp) of
-  sampled lines against the oracle's, for the same cotangent;
+  sampled lines against the oracle's, for the same cotangent: in norm and
+  per element (xs_helpers.check_line_gradients);
 * dL/dT and dL/dP of the FP32 and FP64 adjoints against central differences
   of the FP64 forward on the GPU (a property that holds at any size).
 """
@@ -18,7 +20,7 @@ import pytest
 
 import oracle
 import synth
-from xs_helpers import X, gpu_inputs, log, make_plan, rel_err
+from xs_helpers import X, check_line_gradients, gpu_inputs, log, make_plan, rel_err
 
 pytestmark = pytest.mark.gpu
 FP64, FP32 = 0, 1
@@ -47,11 +49,17 @@ def test_sigma_sampled_points_full_size(full):
     s64 = p64.cross_section(ds, dl)[0].cpu().numpy()
     p64.close()
     # sigma spans many decades, so only ~15% of uniformly drawn points are
-    # above 1e-6 of the peak: draw enough of them
+    # above 1e-6 of the peak: draw enough of them, and add the points around
+    # the 100 strongest lines by the oracle's own intensities
+    cond = wl.conditions[0]
     bins = synth.sample_bins(wl.grid.n_bins, 20000, 77)
-    bins = np.unique(np.concatenate([bins, [int(np.argmax(s64))]]))
-    ref = oracle.run_condition(wl, ln, wl.conditions[0], bins=bins).sigma
-    peak = max(float(ref.max()), float(s64.max()))
+    r0 = oracle.run_condition(wl, ln, cond, with_sigma=False)
+    top = np.argpartition(r0.S, -100)[-100:]
+    kc = np.rint((r0.nu[top] - wl.grid.nu0) / wl.grid.dnu).astype(np.int64)
+    near = (kc[:, None] + np.array([-3, -1, 0, 1, 3])[None, :]).ravel()
+    bins = np.unique(np.concatenate([bins, near[(near >= 0) & (near < wl.grid.n_bins)]]))
+    ref = oracle.run_condition(wl, ln, cond, bins=bins).sigma
+    peak = float(ref.max())
     for name, got, tol in (("fp64", s64, 1e-10), ("fp32", s32, 1e-4)):
         e, l1, n = rel_err(got[bins], ref, peak=peak)
         log(f"[full] sigma {name}: max_rel={e:.2e} L1={l1:.2e} over {n} sampled points (peak {peak:.3e})")
@@ -65,7 +73,9 @@ def test_adjoint_sampled_lines_full_size(full):
     g = wl.cotangent()
     rng = np.random.default_rng(5)
     idx = np.sort(rng.choice(ln.n, 400, replace=False))
-    ref = oracle.adjoint(wl, ln.take(idx), wl.conditions[0], g[0])
+    sub = ln.take(idx)
+    ref = oracle.adjoint(wl, sub, wl.conditions[0], g[0])
+    bnd = oracle.adjoint_bounds(wl, sub, wl.conditions[0], g[0])
     p64 = make_plan(wl, FP64, ln.n)
     p64.set_config(**cfg)
     for name, plan, tol in (("fp64", p64, 1e-9), ("fp32", p32, 1e-4)):
@@ -73,9 +83,7 @@ def test_adjoint_sampled_lines_full_size(full):
         torch.cuda.synchronize()
         for k in ("d_log_scale", "d_gamma_ref", "d_n_exp"):
             got = r[k].cpu().numpy()[idx]
-            e = float(np.linalg.norm(got - ref[k]) / np.linalg.norm(ref[k]))
-            log(f"[full] adjoint {name} {k}: ||diff||/||ref|| = {e:.2e} over {len(idx)} sampled lines")
-            assert e <= tol
+            check_line_gradients(f"full size {name} {k} ({len(idx)} sampled lines)", got, ref[k], bnd[k], tol)
     p64.close()
 
 

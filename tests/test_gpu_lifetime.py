@@ -5,7 +5,8 @@ A third of the states of a reduced benchmark list get lifetimes
 the pressure widths), the rest are stable.  sigma (sampled and binned Voigt,
 Lorentzian; gather and scatter; FP64 1e-10 and FP32 1e-4 on bins >= 1e-6 of
 the peak) and the adjoint (per-line gradients and dL/dT, dL/dP against the
-oracle's analytic gradient: FP64 1e-9 / 1e-8, FP32 1e-4 / 1e-3) with the
+oracle's analytic gradient: FP64 1e-9 / 1e-8, FP32 1e-4 / 1e-3, per-line
+vectors in norm and per element) with the
 lifetime width entering the profile and the chain rule acting on the
 pressure width only.
 """
@@ -14,7 +15,7 @@ import pytest
 
 import oracle
 import synth
-from xs_helpers import gpu_inputs, gpu_sigma, log, make_plan, rel_err
+from xs_helpers import check_line_gradients, gpu_inputs, gpu_sigma, log, make_plan, rel_err
 
 pytestmark = pytest.mark.gpu
 FP64, FP32 = 0, 1
@@ -58,16 +59,18 @@ def test_lifetime_adjoint(prof, prec):
     torch.cuda.synchronize()
     got = {k: v.cpu().numpy() for k, v in r.items()}
     ref = {"d_log_scale": 0.0, "d_gamma_ref": 0.0, "d_n_exp": 0.0}
+    bnd = dict(ref)
     for c, cond in enumerate(wl.conditions):
         o = oracle.adjoint(wl, ln, cond, g[c])
+        b = oracle.adjoint_bounds(wl, ln, cond, g[c])
         for k in ref:
             ref[k] = ref[k] + o[k]
+            bnd[k] = bnd[k] + b[k]
         for name in ("dT", "dP"):
             gv, ov = float(got[name][c]), o[name]
             log(f"[lifetime adj] prof={prof} prec={prec} c{c} {name}: gpu={gv:.10e} oracle={ov:.10e}")
             assert gv == pytest.approx(ov, rel=1e-8 if prec == FP64 else 1e-3, abs=0)
     for k in ref:
-        e = float(np.linalg.norm(got[k] - ref[k]) / np.linalg.norm(ref[k]))
-        log(f"[lifetime adj] prof={prof} prec={prec} {k}: {e:.2e}")
-        assert e <= (1e-9 if prec == FP64 else 1e-4)
+        check_line_gradients(f"lifetime prof={prof} prec={prec} {k}", got[k], ref[k], bnd[k],
+                             1e-9 if prec == FP64 else 1e-4)
     plan.close()

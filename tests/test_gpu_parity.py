@@ -142,3 +142,60 @@ def test_window_pair_count_matches_oracle():
     log(f"[pairs] gpu={st['window_pairs']} oracle={tot} kept={st['lines_kept']}")
     assert st["window_pairs"] == tot
     assert st["lines_kept"] == int(np.sum(counts > 0))
+
+
+@pytest.mark.parametrize("algo", [0, 1])
+def test_config1_full_size_every_point(algo):
+    """The small FP64 workload at its stated size: 2,000 states, 1e4 lines,
+    LTE absorption at T = 1000 K, mass 18, Doppler profile, grid 0-10000
+    cm^-1 step 0.01 (1,000,001 points), cut-off 25 cm^-1; the oracle at every
+    point; FP64 (the workload's form) and FP32."""
+    wl = synth.config(1)
+    ln = wl.lines()
+    assert ln.n == 10_000 and wl.grid.n_bins == 1_000_001
+    ref = oracle.run_condition(wl, ln, wl.conditions[0]).sigma
+    for prec in (FP64, FP32):
+        got, st, _ = gpu_sigma(wl, ln, prec, algo=algo)
+        _check_sigma(f"config1 full algo={algo}", got[0], ref, prec, st)
+        assert st["lines_in"] == 10_000
+
+
+def _tie_workload(profile):
+    """Lines whose wavenumbers lie exactly the cut-off away from points of an
+    exactly representable grid (0, 0.25, ..., 25; cut-off 2): nu = 10 (points
+    8 and 12 are at exactly the cut-off), nu = 26.75 (beyond the grid end,
+    its wing reaching 24.75 and 25), and lines with nu < 0 and nu = 0
+    (discarded)."""
+    states = synth.States(np.array([0.0, 10.0, 26.75, 3.0, 1.5]), np.array([1.0, 3.0, 5.0, 3.0, 1.0]))
+    lines = synth.Lines(np.array([1, 2, 0, 4, 3], np.int32), np.array([0, 0, 1, 3, 3], np.int32),
+                        np.array([1.0, 2.0, 1.0, 1.0, 1.0], np.float32),
+                        np.full(5, 0.3, np.float32), np.full(5, 0.5, np.float32))
+    wl = synth.config(2, n_states=5, n_lines=5, nu_hi=25.0, profile=profile)
+    wl.states = states
+    wl.grid = synth.Grid(0.0, 0.25, 101)
+    wl.conditions = [synth.Condition(1000.0, 1.0, 2.0)]
+    wl.hwhm_fixed = 0.5
+    return wl, lines
+
+
+@pytest.mark.parametrize("profile", [synth.GAUSSIAN, synth.LORENTZ, synth.VOIGT, synth.BIN_LORENTZ])
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("algo", [0, 1])
+def test_cutoff_tie_is_inclusive(profile, prec, algo):
+    """The cut-off rule |nu_k - nu_i| <= cut is inclusive (section "Spectral
+    synthesis"): points exactly the cut-off away receive the line, the next
+    ones do not; lines beyond the grid end reach it with their wings; lines
+    with nu <= 0 are discarded.  The oracle pins the same case on its own."""
+    wl, ln = _tie_workload(profile)
+    ref = oracle.run_condition(wl, ln, wl.conditions[0]).sigma
+    got, st, _ = gpu_sigma(wl, ln, prec, algo=algo)
+    got = got[0]
+    nuk = np.arange(wl.grid.n_bins) * 0.25
+    k8, k12, k775, k1225 = (int(np.searchsorted(nuk, v)) for v in (8.0, 12.0, 7.75, 12.25))
+    assert ref[k8] > 0 and ref[k12] > 0 and ref[k775] == 0 and ref[k1225] == 0
+    assert got[k8] > 0 and got[k12] > 0, (got[k8], got[k12])
+    assert got[k775] == 0 and got[k1225] == 0
+    assert got[int(np.searchsorted(nuk, 24.75))] > 0 and got[-1] > 0
+    np.testing.assert_array_equal(got == 0.0, ref == 0.0)
+    _check_sigma(f"cut-off tie prof={profile} algo={algo}", got, ref, prec, st)
+    assert st["lines_kept"] == 2 and st["window_pairs"] == 17 + 2

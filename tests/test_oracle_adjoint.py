@@ -110,3 +110,38 @@ def test_adjoint_log_scale_dot_product(orc, prof):
     fp = orc.run_condition(wl, ln, cond, log_scale=sp).sigma
     fm = orc.run_condition(wl, ln, cond, log_scale=sm).sigma
     assert math.fsum((fp - fm) * u) / (2 * h) == pytest.approx(adj["d_log_scale"][i], rel=1e-6, abs=0)
+
+
+@pytest.mark.parametrize("prof", [0, 2, 3])
+def test_adjoint_bounds(orc, prof):
+    """The per-line error scales (window sums of the terms' absolute values):
+    with a positive cotangent the log-scale gradient's terms share one sign,
+    so its scale equals the gradient; with a signed cotangent every scale
+    bounds its gradient; the gamma sums agree with a brute-force sum over
+    the window of |g| |df/dgamma| from central differences of the oracle's
+    profile (a different computation)."""
+    wl, ln = _wl(prof)
+    cond = wl.conditions[0]
+    rng = np.random.default_rng(7)
+    g = rng.standard_normal(wl.grid.n_bins)
+    pos = orc.adjoint(wl, ln, cond, np.abs(g))
+    bpos = orc.adjoint_bounds(wl, ln, cond, np.abs(g))
+    np.testing.assert_allclose(bpos["d_log_scale"], np.abs(pos["d_log_scale"]), rtol=1e-13, atol=0)
+    ref = orc.adjoint(wl, ln, cond, g)
+    b = orc.adjoint_bounds(wl, ln, cond, g)
+    for k in ("d_log_scale", "d_gamma_ref", "d_n_exp"):
+        assert np.all(b[k] >= np.abs(ref[k]) * (1 - 1e-12)), k
+        assert np.all(b[k] <= bpos[k] * (1 + 1e-12)), k  # |g| is the same in both
+    r = orc.run_condition(wl, ln, cond, with_sigma=False)
+    _, _, Cabs = orc.adjoint_sums(r.nu, r.alpha, r.gamma, prof, wl.grid, cond.cutoff, g, absolute=True)
+    if prof == 0:
+        assert np.all(Cabs == 0.0)  # the Doppler profile has no Lorentzian width
+        return
+    nuk = wl.grid.nu0 + np.arange(wl.grid.n_bins) * wl.grid.dnu
+    for i in np.flatnonzero(r.nu > 0)[:8]:
+        m = np.abs(nuk - r.nu[i]) <= cond.cutoff
+        h = 1e-6 * r.gamma[i]
+        dfg = np.array([(orc.profile(prof, d, r.alpha[i], r.gamma[i] + h)
+                         - orc.profile(prof, d, r.alpha[i], r.gamma[i] - h)) / (2 * h) for d in nuk[m] - r.nu[i]])
+        brute = math.fsum(np.abs(g[m]) * np.abs(dfg))
+        assert Cabs[i] == pytest.approx(brute, rel=1e-6, abs=0), i
