@@ -303,6 +303,27 @@ int xs_profile_adjoint(xs_plan* plan, const xs_states* states, const xs_lines* l
 int xs_cooling_function(xs_plan* plan, const xs_states* states, const xs_lines* lines,
                         int32_t n_T, const double* T, double* W, double* Q);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * xs_cross_section path with the same arguments and sigma contract, run with
+ * its workspace carved from a static scratch array of 64 MiB that the library
+ * holds on each GPU it runs on until the process ends, instead of the plan's
+ * bound workspace (which need not exist, and is left untouched with the
+ * records of its last xs_prepare).  Nothing is allocated: no hipMalloc,
+ * hipFree or allocating library routine.  The gather aims at 2 work items per
+ * compute unit here, so FP64 results agree with xs_cross_section to rounding
+ * (the split of tiles into partial rows differs) rather than bitwise.  Every
+ * call on one GPU shares that GPU's scratch and leaves its contents behind:
+ * calls that overlap on one GPU (other threads, or plans on other streams
+ * with work still running) race.  The call uploads the plan's conditions and
+ * waits for the plan's stream to take them, then returns once the path is
+ * enqueued.  xs_plan_get_stats keeps reporting the plan's own workspace.
+ * Errors: as xs_cross_section, but no workspace is required; XS_EWORKSPACE
+ * when the plan's layout (max_lines lines, n_bins points, n_cond conditions)
+ * exceeds 64 MiB; XS_EINVAL when the plan's GPU is not the current device. */
+int xs_cross_section_noalloc(xs_plan* plan, const xs_states* states, const xs_lines* lines,
+                             double* sigma, int32_t accumulate);
+
 /* Record one xs_cross_section call with these arguments into a HIP graph
  * (no kernel runs during capture); xs_plan_replay launches it on the plan's
  * stream.  The pointers are kept until destroy or the next capture. */

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -292,7 +293,9 @@ void derive(xs_plan* p) {
   d.max_cut = maxcut;
 }
 
-size_t layout(xs_plan* p, char* base, Work* w) {
+// item_target: gather work items aimed at when tiles are split (sizes the
+// partial-row buffer, 2 item_target rows); 0 = kItemsPerCU per compute unit.
+size_t layout(xs_plan* p, char* base, Work* w, int64_t item_target = 0) {
   const ModelDev& d = p->md;
   const int64_t L = p->max_lines;
   const int nsb = (int)((L + kSortBlock - 1) / kSortBlock);
@@ -339,7 +342,7 @@ size_t layout(xs_plan* p, char* base, Work* w) {
     x.item_base = (int32_t*)take(4 * (size_t)(n_ct + 1));
     x.part_base = (int32_t*)take(4 * (size_t)(n_ct + 1));
     x.item_sums = (int32_t*)take(4 * (size_t)((n_ct + 1) / 1024 + 2));
-    x.item_target = kItemsPerCU * (int64_t)std::max(1, p->n_cu);
+    x.item_target = item_target > 0 ? item_target : kItemsPerCU * (int64_t)std::max(1, p->n_cu);
     x.part = (double*)take(sizeof(double) * 2 * (size_t)x.item_target * 1024);
   }
   x.stats = (unsigned long long*)take(8 * 8);
@@ -723,6 +726,80 @@ int xs_plan_get_stats(xs_plan* p, xs_stats* s) {
 int xs_plan_sync(xs_plan* p) {
   if (!p) return fail(XS_EINVAL, "plan is NULL");
   return hip_check(hipStreamSynchronize(p->stream), "stream sync");
+}
+
+// ---- allocation-free cross section ---------------------------------------
+// For callers that cannot allocate device memory, xs_cross_section_noalloc
+// runs the xs_cross_section path with its workspace carved from this array
+// instead of a caller-bound buffer.  Each GPU that runs the library holds its
+// own copy until the process ends.  Host code never uses the array's name as
+// an address: the device address comes from hipGetSymbolAddress, taken once
+// per device with that device current.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kNoallocItemsPerCU = 2;  // partial-row buffer: 2 x 2 rows of 8 KiB per compute unit
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch (dev must be the current device).
+int scratch_base(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(XS_EDEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    int rc;
+    if ((rc = hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)")))
+      return rc;
+    if (!ptr || ((uintptr_t)ptr & 255)) return fail(XS_EDEVICE, "scratch address is not 256-byte aligned");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return XS_OK;
+}
+}  // namespace
+
+int xs_cross_section_noalloc(xs_plan* p, const xs_states* st, const xs_lines* ln,
+                             double* sigma, int32_t accumulate) {
+  if (!p) return fail(XS_EINVAL, "plan is NULL");
+  int rc;
+  if ((rc = validate_states(p, st))) return rc;
+  if ((rc = validate_lines(p, ln))) return rc;
+  if (!sigma) return fail(XS_EINVAL, "sigma is NULL");
+  if (accumulate != 0 && accumulate != 1) return fail(XS_EINVAL, "accumulate must be 0 or 1");
+  const int64_t items = (int64_t)kNoallocItemsPerCU * std::max(1, p->n_cu);
+  const size_t need = layout(p, nullptr, nullptr, items);
+  if (need > kScratchBytes)
+    return fail(XS_EWORKSPACE, "the plan needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                                   std::to_string(kScratchBytes) +
+                                   " of the allocation-free path (fewer max_lines, grid points or conditions)");
+  int dev = -1;
+  if ((rc = hip_check(hipGetDevice(&dev), "hipGetDevice"))) return rc;
+  if (dev != p->device) return fail(XS_EINVAL, "the plan's GPU is not the current device");
+  void* base = nullptr;
+  if ((rc = scratch_base(dev, &base))) return rc;
+  // run on the scratch; the plan's own workspace and the state of its last
+  // xs_prepare are left as they were
+  const Work keep_w = p->w;
+  void* const keep_ws = p->ws;
+  const size_t keep_bytes = p->ws_bytes;
+  const bool keep_prepared = p->prepared, keep_tau = p->has_tau;
+  const int64_t keep_last = p->last_lines_in;
+  layout(p, (char*)base, &p->w, items);
+  p->ws = base;
+  p->ws_bytes = kScratchBytes;
+  rc = upload(p);
+  if (!rc) rc = preprocess(p, st, ln);
+  if (!rc) rc = profile_pass(p, sigma, accumulate);
+  p->w = keep_w;
+  p->ws = keep_ws;
+  p->ws_bytes = keep_bytes;
+  p->prepared = keep_prepared;
+  p->has_tau = keep_tau;
+  p->last_lines_in = keep_last;
+  return rc;
 }
 
 // ---- autotuner ----------------------------------------------------------

@@ -91,6 +91,7 @@ SIGNATURES = {
     "xs_cross_section": (C.c_int, [_P, C.POINTER(xs_states), C.POINTER(xs_lines), _P, C.c_int32]),
     "xs_cross_section_adjoint": (C.c_int, [_P, C.POINTER(xs_states), C.POINTER(xs_lines), _P, _P, _P,
                                            _P, _P, _P]),
+    "xs_cross_section_noalloc": (C.c_int, [_P, C.POINTER(xs_states), C.POINTER(xs_lines), _P, C.c_int32]),
     "xs_prepare": (C.c_int, [_P, C.POINTER(xs_states), C.POINTER(xs_lines)]),
     "xs_profile_pass": (C.c_int, [_P, _P, C.c_int32]),
     "xs_cooling_function": (C.c_int, [_P, C.POINTER(xs_states), C.POINTER(xs_lines), C.c_int32, _P, _P, _P]),
@@ -181,6 +182,11 @@ def xs_cross_section(plan, states, lines, sigma_ptr, accumulate=0):
 def xs_cross_section_adjoint(plan, states, lines, g_ptr, dT_ptr, dP_ptr, dgref_ptr, dnexp_ptr, dls_ptr):
     return _check(lib().xs_cross_section_adjoint(plan, C.byref(states), C.byref(lines), g_ptr, dT_ptr,
                                                  dP_ptr, dgref_ptr, dnexp_ptr, dls_ptr))
+
+
+def xs_cross_section_noalloc(plan, states, lines, sigma_ptr, accumulate=0):
+    return _check(lib().xs_cross_section_noalloc(plan, C.byref(states), C.byref(lines), sigma_ptr,
+                                                 accumulate))
 
 
 def xs_prepare(plan, states, lines):
@@ -374,6 +380,12 @@ class Plan:
         if out is None:
             out = t.empty((self.n_cond, self.grid.n_bins), dtype=t.float64, device="cuda")
         xs_cross_section(self.h, states.struct(), lines.struct(), out.data_ptr(), int(accumulate))
+        return out
+
+    def cross_section_noalloc(self, states: DeviceStates, lines: DeviceLines, out, accumulate=False):
+        """xs_cross_section_noalloc into the caller's ``out`` ([n_cond, n_bins]
+        float64): the library's static scratch instead of the workspace."""
+        xs_cross_section_noalloc(self.h, states.struct(), lines.struct(), out.data_ptr(), int(accumulate))
         return out
 
     def prepare(self, states: DeviceStates, lines: DeviceLines):
