@@ -714,6 +714,9 @@ def main():
                     help="skip the FP64 step, scatter, binned, pseudo-Voigt, lifetime and cooling-function extras")
     ap.add_argument("--no-full", action="store_true",
                     help="skip the 48-condition grid at 1e8 lines and the 1e9-line two-temperature stream")
+    ap.add_argument("--full-only", choices=["c3", "c5"], default=None,
+                    help="run only the 48-condition grid at 1e8 lines (c3) or the 1e9-line stream (c5) and "
+                         "print its JSON (for profiler runs)")
     ap.add_argument("--n-lines", type=int, default=None, help="(testing) fewer lines")
     ap.add_argument("--calib-copy", action="store_true", help="run only a 1 GiB device copy (PMC calibration)")
     args = ap.parse_args()
@@ -723,7 +726,7 @@ def main():
               "(sharding is described in the design notes); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    if not args.no_cpu_baseline and not args.calib_copy:
+    if not args.no_cpu_baseline and not args.calib_copy and not args.full_only:
         # the cpu_baseline leg's oracle is compiled (if stale) now, before
         # this process touches the GPU: afterwards it starts no child process
         import oracle
@@ -746,6 +749,10 @@ def main():
 
     copy = copy_bandwidth()
     log(f"device copy: {copy['GB_per_s']} GB/s")
+    if args.full_only:
+        leg = batched_48_full if args.full_only == "c3" else stream_2t_full
+        print(json.dumps({args.full_only: leg(X, copy["GB_per_s"]), "device_copy": copy}), flush=True)
+        return
     t_gen = time.perf_counter()
     wl = synth.config(2, n_lines=args.n_lines)
     lines = wl.lines()

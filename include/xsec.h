@@ -174,13 +174,17 @@ typedef struct {
  * 64..4096; a new plan starts at 64 for the Doppler and fixed-width Gaussian,
  * 256 otherwise); persistent: 1 = one persistent launch pulling items from a
  * device queue, 0 = one workgroup per item; waves_per_cu: size of the
- * persistent grid in waves per compute unit (4..64). */
+ * persistent grid in waves per compute unit (4..64); adj_blocks: blocks of
+ * 256 threads of the adjoint's persistent grid (0 = 2048, else a multiple of
+ * 256 in 256..8192; its per-block partial sums of dL/dT, dL/dP are added in
+ * block order, so each value is deterministic). */
 typedef struct {
   int32_t tile_bins;
   int32_t bucket_bins;
   int32_t persistent;
   int32_t waves_per_cu;
   int32_t chunk_lines;
+  int32_t adj_blocks;
 } xs_config;
 
 /* Counters of the last xs_cross_section / adjoint call (read after sync). */

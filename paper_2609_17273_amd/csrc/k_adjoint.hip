@@ -125,7 +125,7 @@ struct AdjArgs {
   double* dgref;
   double* dnexp;
   double* dls;
-  double* part;   // [n_cond][2][kAdjBlocks]
+  double* part;   // [n_cond][2][gridDim.x]
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -755,18 +755,18 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 4 : 3) void k_adjoint(AdjArgs
   for (int c = threadIdx.x; c < m.n_cond; c += 256) {
     const double t = ((sdt[0][c] + sdt[1][c]) + sdt[2][c]) + sdt[3][c];
     const double q = ((sdp[0][c] + sdp[1][c]) + sdp[2][c]) + sdp[3][c];
-    a.part[((int64_t)c * 2 + 0) * kAdjBlocks + blockIdx.x] = t;
-    a.part[((int64_t)c * 2 + 1) * kAdjBlocks + blockIdx.x] = q;
+    a.part[((int64_t)c * 2 + 0) * gridDim.x + blockIdx.x] = t;
+    a.part[((int64_t)c * 2 + 1) * gridDim.x + blockIdx.x] = q;
   }
 }
 
-__global__ __launch_bounds__(256) void k_adj_final(const double* part, int n_cond, double* dT,
+__global__ __launch_bounds__(256) void k_adj_final(const double* part, int n_cond, int nblk, double* dT,
                                                    double* dP) {
   __shared__ double sh[256];
   const int c = blockIdx.x;
   for (int which = 0; which < 2; ++which) {
     double v = 0.0;
-    for (int b = threadIdx.x; b < kAdjBlocks; b += 256) v += part[((int64_t)c * 2 + which) * kAdjBlocks + b];
+    for (int b = threadIdx.x; b < nblk; b += 256) v += part[((int64_t)c * 2 + which) * nblk + b];
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -810,7 +810,7 @@ __global__ __launch_bounds__(256) void k_gmax(const double* g, int64_t n_bins, u
 
 void launch_adjoint(const ModelDev& m, const Work& w, const StatesView& st, const LinesView& ln,
                     const double* g, double* dT, double* dP, double* dgref, double* dnexp,
-                    double* dls, int64_t n_lines, hipStream_t s) {
+                    double* dls, int64_t n_lines, int adj_blocks, hipStream_t s) {
   hipLaunchKernelGGL(k_zero3, dim3(2048), dim3(256), 0, s, dgref, dnexp, dls, n_lines, w.gmax, m.n_cond);
   if (m.prec == XS_FP32) {
     const int64_t gb = std::min<int64_t>((m.n_bins + 1023) / 1024, 512);
@@ -840,7 +840,7 @@ void launch_adjoint(const ModelDev& m, const Work& w, const StatesView& st, cons
   a.part = w.adjpart;
 #define XS_A(R, P)                                                                      \
   if (m.profile == P) {                                                                 \
-    hipLaunchKernelGGL((k_adjoint<R, P>), dim3(kAdjBlocks), dim3(256), 0, s, a);         \
+    hipLaunchKernelGGL((k_adjoint<R, P>), dim3(adj_blocks), dim3(256), 0, s, a);         \
   }
   if (m.prec == XS_FP32) {
     XS_A(float, XS_DOPPLER) XS_A(float, XS_GAUSSIAN) XS_A(float, XS_LORENTZ) XS_A(float, XS_VOIGT)
@@ -848,7 +848,7 @@ void launch_adjoint(const ModelDev& m, const Work& w, const StatesView& st, cons
     XS_A(double, XS_DOPPLER) XS_A(double, XS_GAUSSIAN) XS_A(double, XS_LORENTZ) XS_A(double, XS_VOIGT)
   }
 #undef XS_A
-  hipLaunchKernelGGL(k_adj_final, dim3(m.n_cond), dim3(256), 0, s, w.adjpart, m.n_cond, dT, dP);
+  hipLaunchKernelGGL(k_adj_final, dim3(m.n_cond), dim3(256), 0, s, w.adjpart, m.n_cond, adj_blocks, dT, dP);
 }
 
 }  // namespace xs

@@ -83,36 +83,41 @@ struct LineState {
   double nvu, nvl;  // vibronic densities of the upper and lower manifolds
 };
 
+// The part of ln|S| that no temperature enters: ln(g_u A / (8 pi c nu^2))
+// (absorption) or ln(g_u h c A nu / (4 pi)) (emission).
+__device__ inline double ln_line(int mode, const LineState& ls, double A, double nu) {
+  if (mode == XS_ABSORPTION) return log(ls.gu * A) - log(8.0 * kPI * kC) - 2.0 * log(nu);
+  return log(ls.gu * kH * kC * A * nu / (4.0 * kPI));
+}
+
+// The population (and stimulated-emission) part of ln|S| for one slot's
+// temperatures, and the sign of S.
+__device__ inline double ln_pop(int mode, int pop, const LineState& ls, double nu, double T, double Tv,
+                                double Tr, int& sign) {
+  sign = 1;
+  if (mode == XS_ABSORPTION) {
+    if (pop == XS_LTE) return -kC2 * ls.El / T + log(-expm1(-kC2 * nu / T));
+    if (pop == XS_NLTE_DENSITY)
+      return (ls.nvl > 0.0 ? log(ls.nvl) : -INFINITY) - kC2 * (ls.El - ls.evl) / Tr +
+             log(-expm1(-kC2 * nu / Tr));
+    const double nuv = ls.evu - ls.evl;
+    const double nur = (ls.Eu - ls.evu) - (ls.El - ls.evl);
+    const double x = kC2 * (nuv / Tv + nur / Tr);
+    const double st = -expm1(-x);
+    if (st < 0.0) sign = -1;
+    return -kC2 * ls.evl / Tv - kC2 * (ls.El - ls.evl) / Tr + log(fabs(st));
+  }
+  if (pop == XS_LTE) return -kC2 * ls.Eu / T;
+  if (pop == XS_NLTE_DENSITY) return (ls.nvu > 0.0 ? log(ls.nvu) : -INFINITY) - kC2 * (ls.Eu - ls.evu) / Tr;
+  return -kC2 * ls.evu / Tv - kC2 * (ls.Eu - ls.evu) / Tr;
+}
+
+// ln|S| = ln_line + ln_pop - ln Q + s (the loops over slots take ln_line
+// once per line and ln Q once per slot).
 __device__ inline double ln_intensity(int mode, int pop, const LineState& ls, double A,
                                       double nu, double T, double Tv, double Tr, double lnQ,
                                       double lscale, int& sign) {
-  sign = 1;
-  double r;
-  if (mode == XS_ABSORPTION) {
-    r = log(ls.gu * A) - log(8.0 * kPI * kC) - 2.0 * log(nu);
-    if (pop == XS_LTE) {
-      r += -kC2 * ls.El / T + log(-expm1(-kC2 * nu / T));
-    } else if (pop == XS_NLTE_DENSITY) {
-      r += (ls.nvl > 0.0 ? log(ls.nvl) : -INFINITY) - kC2 * (ls.El - ls.evl) / Tr +
-           log(-expm1(-kC2 * nu / Tr));
-    } else {
-      double nuv = ls.evu - ls.evl;
-      double nur = (ls.Eu - ls.evu) - (ls.El - ls.evl);
-      double x = kC2 * (nuv / Tv + nur / Tr);
-      double st = -expm1(-x);
-      if (st < 0.0) sign = -1;
-      r += -kC2 * ls.evl / Tv - kC2 * (ls.El - ls.evl) / Tr + log(fabs(st));
-    }
-  } else {
-    r = log(ls.gu * kH * kC * A * nu / (4.0 * kPI));
-    if (pop == XS_LTE)
-      r += -kC2 * ls.Eu / T;
-    else if (pop == XS_NLTE_DENSITY)
-      r += (ls.nvu > 0.0 ? log(ls.nvu) : -INFINITY) - kC2 * (ls.Eu - ls.evu) / Tr;
-    else
-      r += -kC2 * ls.evu / Tv - kC2 * (ls.Eu - ls.evu) / Tr;
-  }
-  return r - lnQ + lscale;
+  return (ln_line(mode, ls, A, nu) + ln_pop(mode, pop, ls, nu, T, Tv, Tr, sign)) - lnQ + lscale;
 }
 
 // Order-preserving map of doubles to unsigned keys (for an atomic max).

@@ -1,5 +1,7 @@
 // Line-side kernels: partition functions, the intensity pass, bucketing of
 // lines by home bin (stable LSD radix sort) and the sorted line records.
+#include <algorithm>
+
 #include "k_common.h"
 
 namespace xs {
@@ -119,19 +121,15 @@ __device__ __forceinline__ LineState line_state(const StatesView& st, int32_t u,
   return s;
 }
 
-// As line_state, with the energies and degeneracy from the line's pack (the
-// state tables are read only for the non-LTE manifold terms).
+// As line_state, with the energies, degeneracy and manifold energies from
+// the line's pack (the state tables are read only for the custom densities).
 __device__ __forceinline__ LineState line_state(const StatesView& st, const LinePack& lp, int pop) {
   LineState s;
   s.Eu = lp.Eu;
   s.El = lp.El;
   s.gu = lp.gu;
-  if (pop != XS_LTE) {
-    s.evu = st.ev[st.v[lp.u]];
-    s.evl = st.ev[st.v[lp.l]];
-  } else {
-    s.evu = s.evl = 0.0;
-  }
+  s.evu = lp.evu;
+  s.evl = lp.evl;
   if (pop == XS_NLTE_DENSITY) {
     s.nvu = st.nv[st.v[lp.u]];
     s.nvl = st.nv[st.v[lp.l]];
@@ -141,9 +139,95 @@ __device__ __forceinline__ LineState line_state(const StatesView& st, const Line
   return s;
 }
 
+// Per-state record for the first line pass: one random load per state of a
+// line instead of one per table (energies, degeneracies, manifold index and
+// energy).  Built once per prepare into the sort's second ping-pong buffers,
+// which are free until the sort's last pass; lists with more states than that
+// space holds read the tables directly.
+struct __attribute__((aligned(16))) StatePackLTE {
+  double E, g;
+};
+struct __attribute__((aligned(32))) StatePackNLTE {
+  double E, g, ev;  // ev: E_vib of the state's manifold
+  int64_t vi;       // manifold index, or -1 when outside the table
+};
+
+__global__ __launch_bounds__(256) void k_state_pack(ModelDev m, StatesView st, void* pack) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < st.n; i += (int64_t)gridDim.x * 256) {
+    if (m.pop == XS_LTE) {
+      StatePackLTE r;
+      r.E = st.E[i];
+      r.g = st.g[i];
+      ((StatePackLTE*)pack)[i] = r;
+    } else {
+      StatePackNLTE r;
+      r.E = st.E[i];
+      r.g = st.g[i];
+      const int32_t vi = st.v[i];
+      const bool ok = (uint32_t)vi < (uint32_t)st.n_v;
+      r.ev = ok ? st.ev[vi] : 0.0;
+      r.vi = ok ? (int64_t)vi : -1;
+      ((StatePackNLTE*)pack)[i] = r;
+    }
+  }
+}
+
+// The states of one line, read once: from the packed table, or from the
+// caller's tables.  ok: both indices (and, non-LTE, both manifolds) inside
+// the tables.
+template <int MODE>
+__device__ __forceinline__ bool gather_line_states(const ModelDev& m, const StatesView& st, const void* pack,
+                                                   int32_t u, int32_t l, LineState& ls, int32_t& vu, int32_t& vl) {
+  if ((uint32_t)u >= (uint64_t)st.n || (uint32_t)l >= (uint64_t)st.n) return false;
+  if (m.pop == XS_LTE) {
+    if (MODE) {
+      const StatePackLTE a = ((const StatePackLTE*)pack)[u], b = ((const StatePackLTE*)pack)[l];
+      ls.Eu = a.E;
+      ls.gu = a.g;
+      ls.El = b.E;
+    } else {
+      ls.Eu = st.E[u];
+      ls.gu = st.g[u];
+      ls.El = st.E[l];
+    }
+    ls.evu = ls.evl = 0.0;
+    vu = vl = 0;
+  } else {
+    if (MODE) {
+      const StatePackNLTE a = ((const StatePackNLTE*)pack)[u], b = ((const StatePackNLTE*)pack)[l];
+      if (a.vi < 0 || b.vi < 0) return false;
+      ls.Eu = a.E;
+      ls.gu = a.g;
+      ls.evu = a.ev;
+      ls.El = b.E;
+      ls.evl = b.ev;
+      vu = (int32_t)a.vi;
+      vl = (int32_t)b.vi;
+    } else {
+      vu = st.v[u];
+      vl = st.v[l];
+      if ((uint32_t)vu >= (uint32_t)st.n_v || (uint32_t)vl >= (uint32_t)st.n_v) return false;
+      ls.Eu = st.E[u];
+      ls.gu = st.g[u];
+      ls.El = st.E[l];
+      ls.evu = st.ev[vu];
+      ls.evl = st.ev[vl];
+    }
+  }
+  if (m.pop == XS_NLTE_DENSITY) {
+    ls.nvu = st.nv[vu];
+    ls.nvl = st.nv[vl];
+  } else {
+    ls.nvu = ls.nvl = 1.0;
+  }
+  return true;
+}
+
+// MODE 1: states from the packed table; 0: from the caller's tables.
+template <int MODE>
 __global__ __launch_bounds__(256) void k_lines_pass1(ModelDev m, const SlotDev* slots,
                                                      const double* Q, const double* cutc,
-                                                     const int32_t* cutm, StatesView st,
+                                                     const int32_t* cutm, StatesView st, const void* spack,
                                                      LinesView ln, int32_t* key,
                                                      LinePack* lpack,
                                                      unsigned long long* smax,
@@ -152,19 +236,24 @@ __global__ __launch_bounds__(256) void k_lines_pass1(ModelDev m, const SlotDev* 
   __shared__ unsigned long long scnt[3];
   if (threadIdx.x < 3) scnt[threadIdx.x] = 0;
   __syncthreads();
-  double lmax[8];
-  for (int q = 0; q < 8; ++q) lmax[q] = -INFINITY;
+  double lmax[8], lnq[8];
+  for (int q = 0; q < 8; ++q) {
+    lmax[q] = -INFINITY;
+    lnq[q] = (q < m.n_slots && m.prec == XS_FP32) ? log(Q[q]) : 0.0;
+  }
   unsigned long long kept = 0, pairs = 0, bad = 0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ln.n;
        i += (int64_t)gridDim.x * 256) {
     const int32_t u = ln.up[i], l = ln.lo[i];
     int32_t kk = m.n_buckets;
-    if (!line_indices_ok(st, u, l, m.pop)) {
+    LineState ls;
+    int32_t vu, vl;
+    if (!gather_line_states<MODE>(m, st, spack, u, l, ls, vu, vl)) {
       ++bad;
       key[i] = kk;
       continue;
     }
-    const double nu = st.E[u] - st.E[l];
+    const double nu = ls.Eu - ls.El;
     int64_t a, b;
     if (nu > 0.0 && line_window(nu, m.max_cut, m.nu0, m.dnu, m.n_bins, a, b)) {
       int64_t kc = home_bin(nu, m.nu0, m.dnu);
@@ -172,35 +261,37 @@ __global__ __launch_bounds__(256) void k_lines_pass1(ModelDev m, const SlotDev* 
       kk = (int32_t)(bk < m.n_buckets - 1 ? bk : m.n_buckets - 1);
       ++kept;
       LinePack lp;
-      lp.Eu = st.E[u];
-      lp.El = st.E[l];
-      lp.gu = st.g[u];
+      lp.Eu = ls.Eu;
+      lp.El = ls.El;
+      lp.gu = ls.gu;
       lp.u = u;
       lp.l = l;
-      lp.A = ln.A[i];
+      const float Af = ln.A[i];
+      const float lsf = ln.lscale ? ln.lscale[i] : 0.0f;
+      lp.A = Af;
       lp.gref = ln.gref ? ln.gref[i] : (float)ln.gref_scalar;
       lp.nexp = ln.nexp ? ln.nexp[i] : (float)ln.nexp_scalar;
-      lp.lscale = ln.lscale ? ln.lscale[i] : 0.0f;
-      lp.pad[0] = lp.pad[1] = lp.pad[2] = lp.pad[3] = 0;
+      lp.lscale = lsf;
+      lp.evu = ls.evu;
+      lp.evl = ls.evl;
       lpack[i] = lp;
       for (int q = 0; q < m.n_cut_classes; ++q) {
         if (line_window(nu, cutc[q], m.nu0, m.dnu, m.n_bins, a, b))
           pairs += (unsigned long long)(b - a + 1) * (unsigned long long)cutm[q];
       }
       if (m.prec == XS_FP32) {
-        const LineState ls = line_state(st, u, l, m.pop);
-        const double A = (double)ln.A[i];
-        const double sc = ln.lscale ? (double)ln.lscale[i] : 0.0;
+        const double sc = (double)lsf;
+        const double base = ln_line(m.mode, ls, (double)Af, nu);
         for (int q = 0; q < m.n_slots && q < 8; ++q) {
           const SlotDev sd = slots[q];
           int sg;
-          double lS = ln_intensity(m.mode, m.pop, ls, A, nu, sd.T, sd.Tv, sd.Tr, log(Q[q]), sc, sg);
+          double lS = (base + ln_pop(m.mode, m.pop, ls, nu, sd.T, sd.Tv, sd.Tr, sg)) - lnq[q] + sc;
           if (lS > lmax[q]) lmax[q] = lS;
         }
         for (int q = 8; q < m.n_slots; ++q) {  // rare: more than 8 temperatures
           const SlotDev sd = slots[q];
           int sg;
-          double lS = ln_intensity(m.mode, m.pop, ls, A, nu, sd.T, sd.Tv, sd.Tr, log(Q[q]), sc, sg);
+          double lS = (base + ln_pop(m.mode, m.pop, ls, nu, sd.T, sd.Tv, sd.Tr, sg)) - log(Q[q]) + sc;
           if (lS > -INFINITY) atomicMax(smax + q, dbl_key(lS));
         }
       }
@@ -240,8 +331,21 @@ void launch_lines_pass1(const ModelDev& m, const Work& w, const StatesView& st,
   int64_t blocks = (ln.n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_lines_pass1, dim3((unsigned)blocks), dim3(256), 0, s, m, w.slot, w.Q,
-                     w.cut_class, w.cut_mult, st, ln, w.key, w.lpack, w.smax, w.stats);
+  // the packed state table goes into the sort's second ping-pong buffers
+  // (keyB, valB: adjacent), when it fits there
+  const size_t rec = (m.pop == XS_LTE) ? sizeof(StatePackLTE) : sizeof(StatePackNLTE);
+  const size_t room = (size_t)((const char*)w.valB - (const char*)w.keyB) + 4 * (size_t)w.max_lines;
+  const bool packed = (size_t)st.n * rec <= room && ((uintptr_t)w.keyB % 32) == 0;
+  if (packed) {
+    const int64_t sb = std::min<int64_t>((st.n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_state_pack, dim3((unsigned)sb), dim3(256), 0, s, m, st, (void*)w.keyB);
+    hipLaunchKernelGGL(k_lines_pass1<1>, dim3((unsigned)blocks), dim3(256), 0, s, m, w.slot, w.Q,
+                       w.cut_class, w.cut_mult, st, (const void*)w.keyB, ln, w.key, w.lpack, w.smax, w.stats);
+  } else {
+    hipLaunchKernelGGL(k_lines_pass1<0>, dim3((unsigned)blocks), dim3(256), 0, s, m, w.slot, w.Q,
+                       w.cut_class, w.cut_mult, st, (const void*)nullptr, ln, w.key, w.lpack, w.smax,
+                       w.stats);
+  }
   hipLaunchKernelGGL(k_scale_final, dim3(1), dim3(256), 0, s, m, w.smax, w.sb);
 }
 
@@ -324,42 +428,76 @@ __global__ __launch_bounds__(256) void k_scan_add(int32_t* a, int64_t n, const i
     if (base + j < n) a[base + j] += add;
 }
 
+// Stable scatter of one pass, staged through LDS: the block places its keys
+// in digit order in LDS (the rank of a key among equal digits of its block is
+// the running count from earlier steps + the counts of earlier waves in this
+// step + the number of earlier lanes of its wave with the same digit, from 8
+// ballots), then writes each digit's run to its global place, so neighbouring
+// threads write neighbouring addresses.  offs: the exclusive scan of the
+// digit-major [256][nblk] histogram; the block's count of digit d is the step
+// from its entry to the next one (n after the last).
 __global__ __launch_bounds__(256) void k_sort_scatter(const int32_t* keys, const int32_t* vals,
                                                       int64_t n, int shift, const int32_t* offs,
                                                       int nblk, int32_t* okeys, int32_t* ovals) {
-  __shared__ int run[256];
+  __shared__ int lstart[256];   // first LDS position of each digit
+  __shared__ int goff[256];     // global position of the block's first key of each digit
+  __shared__ int run[256];      // keys of each digit placed so far
   __shared__ int wc[4][256];
+  __shared__ int sk[kSortBlock], sv[kSortBlock];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  run[tid] = offs[tid * nblk + blockIdx.x];
-  wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0;
-  __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortBlock;
+  {
+    const int64_t e = (int64_t)tid * nblk + blockIdx.x;
+    const int64_t next = (e + 1 < (int64_t)256 * nblk) ? (int64_t)offs[e + 1] : n;
+    const int c = (int)(next - offs[e]);
+    goff[tid] = offs[e];
+    // exclusive scan of the block's digit counts (Hillis-Steele in LDS)
+    lstart[tid] = c;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      const int t = tid >= o ? lstart[tid - o] : 0;
+      __syncthreads();
+      lstart[tid] += t;
+      __syncthreads();
+    }
+    lstart[tid] -= c;
+    run[tid] = 0;
+    wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0;
+    __syncthreads();
+  }
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int s = 0; s < kSortItems; ++s) {
-    const int64_t i = base + s * 256 + tid;
+  for (int st = 0; st < kSortItems; ++st) {
+    const int64_t i = base + st * 256 + tid;
     const bool act = i < n;
     const int k = act ? keys[i] : 0;
     const int d = (k >> shift) & 255;
     unsigned long long same = __ballot(act);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const unsigned long long bb = __ballot(act && ((d >> b) & 1));
-      same &= ((d >> b) & 1) ? bb : ~bb;
+    for (int bt = 0; bt < 8; ++bt) {
+      const unsigned long long bb = __ballot(act && ((d >> bt) & 1));
+      same &= ((d >> bt) & 1) ? bb : ~bb;
     }
     const int rank = __popcll(same & lt);
-    const bool leader = act && rank == 0;
-    if (leader) wc[wave][d] = __popcll(same);
+    if (act && rank == 0) wc[wave][d] = __popcll(same);
     __syncthreads();
     if (act) {
-      int pos = run[d] + rank;
+      int pos = lstart[d] + run[d] + rank;
       for (int w2 = 0; w2 < wave; ++w2) pos += wc[w2][d];
-      okeys[pos] = k;
-      ovals[pos] = vals ? vals[i] : (int32_t)i;
+      sk[pos] = k;
+      sv[pos] = vals ? vals[i] : (int32_t)i;
     }
     __syncthreads();
     run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
     wc[0][tid] = wc[1][tid] = wc[2][tid] = wc[3][tid] = 0;
     __syncthreads();
+  }
+  const int cnt = (int)min<int64_t>(kSortBlock, n - base);
+  for (int p = tid; p < cnt; p += 256) {
+    const int k = sk[p];
+    const int d = (k >> shift) & 255;
+    const int64_t g = (int64_t)goff[d] + (p - lstart[d]);
+    okeys[g] = k;
+    ovals[g] = sv[p];
   }
 }
 
@@ -421,6 +559,9 @@ __global__ __launch_bounds__(256) void k_records(ModelDev m, const SlotDev* slot
                                                  float* rnexp, double* rgpre, int32_t* ridx, void* rS,
                                                  const double* cut_class, int32_t* rkc, float* rdel,
                                                  int32_t* rwin) {
+  __shared__ double lnQ[kMaxCond];  // ln Q of every slot, once per block
+  for (int q = threadIdx.x; q < m.n_slots; q += 256) lnQ[q] = log(Q[q]);
+  __syncthreads();
   const int64_t nk = off[m.n_buckets];
   for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < nk;
        p += (int64_t)gridDim.x * 256) {
@@ -453,10 +594,11 @@ __global__ __launch_bounds__(256) void k_records(ModelDev m, const SlotDev* slot
     const LineState ls = line_state(st, lp, m.pop);
     const double A = (double)lp.A;
     const double sc = (double)lp.lscale;
+    const double base = ln_line(m.mode, ls, A, nu);
     for (int q = 0; q < m.n_slots; ++q) {
       const SlotDev sd = slots[q];
       int sg;
-      const double lS = ln_intensity(m.mode, m.pop, ls, A, nu, sd.T, sd.Tv, sd.Tr, log(Q[q]), sc, sg);
+      const double lS = (base + ln_pop(m.mode, m.pop, ls, nu, sd.T, sd.Tv, sd.Tr, sg)) - lnQ[q] + sc;
       if (m.prec == XS_FP32)
         ((float*)rS)[(int64_t)q * max_lines + p] = (float)(sg * exp(lS - sb[q]));
       else

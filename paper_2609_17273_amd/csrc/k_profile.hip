@@ -1329,7 +1329,10 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
           acc32[j] = 0.0f;
         }
       } else {
-        // FP64 form: x from the exact difference nu_k - nu_i
+        // FP64 form: x from the exact difference (nu_k - nu_i) inv, with the
+        // grid point nu_k rounded as the oracle rounds it.  (Stepping x from
+        // the row's first point skips that rounding: up to an ulp of nu_k,
+        // which moves the values of narrow lines near their core by ~1e-12.)
         auto uniform = [&](int l0, int l1, auto masked, auto npairs) {
           constexpr int NP = decltype(npairs)::value;
           for (int l = l0; l < l1; ++l) {
@@ -1347,21 +1350,53 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
               xs[j] = (nuk[j] - nu) * inv;
             }
             Pair<double> C[3];
+            KRange R1 = KRange{0x7fffffff, -0x7fffffff};
             if (PROF == XS_VOIGT && NP == 3) {
 #pragma unroll
               for (int q = 0; q < 3; ++q) C[q] = make_pair<double>(rr.c0, rr.y, GH::t6[q], GH::w6[q]);
+              R1 = KRange{uni(rr.r[1].lo), uni(rr.r[1].hi)};
+            }
+            double t[M];
+            if (PROF == XS_VOIGT && NP == 2) {
+              // two node pairs as one fraction N/D per point, and one
+              // reciprocal (with its Newton step) per two points:
+              // 1/D_j = D_j' r, 1/D_j' = D_j r with r = 1/(D_j D_j'); D is
+              // at least 6400^4 here and D_j D_j' stays below 1e170
+#pragma unroll
+              for (int j = 0; j + 1 < M; j += 2) {
+                double N[2], D[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                  const double x = xs[j + h];
+                  const double s1 = fma(x, x, rr.B1.h), s2 = fma(x, x, rr.B2.h);
+                  const double n1 = fma(rr.B1.cw, s1, rr.B1.cwt), d1 = fma(s1, s1, rr.B1.c);
+                  const double n2 = fma(rr.B2.cw, s2, rr.B2.cwt), d2 = fma(s2, s2, rr.B2.c);
+                  N[h] = fma(n1, d2, n2 * d1);
+                  D[h] = d1 * d2;
+                }
+                const double r = rcp64(D[0] * D[1]);
+                t[j] = N[0] * (D[1] * r);
+                t[j + 1] = N[1] * (D[0] * r);
+              }
+            } else {
+#pragma unroll
+              for (int j = 0; j < M; ++j) {
+                const double u = xs[j] * xs[j];
+                if (PROF == XS_LORENTZ) t[j] = rr.c0 * rcp64(fma(xs[j], xs[j], 1.0));
+                else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) t[j] = rr.c0 * exp2(-u);
+                else if (NP == 1) t[j] = pair_term<double>(rr.A, xs[j]);
+                else {
+                  // three-pair row: chunks wholly at |z|^2 >= 6400 take two pairs
+                  const int cl = row_lo + 64 * j;
+                  if (!meets(cl, cl + 63, R1)) t[j] = pair2_term(rr.B1, rr.B2, xs[j]);
+                  else t[j] = pair_term<double>(C[0], xs[j]) + pair2_term(C[1], C[2], xs[j]);
+                }
+              }
             }
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-              double t;
-              const double u = xs[j] * xs[j];
-              if (PROF == XS_LORENTZ) t = rr.c0 * rcp64(fma(xs[j], xs[j], 1.0));
-              else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) t = rr.c0 * exp2(-u);
-              else if (NP == 1) t = pair_term<double>(rr.A, xs[j]);
-              else if (NP == 2) t = pair2_term(rr.B1, rr.B2, xs[j]);
-              else t = pair_term<double>(C[0], xs[j]) + pair2_term(C[1], C[2], xs[j]);
               const int k = my0 + 64 * j;
-              if (!masked || (k >= klo && k <= khi)) acc64[j] += t;
+              if (!masked || (k >= klo && k <= khi)) acc64[j] += t[j];
             }
           }
         };
@@ -1405,7 +1440,9 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
               } else if (!meets(cl, ch, KRange{uni(rr.r[1].lo), uni(rr.r[1].hi)})) {
                 v = pair2_term(rr.B1, rr.B2, x);
               } else if (!meets(cl, ch, KRange{uni(rr.r[2].lo), uni(rr.r[2].hi)})) {
-                v = gh_pairs_y<3>(rr.c0, rr.y, u);
+                v = pair_term<double>(make_pair<double>(rr.c0, rr.y, GH::t6[0], GH::w6[0]), x) +
+                    pair2_term(make_pair<double>(rr.c0, rr.y, GH::t6[1], GH::w6[1]),
+                               make_pair<double>(rr.c0, rr.y, GH::t6[2], GH::w6[2]), x);
               } else if (!meets(cl, ch, KRange{uni(rr.r[3].lo), uni(rr.r[3].hi)})) {
                 v = gh_pairs_y<4>(rr.c0, rr.y, u);
               } else if (!meets(cl, ch, KRange{uni(rr.r[4].lo), uni(rr.r[4].hi)}) || u + rr.y * rr.y >= 64.0) {

@@ -162,6 +162,8 @@ int validate_config(const xs_config* c) {
   if (b < 64 || b > 4096 || (b & (b - 1))) return fail(XS_EINVAL, "config.bucket_bins must be a power of two in [64, 4096]");
   if (c->persistent != 0 && c->persistent != 1) return fail(XS_EINVAL, "config.persistent must be 0 or 1");
   if (c->waves_per_cu < 4 || c->waves_per_cu > 64) return fail(XS_EINVAL, "config.waves_per_cu must be in [4, 64]");
+  if (c->adj_blocks != 0 && (c->adj_blocks < 256 || c->adj_blocks > kAdjBlocksMax || c->adj_blocks % 256))
+    return fail(XS_EINVAL, "config.adj_blocks must be 0 or a multiple of 256 in [256, 8192]");
   return XS_OK;
 }
 
@@ -193,12 +195,14 @@ LinesView view(const xs_lines* l) {
 }
 
 // Tile shape (64 lanes x tile_bins / 64 bins), launch mode and lines per work item.
-void tiling_for(xs_plan* p, int tile_bins, int persistent, int waves_per_cu, int chunk_lines) {
+void tiling_for(xs_plan* p, int tile_bins, int persistent, int waves_per_cu, int chunk_lines,
+                int adj_blocks) {
   Tiling t;
   t.tile_bins = tile_bins;
   t.persistent = persistent;
   t.grid_blocks = std::max(1, p->n_cu * waves_per_cu);
   t.chunk_lines = chunk_lines;
+  t.adj_blocks = adj_blocks > 0 ? adj_blocks : kAdjBlocks;
   p->tiling = t;
 }
 
@@ -316,8 +320,10 @@ size_t layout(xs_plan* p, char* base, Work* w, int64_t item_target = 0) {
   x.sb = (double*)take(8 * d.n_slots);
   x.key = (int32_t*)take(4 * L);
   x.keyA = (int32_t*)take(4 * L);
-  x.keyB = (int32_t*)take(4 * L);
   x.valA = (int32_t*)take(4 * L);
+  // keyB and valB adjacent: before the sort's last pass they hold the first
+  // line pass's packed state table
+  x.keyB = (int32_t*)take(4 * L);
   x.valB = (int32_t*)take(4 * L);
   x.hist = (int32_t*)take(4 * (size_t)256 * nsb);
   x.hsum = (int32_t*)take(4 * ((size_t)256 * nsb / 1024 + 2));
@@ -346,7 +352,7 @@ size_t layout(xs_plan* p, char* base, Work* w, int64_t item_target = 0) {
     x.part = (double*)take(sizeof(double) * 2 * (size_t)x.item_target * 1024);
   }
   x.stats = (unsigned long long*)take(8 * 8);
-  x.adjpart = (double*)take(sizeof(double) * d.n_cond * 2 * kAdjBlocks);
+  x.adjpart = (double*)take(sizeof(double) * d.n_cond * 2 * kAdjBlocksMax);
   x.gmax = (unsigned long long*)take(sizeof(unsigned long long) * d.n_cond);
   x.cut_class = (double*)take(sizeof(double) * d.n_cut_classes);
   x.cut_mult = (int32_t*)take(sizeof(int32_t) * d.n_cut_classes);
@@ -461,7 +467,7 @@ int xs_plan_create(xs_plan** out, const xs_model* model, const xs_grid* grid, in
   p->n_cu = prop.multiProcessorCount;
   p->arch = prop.gcnArchName;
   derive(p);
-  tiling_for(p, 256, 1, 16, 0);  // the autotuner's usual pick for every profile measured
+  tiling_for(p, 256, 1, 16, 0, kAdjBlocks);  // the autotuner's usual pick for every profile measured
   std::memset(&p->w, 0, sizeof(p->w));
   *out = p;
   g_err.clear();
@@ -543,7 +549,7 @@ int xs_plan_set_config(xs_plan* p, const xs_config* c) {
       if ((rc = upload(p))) return rc;
     }
   }
-  tiling_for(p, c->tile_bins, c->persistent, c->waves_per_cu, c->chunk_lines);
+  tiling_for(p, c->tile_bins, c->persistent, c->waves_per_cu, c->chunk_lines, c->adj_blocks);
   return XS_OK;
 }
 
@@ -554,6 +560,7 @@ int xs_plan_get_config(const xs_plan* p, xs_config* c) {
   c->persistent = p->tiling.persistent;
   c->waves_per_cu = p->tiling.grid_blocks / std::max(1, p->n_cu);
   c->chunk_lines = (int32_t)p->tiling.chunk_lines;
+  c->adj_blocks = p->tiling.adj_blocks;
   return XS_OK;
 }
 
@@ -618,7 +625,8 @@ int xs_profile_adjoint(xs_plan* p, const xs_states* st, const xs_lines* ln, cons
     return fail(XS_EUNSUPPORTED, "adjoint: binned and pseudo-Voigt profiles are not supported");
   if (!g || !dT || !dP || !dls) return fail(XS_EINVAL, "adjoint: dL_dsigma, dL_dT, dL_dP and dL_dlog_scale are required");
   if (ln->n != p->last_lines_in) return fail(XS_EINVAL, "adjoint: lines differ from the prepared ones");
-  launch_adjoint(p->md, kernel_work(p), view(st), view(ln), g, dT, dP, dgref, dnexp, dls, ln->n, p->stream);
+  launch_adjoint(p->md, kernel_work(p), view(st), view(ln), g, dT, dP, dgref, dnexp, dls, ln->n,
+                 p->tiling.adj_blocks, p->stream);
   return hip_check(hipGetLastError(), "adjoint launch");
 }
 
@@ -633,7 +641,8 @@ int xs_cross_section_adjoint(xs_plan* p, const xs_states* st, const xs_lines* ln
     return fail(XS_EUNSUPPORTED, "adjoint: binned and pseudo-Voigt profiles are not supported");
   if (!g || !dT || !dP || !dls) return fail(XS_EINVAL, "adjoint: dL_dsigma, dL_dT, dL_dP and dL_dlog_scale are required");
   if ((rc = preprocess(p, st, ln))) return rc;
-  launch_adjoint(p->md, kernel_work(p), view(st), view(ln), g, dT, dP, dgref, dnexp, dls, ln->n, p->stream);
+  launch_adjoint(p->md, kernel_work(p), view(st), view(ln), g, dT, dP, dgref, dnexp, dls, ln->n,
+                 p->tiling.adj_blocks, p->stream);
   return hip_check(hipGetLastError(), "adjoint launch");
 }
 
@@ -823,14 +832,15 @@ static bool cache_lookup(const char* path, const std::string& key, xs_config* c)
   bool found = false;
   while (std::fgets(line, sizeof(line), f)) {
     char k[256];
-    int t, b, per, wv, cl;
-    if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"tile_bins\": %d, \"bucket_bins\": %d, \"persistent\": %d, \"waves_per_cu\": %d, \"chunk_lines\": %d",
-                    k, &t, &b, &per, &wv, &cl) == 6 && key == k) {
+    int t, b, per, wv, cl, ab;
+    if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"tile_bins\": %d, \"bucket_bins\": %d, \"persistent\": %d, \"waves_per_cu\": %d, \"chunk_lines\": %d, \"adj_blocks\": %d",
+                    k, &t, &b, &per, &wv, &cl, &ab) == 7 && key == k) {
       c->tile_bins = t;
       c->bucket_bins = b;
       c->persistent = per;
       c->waves_per_cu = wv;
       c->chunk_lines = cl;
+      c->adj_blocks = ab;
       found = true;
     }
   }
@@ -838,12 +848,14 @@ static bool cache_lookup(const char* path, const std::string& key, xs_config* c)
   return found;
 }
 
-static void cache_store(const char* path, const std::string& key, const xs_config& c, double ms) {
+static void cache_store(const char* path, const std::string& key, const xs_config& c, double ms,
+                        double adj_ms) {
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "{\"key\": \"%s\", \"tile_bins\": %d, \"bucket_bins\": %d, \"persistent\": %d, \"waves_per_cu\": %d, \"chunk_lines\": %d, \"ms\": %.4f}\n",
-               key.c_str(), c.tile_bins, c.bucket_bins, c.persistent, c.waves_per_cu, c.chunk_lines, ms);
+  std::fprintf(f, "{\"key\": \"%s\", \"tile_bins\": %d, \"bucket_bins\": %d, \"persistent\": %d, \"waves_per_cu\": %d, \"chunk_lines\": %d, \"adj_blocks\": %d, \"ms\": %.4f, \"adj_ms\": %.4f}\n",
+               key.c_str(), c.tile_bins, c.bucket_bins, c.persistent, c.waves_per_cu, c.chunk_lines,
+               c.adj_blocks, ms, adj_ms);
   std::fclose(f);
 }
 
@@ -863,48 +875,80 @@ int xs_plan_autotune(xs_plan* p, const xs_states* st, const xs_lines* ln, double
     (void)hipEventDestroy(e0);
     return rc;
   }
-  // candidates: bucket size (the plan's own first) x tile width x launch mode
-  // (persistent queue with two grid sizes, or one block per item)
+  // best of two timed runs after one untimed
+  auto time3 = [&](auto run, float& ms_best) {
+    ms_best = 1e30f;
+    for (int rep = 0; rep < 3 && !rc; ++rep) {
+      (void)hipEventRecord(e0, p->stream);
+      rc = run();
+      (void)hipEventRecord(e1, p->stream);
+      if (!rc) rc = hip_check(hipEventSynchronize(e1), "autotune sync");
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) ms_best = std::min(ms_best, ms);
+    }
+  };
+  // profile pass: bucket size (the plan's own first) x tile width x launch
+  // mode (persistent queue with two grid sizes, or one block per item)
   const int buckets[2] = {p->bucket_bins, p->bucket_bins == 64 ? 256 : 64};
   const int tiles[3] = {256, 512, 1024};
   const int modes[3][2] = {{0, 16}, {1, 16}, {1, 32}};
   double best_ms = 1e300;
   xs_config cur;
   cur.chunk_lines = 0;
+  cur.adj_blocks = p->tiling.adj_blocks;
   for (int bi = 0; bi < 2 && !rc; ++bi) {
-  if (buckets[bi] != p->bucket_bins) {
-    // re-bucket the lines (the workspace holds any bucket size)
-    p->bucket_bins = buckets[bi];
-    p->prepared = false;
-    derive(p);
-    layout(p, (char*)p->ws, &p->w);
-    if ((rc = upload(p))) break;
-    if ((rc = preprocess(p, st, ln))) break;
-  }
-  cur.bucket_bins = p->bucket_bins;
-  for (int si = 0; si < 3 && !rc; ++si) {
-    for (int mi = 0; mi < 3 && !rc; ++mi) {
-      cur.tile_bins = tiles[si];
-      cur.persistent = modes[mi][0];
-      cur.waves_per_cu = modes[mi][1];
-      tiling_for(p, cur.tile_bins, cur.persistent, cur.waves_per_cu, cur.chunk_lines);
-      float ms_best = 1e30f;
-      for (int rep = 0; rep < 3 && !rc; ++rep) {
-        launch_reset_queue(p->w, p->stream);
-        (void)hipEventRecord(e0, p->stream);
-        rc = profile_pass(p, sigma, 0);
-        (void)hipEventRecord(e1, p->stream);
-        if (!rc) rc = hip_check(hipEventSynchronize(e1), "autotune sync");
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (rep > 0) ms_best = std::min(ms_best, ms);
-      }
-      if (!rc && ms_best < best_ms) {
-        best_ms = ms_best;
-        best = cur;
+    if (buckets[bi] != p->bucket_bins) {
+      // re-bucket the lines (the workspace holds any bucket size)
+      p->bucket_bins = buckets[bi];
+      p->prepared = false;
+      derive(p);
+      layout(p, (char*)p->ws, &p->w);
+      if ((rc = upload(p))) break;
+      if ((rc = preprocess(p, st, ln))) break;
+    }
+    cur.bucket_bins = p->bucket_bins;
+    for (int si = 0; si < 3 && !rc; ++si) {
+      for (int mi = 0; mi < 3 && !rc; ++mi) {
+        cur.tile_bins = tiles[si];
+        cur.persistent = modes[mi][0];
+        cur.waves_per_cu = modes[mi][1];
+        tiling_for(p, cur.tile_bins, cur.persistent, cur.waves_per_cu, cur.chunk_lines, cur.adj_blocks);
+        float ms_best;
+        time3([&]() {
+          launch_reset_queue(p->w, p->stream);
+          return profile_pass(p, sigma, 0);
+        }, ms_best);
+        if (!rc && ms_best < best_ms) {
+          best_ms = ms_best;
+          best = cur;
+        }
       }
     }
   }
+  // adjoint grid size (LTE, sampled profiles): the records of the chosen
+  // bucket size, the last profile pass's sigma as the cotangent, and outputs
+  // in scratch the adjoint does not read (the line pack and partial rows)
+  double adj_ms = 0.0;
+  if (!rc && p->model.population == XS_LTE && p->model.profile < XS_BIN_DOPPLER) {
+    if ((rc = xs_plan_set_config(p, &best)) == XS_OK && !p->prepared) rc = preprocess(p, st, ln);
+    const int cand[3] = {1024, 2048, 4096};
+    double* outs = (double*)p->w.lpack;  // 64 B per line: room for three gradients
+    double* dTP = p->w.part;             // dL/dT, dL/dP
+    float adj_best = 1e30f;
+    for (int ci = 0; ci < 3 && !rc; ++ci) {
+      float ms_best;
+      time3([&]() {
+        launch_adjoint(p->md, kernel_work(p), view(st), view(ln), sigma, dTP, dTP + p->conds.size(), outs,
+                       outs + ln->n, outs + 2 * ln->n, ln->n, cand[ci], p->stream);
+        return hip_check(hipGetLastError(), "adjoint launch");
+      }, ms_best);
+      if (!rc && ms_best < adj_best) {
+        adj_best = ms_best;
+        best.adj_blocks = cand[ci];
+      }
+    }
+    adj_ms = adj_best;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -912,7 +956,7 @@ int xs_plan_autotune(xs_plan* p, const xs_states* st, const xs_lines* ln, double
   // the best bucket size (re-bucketed on the next prepare when it is not
   // the last one tried) and tiling
   if ((rc = xs_plan_set_config(p, &best))) return rc;
-  cache_store(cache_path, key, best, best_ms);
+  cache_store(cache_path, key, best, best_ms, adj_ms);
   return XS_OK;
 }
 

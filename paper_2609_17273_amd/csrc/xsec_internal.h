@@ -25,7 +25,8 @@ constexpr int base_profile(int profile) {
 }
 constexpr int kQBlocks = 256;     // partial sums per slot in the partition-function reduction
 constexpr int kItemsPerCU = 64;   // gather work items aimed at per compute unit when tiles are split
-constexpr int kAdjBlocks = 2048;  // persistent blocks of the adjoint (fixed: deterministic sums)
+constexpr int kAdjBlocks = 2048;     // persistent blocks of the adjoint in a new plan
+constexpr int kAdjBlocksMax = 8192;  // the most the configuration allows (sizes the partial sums)
 constexpr int kSortItems = 16;    // keys per thread in the radix sort (4096 per block)
 constexpr int kSortBlock = 256 * kSortItems;
 
@@ -90,7 +91,7 @@ struct __attribute__((aligned(64))) LinePack {
   double Eu, El, gu;
   float A, gref, nexp, lscale;
   int32_t u, l;
-  int32_t pad[4];
+  double evu, evl;  // E_vib of the upper and lower manifolds (non-LTE; 0 for LTE)
 };
 
 // Workspace pointers (carved by the host runtime from the caller's buffer).
@@ -130,7 +131,7 @@ struct Work {
   double* part;             // [2 item_target][1024] partial rows
   int64_t item_target;      // work items aimed at when tiles are split
   unsigned long long* stats;// [8]
-  double* adjpart;          // [n_cond][2][kAdjBlocks]
+  double* adjpart;          // [n_cond][2][kAdjBlocksMax]
   unsigned long long* gmax; // [n_cond] max |dL/dsigma| per condition (bits; FP32 adjoint's scale)
   double* cut_class;        // [n_cut_classes] distinct cut-offs
   int32_t* cut_mult;        // [n_cut_classes] conditions sharing each cut-off
@@ -143,6 +144,7 @@ struct Tiling {
   int32_t persistent;
   int32_t grid_blocks; // persistent grid size (one wave per block)
   int64_t chunk_lines; // requested candidate lines per work item (0: automatic)
+  int32_t adj_blocks;  // persistent blocks of the adjoint
 };
 
 // ---- launch wrappers (k_lines.hip) ----
@@ -177,6 +179,6 @@ void launch_cooling(const ModelDev& m, const Work& w, const StatesView& st, cons
 // ---- adjoint (k_adjoint.hip) ----
 void launch_adjoint(const ModelDev& m, const Work& w, const StatesView& st, const LinesView& ln,
                     const double* g, double* dT, double* dP, double* dgref, double* dnexp,
-                    double* dls, int64_t n_lines, hipStream_t s);
+                    double* dls, int64_t n_lines, int adj_blocks, hipStream_t s);
 
 }  // namespace xs

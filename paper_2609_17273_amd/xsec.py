@@ -67,7 +67,7 @@ class xs_lines(C.Structure):
 
 class xs_config(C.Structure):
     _fields_ = [("tile_bins", C.c_int32), ("bucket_bins", C.c_int32), ("persistent", C.c_int32),
-                ("waves_per_cu", C.c_int32), ("chunk_lines", C.c_int32)]
+                ("waves_per_cu", C.c_int32), ("chunk_lines", C.c_int32), ("adj_blocks", C.c_int32)]
 
 
 class xs_stats(C.Structure):
@@ -345,8 +345,9 @@ class Plan:
                 raise
             self._bind()
 
-    def set_config(self, tile_bins=256, bucket_bins=256, persistent=1, waves_per_cu=16, chunk_lines=0):
-        cfg = xs_config(tile_bins, bucket_bins, persistent, waves_per_cu, chunk_lines)
+    def set_config(self, tile_bins=256, bucket_bins=256, persistent=1, waves_per_cu=16, chunk_lines=0,
+                   adj_blocks=0):
+        cfg = xs_config(tile_bins, bucket_bins, persistent, waves_per_cu, chunk_lines, adj_blocks)
         try:
             xs_plan_set_config(self.h, cfg)
         except XsecError as e:
@@ -358,7 +359,7 @@ class Plan:
     def get_config(self) -> dict:
         c = xs_plan_get_config(self.h)
         return dict(tile_bins=c.tile_bins, bucket_bins=c.bucket_bins, persistent=c.persistent,
-                    waves_per_cu=c.waves_per_cu, chunk_lines=c.chunk_lines)
+                    waves_per_cu=c.waves_per_cu, chunk_lines=c.chunk_lines, adj_blocks=c.adj_blocks)
 
     def partition_function(self, states: DeviceStates):
         t = self.torch

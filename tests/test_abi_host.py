@@ -55,7 +55,7 @@ _STRUCTS = {
     "xs_states": ["n", "energy", "g_tot", "v", "e_vib", "n_v", "n_vib", "lifetime"],
     "xs_lines": ["n", "upper", "lower", "einstein_a", "gamma_ref", "n_exp", "log_scale",
                  "gamma_ref_scalar", "n_exp_scalar"],
-    "xs_config": ["tile_bins", "bucket_bins", "persistent", "waves_per_cu", "chunk_lines"],
+    "xs_config": ["tile_bins", "bucket_bins", "persistent", "waves_per_cu", "chunk_lines", "adj_blocks"],
     "xs_stats": ["lines_in", "lines_kept", "window_pairs", "work_items", "lines_invalid"],
 }
 
