@@ -76,7 +76,7 @@ ADJ_POINT_FLOPS = {"f32": [23, 51], "f64": [23, 51, 71]}
 # and FP64 alike.  The published 157.3 TFLOP/s FP32 figure needs packed math.
 PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
 KERNEL_SOURCES = ["paper_2609_17273_amd/csrc/k_profile.hip", "paper_2609_17273_amd/csrc/k_adjoint.hip",
-                  "paper_2609_17273_amd/csrc/k_common.h"]
+                  "paper_2609_17273_amd/csrc/k_common.h", "paper_2609_17273_amd/csrc/k_lines.hip"]
 
 
 def region_fractions(wl, lines, cond):
@@ -805,7 +805,8 @@ def main():
     extras = {}
     if not args.no_extras:
         p64 = plan_for(X.XS_FP64)
-        p64.set_config(**cfg)
+        cfg64 = p64.autotune(ds, dl, sig, cache_path=os.path.join("/tmp", "xsec_autotune.json"))
+        log(f"autotuned fp64: {cfg64}")
         ms64, per64, dist64 = time_steps(p64, ds, dl, sig, w, target, max(3, args.steps // 2), 2)
         log(f"fp64 step {ms64:.2f} ms {per64}")
         rl64 = {}
@@ -816,7 +817,8 @@ def main():
                                       traffic=traffic_from_profiles("gather_c2_f64" if kind == "fwd"
                                                                     else "adjoint_c2_f64"),
                                       region_fractions=[round(f, 5) for f in fracs[(kind, "f64")]])
-        extras["fp64"] = {"ms_per_step": round(ms64, 3), "stage_ms": {k: round(v, 3) for k, v in per64.items()},
+        extras["fp64"] = {"ms_per_step": round(ms64, 3), "kernel_config": cfg64,
+                          "stage_ms": {k: round(v, 3) for k, v in per64.items()},
                           "step_ms_device": dist64, "evals_per_s": 2 * pairs / (ms64 / 1e3),
                           "roofline_gather": rl64["fwd"], "roofline_adjoint": rl64["adj"],
                           "prepare_hbm": hbm_roofline(100, lines.n, per64["prepare"], copy["GB_per_s"])}
