@@ -550,7 +550,7 @@ def batched_48_full(X, copy_gbs, reps=3, tune_every=50):
     import numpy as np
     import torch
     import synth
-    wl = synth.config(3)
+    wl = synth.workload("voigt_grid48_1e8")
     t0 = time.perf_counter()
     ln = wl.lines()
     log(f"batched 48: generated {ln.n} lines in {time.perf_counter() - t0:.1f} s")
@@ -627,7 +627,7 @@ def stream_2t_full(X, copy_gbs, gen_threads=16):
     import torch
     from concurrent.futures import ThreadPoolExecutor
     import synth
-    wl = synth.config(5)
+    wl = synth.workload("twotemp_1e9")
     sizes = wl.chunk_sizes()
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=max(1, min(gen_threads, wl.n_chunks))) as ex:
@@ -682,7 +682,7 @@ def stream_2t_full(X, copy_gbs, gen_threads=16):
     dl = X.DeviceLines.from_numpy(chunks[0])
     del chunks
     variants = {}
-    wd = synth.with_vib_densities(synth.config(5))
+    wd = synth.with_vib_densities(synth.workload("twotemp_1e9"))
     dsd = X.DeviceStates.from_numpy(wd.states)
     for key, w_, dss, prof, prec in (("density_f32", wd, dsd, wl.profile, X.XS_FP32),
                                      ("binned_doppler_f32", wl, ds, synth.BIN_DOPPLER, X.XS_FP32),
@@ -714,8 +714,8 @@ def main():
                     help="skip the FP64 step, scatter, binned, pseudo-Voigt, lifetime and cooling-function extras")
     ap.add_argument("--no-full", action="store_true",
                     help="skip the 48-condition grid at 1e8 lines and the 1e9-line two-temperature stream")
-    ap.add_argument("--full-only", choices=["c3", "c5"], default=None,
-                    help="run only the 48-condition grid at 1e8 lines (c3) or the 1e9-line stream (c5) and "
+    ap.add_argument("--full-only", choices=["grid48", "twotemp"], default=None,
+                    help="run only the 48-condition grid at 1e8 lines (grid48) or the 1e9-line stream (twotemp) and "
                          "print its JSON (for profiler runs)")
     ap.add_argument("--n-lines", type=int, default=None, help="(testing) fewer lines")
     ap.add_argument("--calib-copy", action="store_true", help="run only a 1 GiB device copy (PMC calibration)")
@@ -750,11 +750,11 @@ def main():
     copy = copy_bandwidth()
     log(f"device copy: {copy['GB_per_s']} GB/s")
     if args.full_only:
-        leg = batched_48_full if args.full_only == "c3" else stream_2t_full
+        leg = batched_48_full if args.full_only == "grid48" else stream_2t_full
         print(json.dumps({args.full_only: leg(X, copy["GB_per_s"]), "device_copy": copy}), flush=True)
         return
     t_gen = time.perf_counter()
-    wl = synth.config(2, n_lines=args.n_lines)
+    wl = synth.workload("voigt_1e7", n_lines=args.n_lines)
     lines = wl.lines()
     cond = wl.conditions[0]
     log(f"generated {lines.n} lines, {wl.states.n} states in {time.perf_counter() - t_gen:.1f} s")
@@ -789,7 +789,7 @@ def main():
     rl = {}
     for kind, ms in (("fwd", per32["forward"]), ("adj", per32["adjoint"])):
         fpe = flops_per_eval(fracs, (kind, "f32"), shares["f32"])
-        key = "gather_c2_f32" if kind == "fwd" else "adjoint_c2_f32"
+        key = "gather_voigt1e7_f32" if kind == "fwd" else "adjoint_voigt1e7_f32"
         extra = {"traffic": traffic_from_profiles(key),
                  "region_fractions": [round(f, 5) for f in fracs[(kind, "f32")]],
                  "peak_note": "78.6 TFLOP/s: FP32 FMA without packed math (256 CU x 4 SIMD x 16 lanes x 2 x "
@@ -814,8 +814,8 @@ def main():
             fpe = flops_per_eval(fracs, (kind, "f64"), shares["f64"])
             rl64[kind] = alu_roofline(fpe, pairs, ms, "f64",
                                       "k_gather<double,Voigt>" if kind == "fwd" else "k_adjoint<double,Voigt>",
-                                      traffic=traffic_from_profiles("gather_c2_f64" if kind == "fwd"
-                                                                    else "adjoint_c2_f64"),
+                                      traffic=traffic_from_profiles("gather_voigt1e7_f64" if kind == "fwd"
+                                                                    else "adjoint_voigt1e7_f64"),
                                       region_fractions=[round(f, 5) for f in fracs[(kind, "f64")]])
         extras["fp64"] = {"ms_per_step": round(ms64, 3), "kernel_config": cfg64,
                           "stage_ms": {k: round(v, 3) for k, v in per64.items()},
@@ -866,7 +866,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded generator of the 1e7-line Voigt workload; no dataset)",
-        "config": {"workload": "config 2: LTE Voigt absorption, 1e6 states, 1e7 lines, T 2000 K, P 1 bar, "
+        "config": {"workload": "LTE Voigt absorption, 1e6 states, 1e7 lines, T 2000 K, P 1 bar, "
                                "grid 0-20000 cm^-1 step 0.01 (2,000,001 points), cut-off 25 cm^-1; step = "
                                "prepare + sigma + dL/dsigma + adjoint, FP32 log-scaled form",
                    "lines": lines.n, "states": wl.states.n, "grid_points": wl.grid.n_bins,

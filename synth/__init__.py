@@ -96,7 +96,7 @@ class Workload:
     n_chunks: int
     seed: int
     nu_max: float
-    line_kind: str                      # "c1" | "c2" | "c5"
+    line_kind: str                      # "flat" | "exp" | "manifold"
     hwhm_fixed: float = 0.0
     T_ref: float = 296.0
     P_ref: float = 1.0
@@ -120,7 +120,7 @@ class Workload:
             yield self.chunk(j)
 
     def lines(self) -> Lines:
-        """All lines (single-chunk workloads only: C5 at full size streams)."""
+        """All lines at once (the 1e9-line workload at full size is streamed chunk by chunk)."""
         if self._lines_cache is None:
             parts = [self.chunk(j) for j in range(self.n_chunks)]
             if len(parts) == 1:
@@ -154,7 +154,7 @@ def _f32(a: np.ndarray) -> np.ndarray:
     return np.asarray(a, dtype=np.float32)
 
 
-def _states_c1(rng: np.random.Generator, n: int) -> States:
+def _states_flat(rng: np.random.Generator, n: int) -> States:
     E = rng.uniform(0.0, 20000.0, n)
     J = rng.integers(0, 51, n)
     E[0] = 0.0
@@ -162,7 +162,7 @@ def _states_c1(rng: np.random.Generator, n: int) -> States:
     return States(E.astype(np.float64), (2 * J + 1).astype(np.float64))
 
 
-def _states_c2(rng: np.random.Generator, n: int) -> States:
+def _states_exp(rng: np.random.Generator, n: int) -> States:
     E = rng.exponential(8000.0, n)
     bad = E > 40000.0
     while bad.any():
@@ -174,7 +174,7 @@ def _states_c2(rng: np.random.Generator, n: int) -> States:
     return States(E.astype(np.float64), (2 * J + 1).astype(np.float64))
 
 
-def _states_c5(rng: np.random.Generator, n: int) -> States:
+def _states_manifold(rng: np.random.Generator, n: int) -> States:
     v = rng.integers(0, 11, n)
     J = rng.integers(0, 121, n)
     vv = np.arange(11, dtype=np.float64)
@@ -204,46 +204,50 @@ def _draw_lines(rng: np.random.Generator, st: States, n: int, nu_max: float,
         lo = np.concatenate([lo, l[ok]])
     up = up[:n].astype(np.int32)
     lo = lo[:n].astype(np.int32)
-    if kind == "c1":
+    if kind == "flat":
         A = _f32(10.0 ** rng.uniform(-6.0, 2.0, n))
         return Lines(up, lo, A)
     A = _f32(10.0 ** rng.uniform(-8.0, 3.0, n))
-    if kind == "c5":
+    if kind == "manifold":
         return Lines(up, lo, A)
     g = _f32(10.0 ** rng.uniform(np.log10(0.02), np.log10(0.1), n))
     ne = _f32(rng.uniform(0.3, 0.8, n))
     return Lines(up, lo, A, g, ne)
 
 
-C3_T = (300.0, 500.0, 800.0, 1200.0, 1800.0, 2500.0, 3500.0, 5000.0)
-C3_P = (1e-4, 1e-2, 1.0, 10.0, 50.0, 100.0)
-C5_PAIRS = ((3000.0, 1500.0), (5000.0, 2000.0), (2000.0, 2000.0), (8000.0, 3000.0))
+GRID48_T = (300.0, 500.0, 800.0, 1200.0, 1800.0, 2500.0, 3500.0, 5000.0)
+GRID48_P = (1e-4, 1e-2, 1.0, 10.0, 50.0, 100.0)
+TWOTEMP_PAIRS = ((3000.0, 1500.0), (5000.0, 2000.0), (2000.0, 2000.0), (8000.0, 3000.0))
+
+# name -> (seed, states, lines, nu_max, dnu, chunks, line kind, profile, mass)
+_WORKLOADS = {
+    # LTE absorption, Doppler, 2,000 states, 1e4 lines, grid 0-10000 step 0.01, 1000 K
+    "doppler_1e4": (1001, 2000, 10_000, 10000.0, 0.01, 1, "flat", DOPPLER, 18.0),
+    # LTE absorption, Voigt, 1e6 states, 1e7 lines, grid 0-20000 step 0.01, 2000 K, 1 bar
+    "voigt_1e7": (1002, 1_000_000, 10_000_000, 20000.0, 0.01, 1, "exp", VOIGT, 30.0),
+    # the same generator at 1e8 lines under 48 (T, P) conditions
+    "voigt_grid48_1e8": (1003, 1_000_000, 100_000_000, 20000.0, 0.01, 1, "exp", VOIGT, 30.0),
+    # the 1e7-line Voigt lines driving the adjoint (target spectrum at 1700 K, 0.8 bar)
+    "voigt_fit_1e7": (1004, 1_000_000, 10_000_000, 20000.0, 0.01, 1, "exp", VOIGT, 30.0),
+    # two-temperature emission, Doppler at T_rot, 1e6 states with v = 0..10,
+    # 1e9 lines in 10 chunks, grid 0-30000 step 0.05
+    "twotemp_1e9": (1005, 1_000_000, 1_000_000_000, 30000.0, 0.05, 10, "manifold", DOPPLER, 30.0),
+}
+WORKLOADS = tuple(_WORKLOADS)
 
 
-def config(k: int, *, n_lines: Optional[int] = None, n_states: Optional[int] = None,
-           nu_hi: Optional[float] = None, n_chunks: Optional[int] = None,
-           conditions: Optional[Sequence[Condition]] = None,
-           profile: Optional[int] = None, seed: Optional[int] = None) -> Workload:
-    """Workload k in 1..5 at full size, or shrunk through the keyword overrides.
+def workload(name: str, *, n_lines: Optional[int] = None, n_states: Optional[int] = None,
+             nu_hi: Optional[float] = None, n_chunks: Optional[int] = None,
+             conditions: Optional[Sequence[Condition]] = None,
+             profile: Optional[int] = None, seed: Optional[int] = None) -> Workload:
+    """A named workload at full size, or shrunk through the keyword overrides.
 
-    1: LTE absorption, Doppler, 2,000 states, 1e4 lines, grid 0-10000 step 0.01.
-    2: LTE absorption, Voigt, 1e6 states, 1e7 lines, grid 0-20000 step 0.01.
-    3: the workload-2 generator at 1e8 lines, 48 (T, P) conditions.
-    4: workload 2 (adjoint; target conditions 1700 K, 0.8 bar).
-    5: two-temperature emission, Doppler at T_rot, 1e6 states with v = 0..10,
-       1e9 lines in 10 chunks, grid 0-30000 step 0.05.
     ``nu_hi`` shrinks the line range and the grid together (same step).
     """
-    seed = 1000 + k if seed is None else seed
-    if k == 1:
-        ns, nl, hi, dnu, chunks, kind = 2000, 10_000, 10000.0, 0.01, 1, "c1"
-    elif k in (2, 3, 4):
-        ns, nl, hi, dnu, chunks, kind = 1_000_000, (10_000_000 if k != 3 else 100_000_000), \
-            20000.0, 0.01, 1, "c2"
-    elif k == 5:
-        ns, nl, hi, dnu, chunks, kind = 1_000_000, 1_000_000_000, 30000.0, 0.05, 10, "c5"
-    else:
-        raise ValueError("workload must be 1..5")
+    if name not in _WORKLOADS:
+        raise ValueError(f"unknown workload {name!r}; one of {WORKLOADS}")
+    seed0, ns, nl, hi, dnu, chunks, kind, prof0, mass = _WORKLOADS[name]
+    seed = seed0 if seed is None else seed
     if n_states is not None:
         ns = n_states
     if n_lines is not None:
@@ -257,29 +261,29 @@ def config(k: int, *, n_lines: Optional[int] = None, n_states: Optional[int] = N
     n_bins = int(round(hi / dnu)) + 1
     ss = np.random.SeedSequence(seed).spawn(chunks + 2)
     rng = np.random.Generator(np.random.PCG64(ss[0]))
-    if kind == "c1":
-        st = _states_c1(rng, ns)
-    elif kind == "c2":
-        st = _states_c2(rng, ns)
+    if kind == "flat":
+        st = _states_flat(rng, ns)
+    elif kind == "exp":
+        st = _states_exp(rng, ns)
     else:
-        st = _states_c5(rng, ns)
+        st = _states_manifold(rng, ns)
 
+    two_temp = name == "twotemp_1e9"
     if conditions is None:
-        if k == 1:
+        if name == "doppler_1e4":
             conditions = [Condition(1000.0, 0.0, 25.0)]
-        elif k in (2, 4):
-            conditions = [Condition(2000.0, 1.0, 25.0)]
-        elif k == 3:
+        elif name == "voigt_grid48_1e8":
             conditions = [Condition(T, P, 100.0 if P >= 10.0 else 25.0)
-                          for T in C3_T for P in C3_P]
+                          for T in GRID48_T for P in GRID48_P]
+        elif two_temp:
+            conditions = [Condition(tr, 0.0, 25.0, T_vib=tv, T_rot=tr) for tv, tr in TWOTEMP_PAIRS]
         else:
-            conditions = [Condition(tr, 0.0, 25.0, T_vib=tv, T_rot=tr) for tv, tr in C5_PAIRS]
+            conditions = [Condition(2000.0, 1.0, 25.0)]
     if profile is None:
-        profile = {1: DOPPLER, 2: VOIGT, 3: VOIGT, 4: VOIGT, 5: DOPPLER}[k]
-    mode = EMISSION if k == 5 else ABSORPTION
-    pop = NLTE_2T if k == 5 else LTE
-    mass = {1: 18.0, 2: 30.0, 3: 30.0, 4: 30.0, 5: 30.0}[k]
-    return Workload(name=f"config{k}", states=st, grid=Grid(0.0, dnu, n_bins),
+        profile = prof0
+    mode = EMISSION if two_temp else ABSORPTION
+    pop = NLTE_2T if two_temp else LTE
+    return Workload(name=name, states=st, grid=Grid(0.0, dnu, n_bins),
                     conditions=list(conditions), profile=profile, mode=mode, population=pop,
                     mass_amu=mass, n_lines=nl, n_chunks=chunks, seed=seed, nu_max=hi,
                     line_kind=kind, _ss=ss)
@@ -291,7 +295,7 @@ def with_vib_densities(wl: Workload, seed: int = 77) -> Workload:
     normalised to sum 1 (the densities' normalisation in the paper's
     custom-density population model).  Only T_rot of each condition is used."""
     if wl.states.e_vib is None:
-        raise ValueError("vibronic densities need states with manifolds (workload 5)")
+        raise ValueError("vibronic densities need states with manifolds (the two-temperature workload)")
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
     w = 10.0 ** rng.uniform(-3.0, 0.0, wl.states.e_vib.shape[0])
     wl.states.n_vib = w / w.sum()

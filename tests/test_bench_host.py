@@ -22,7 +22,7 @@ def test_more_than_one_gpu_is_refused(no_gpu_in_process):
 
 
 def test_region_fractions_partition_the_evaluations():
-    wl = synth.config(2, n_states=20000, n_lines=20000, nu_hi=5000.0)
+    wl = synth.workload("voigt_1e7", n_states=20000, n_lines=20000, nu_hi=5000.0)
     ln = wl.lines()
     fr = bench.region_fractions(wl, ln, wl.conditions[0])
     for kind, f in fr.items():
@@ -36,7 +36,7 @@ def test_region_fractions_partition_the_evaluations():
 def test_region_fractions_match_a_brute_force_count():
     """The closed form against counting |x|^2 + y^2 per grid point of the
     windows of a few lines (grid clipping excluded: lines in the middle)."""
-    wl = synth.config(2, n_states=20000, n_lines=40, nu_hi=3000.0)
+    wl = synth.workload("voigt_1e7", n_states=20000, n_lines=40, nu_hi=3000.0)
     ln = wl.lines()
     cond = wl.conditions[0]
     E = wl.states.energy
@@ -63,7 +63,7 @@ def test_traffic_only_for_the_current_sources():
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     with open(path) as f:
         d = json.load(f)
-    for key in ("gather_c2_f32", "adjoint_c2_f32"):
+    for key in ("gather_voigt1e7_f32", "adjoint_voigt1e7_f32"):
         got = bench.traffic_from_profiles(key)
         if d[key]["source_hash"] == bench.source_hash():
             assert got == d[key]["hbm_bytes_per_launch"] and got > 0
@@ -75,7 +75,7 @@ def test_adjoint_block_share_limits():
     """The share of adjoint waves in a block-summed form: all of them at a
     vanishing pressure, none at a huge one, and falling as y grows with P;
     the flop average moves between the two forms with it."""
-    wl = synth.config(2, n_states=20000, n_lines=5000, nu_hi=3000.0)
+    wl = synth.workload("voigt_1e7", n_states=20000, n_lines=5000, nu_hi=3000.0)
     ln = wl.lines()
     share = [bench.adj_block_share(wl, ln, synth.Condition(2000.0, P, 25.0), 450.0) for P in (1e-6, 0.3, 3.0, 1e4)]
     assert share[0] == 1.0 and share[-1] == 0.0

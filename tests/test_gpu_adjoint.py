@@ -47,7 +47,7 @@ _NARROW = (synth.Condition(2200.0, 0.05, 25.0), synth.Condition(2200.0, 0.2, 25.
 
 
 def _adj_case(prof, conds=_WIDE, gscale=1.0, positive=False):
-    wl = synth.config(2, n_states=20000, n_lines=8000, nu_hi=600.0, profile=prof, conditions=list(conds))
+    wl = synth.workload("voigt_1e7", n_states=20000, n_lines=8000, nu_hi=600.0, profile=prof, conditions=list(conds))
     ln = wl.lines()
     rng = np.random.default_rng(31)
     ls = (0.1 * rng.standard_normal(ln.n)).astype(np.float32)
@@ -133,7 +133,7 @@ def _check_adjoint(prof, prec, conds, gscale=1.0, positive=False):
 
 def _loss_setup(n_lines=6000, nu_hi=500.0):
     import torch
-    wl = synth.config(4, n_states=20000, n_lines=n_lines, nu_hi=nu_hi)
+    wl = synth.workload("voigt_fit_1e7", n_states=20000, n_lines=n_lines, nu_hi=nu_hi)
     ln = wl.lines()
     ds, dl = gpu_inputs(wl, ln)
     w = torch.as_tensor(wl.bin_weights(), device="cuda")
@@ -174,7 +174,7 @@ def test_adjoint_physical_cotangent():
     target t from the oracle: per-line gradients and dL/dT, dL/dP against the
     oracle's gradient."""
     import torch
-    wl = synth.config(4, n_states=20000, n_lines=6000, nu_hi=500.0)
+    wl = synth.workload("voigt_fit_1e7", n_states=20000, n_lines=6000, nu_hi=500.0)
     ln = wl.lines()
     cond = wl.conditions[0]
     s = oracle.run_condition(wl, ln, cond).sigma

@@ -19,7 +19,7 @@ FP64, FP32 = 0, 1
 @pytest.mark.parametrize("prec", [FP32, FP64])
 def test_batched_48_conditions_graph_vs_oracle(prec):
     import torch
-    wl = synth.config(3, n_lines=200_000, n_states=100_000)
+    wl = synth.workload("voigt_grid48_1e8", n_lines=200_000, n_states=100_000)
     assert len(wl.conditions) == 48
     ln = wl.lines()
     ds, dl = gpu_inputs(wl, ln)

@@ -27,23 +27,23 @@ TOL = {FP64: 1e-10, FP32: 1e-4}
 
 def _wl(name):
     if name == "doppler":
-        return synth.config(1, n_lines=3000, nu_hi=1500.0, profile=synth.BIN_DOPPLER)
+        return synth.workload("doppler_1e4", n_lines=3000, nu_hi=1500.0, profile=synth.BIN_DOPPLER)
     if name == "gaussian":
-        wl = synth.config(2, n_states=5000, n_lines=3000, nu_hi=400.0, profile=synth.BIN_GAUSSIAN)
+        wl = synth.workload("voigt_1e7", n_states=5000, n_lines=3000, nu_hi=400.0, profile=synth.BIN_GAUSSIAN)
         wl.hwhm_fixed = 0.037
         return wl
     if name == "lorentz":
-        return synth.config(2, n_states=20000, n_lines=3000, nu_hi=300.0, profile=synth.BIN_LORENTZ)
+        return synth.workload("voigt_1e7", n_states=20000, n_lines=3000, nu_hi=300.0, profile=synth.BIN_LORENTZ)
     if name == "voigt":
-        return synth.config(2, n_states=20000, n_lines=2000, nu_hi=250.0, profile=synth.BIN_VOIGT)
+        return synth.workload("voigt_1e7", n_states=20000, n_lines=2000, nu_hi=250.0, profile=synth.BIN_VOIGT)
     if name == "voigt_lowP":
-        return synth.config(2, n_states=20000, n_lines=2000, nu_hi=250.0, profile=synth.BIN_VOIGT,
+        return synth.workload("voigt_1e7", n_states=20000, n_lines=2000, nu_hi=250.0, profile=synth.BIN_VOIGT,
                             seed=1212, conditions=[synth.Condition(300.0, 1e-4, 25.0)])
     if name == "voigt_highP":
-        return synth.config(2, n_states=20000, n_lines=1500, nu_hi=250.0, profile=synth.BIN_VOIGT,
+        return synth.workload("voigt_1e7", n_states=20000, n_lines=1500, nu_hi=250.0, profile=synth.BIN_VOIGT,
                             seed=1213, conditions=[synth.Condition(300.0, 100.0, 100.0)])
     if name == "em2T":
-        return synth.config(5, n_states=20000, n_lines=6000, n_chunks=1, nu_hi=1500.0,
+        return synth.workload("twotemp_1e9", n_states=20000, n_lines=6000, n_chunks=1, nu_hi=1500.0,
                             profile=synth.BIN_DOPPLER)
     raise KeyError(name)
 
@@ -115,7 +115,7 @@ def test_binned_adjoint_unsupported():
 
 @pytest.mark.parametrize("prec", [FP32, FP64])
 def test_binned_voigt_full_size_sampled(prec):
-    wl = synth.config(2, profile=synth.BIN_VOIGT)
+    wl = synth.workload("voigt_1e7", profile=synth.BIN_VOIGT)
     ln = wl.lines()
     got, st, dt = gpu_sigma(wl, ln, prec)
     got = got[0]
@@ -141,7 +141,7 @@ def test_binned_gaussian_widths(hwhm, tile):
     """Fixed-width binned Gaussian at step 0.01 with a few nonzero bins per
     line (one line per lane) and with more than a tile of them (whole-row
     and 64-point wave steps)."""
-    wl = synth.config(2, n_states=5000, n_lines=3000, nu_hi=400.0, profile=synth.BIN_GAUSSIAN)
+    wl = synth.workload("voigt_1e7", n_states=5000, n_lines=3000, nu_hi=400.0, profile=synth.BIN_GAUSSIAN)
     wl.hwhm_fixed = hwhm
     ln = wl.lines()
     ref = oracle.run_condition(wl, ln, wl.conditions[0]).sigma

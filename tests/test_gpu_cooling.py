@@ -32,7 +32,7 @@ def _cmp(tag, got, ref, tol=1e-12):
 @pytest.mark.parametrize("prec", [FP64, FP32])
 def test_cooling_small(prec):
     import torch
-    wl = synth.config(2, n_states=20000, n_lines=200000, seed=1204)
+    wl = synth.workload("voigt_1e7", n_states=20000, n_lines=200000, seed=1204)
     ln = wl.lines()
     plan = make_plan(wl, prec, ln.n)
     ds, dl = gpu_inputs(wl, ln)
@@ -57,7 +57,7 @@ def test_cooling_small(prec):
 def test_cooling_discarded_and_invalid_lines():
     import torch
     P = X()
-    wl = synth.config(2, n_states=5000, n_lines=30000, seed=1205)
+    wl = synth.workload("voigt_1e7", n_states=5000, n_lines=30000, seed=1205)
     ln = wl.lines()
     n = ln.n
     up, lo = ln.upper.copy(), ln.lower.copy()
@@ -91,7 +91,7 @@ def test_cooling_discarded_and_invalid_lines():
 
 def test_cooling_non_lte_unsupported():
     P = X()
-    wl = synth.config(5, n_states=2000, n_lines=1000, n_chunks=1)
+    wl = synth.workload("twotemp_1e9", n_states=2000, n_lines=1000, n_chunks=1)
     ln = wl.lines()
     plan = make_plan(wl, FP64, ln.n)
     ds, dl = gpu_inputs(wl, ln)
@@ -103,7 +103,7 @@ def test_cooling_non_lte_unsupported():
 
 def test_cooling_full_size():
     import torch
-    wl = synth.config(2)
+    wl = synth.workload("voigt_1e7")
     ln = wl.lines()
     plan = make_plan(wl, FP32, ln.n)
     ds, dl = gpu_inputs(wl, ln)

@@ -19,7 +19,7 @@ FP64, FP32 = 0, 1
 
 
 def _wl(mode, n_lines=20000, profile=None, nu_hi=1500.0):
-    wl = synth.config(5, n_states=20000, n_lines=n_lines, n_chunks=1, nu_hi=nu_hi, profile=profile)
+    wl = synth.workload("twotemp_1e9", n_states=20000, n_lines=n_lines, n_chunks=1, nu_hi=nu_hi, profile=profile)
     synth.with_vib_densities(wl, seed=11)
     wl.states.n_vib[4] = 0.0  # an unpopulated manifold
     wl.mode = mode

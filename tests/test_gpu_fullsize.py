@@ -30,7 +30,7 @@ CACHE = os.path.join("/tmp", "xsec_autotune.json")
 @pytest.fixture(scope="module")
 def full():
     import torch
-    wl = synth.config(2)
+    wl = synth.workload("voigt_1e7")
     ln = wl.lines()
     ds, dl = gpu_inputs(wl, ln)
     sig = torch.empty((1, wl.grid.n_bins), dtype=torch.float64, device="cuda")

@@ -35,7 +35,7 @@ OFFSETS = np.array([-3, -1, 0, 1, 3])
 @pytest.fixture(scope="module")
 def grid48():
     import torch
-    wl = synth.config(3)
+    wl = synth.workload("voigt_grid48_1e8")
     ln = wl.lines()
     log(f"[full48] {ln.n} lines, {len(wl.conditions)} conditions generated")
     ds, dl = gpu_inputs(wl, ln)

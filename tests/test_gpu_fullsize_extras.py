@@ -37,7 +37,7 @@ def _sampled(wl, ln, got, seed):
 
 @pytest.mark.parametrize("kind", [synth.PV_OLIVERO, synth.PV_THOMPSON])
 def test_pseudo_voigt_full_size_sampled(kind):
-    wl = synth.config(2, profile=kind)
+    wl = synth.workload("voigt_1e7", profile=kind)
     ln = wl.lines()
     got, st, _ = gpu_sigma(wl, ln, FP32, config=CFG)
     e, l1, n = _sampled(wl, ln, got[0], 93)
@@ -47,7 +47,7 @@ def test_pseudo_voigt_full_size_sampled(kind):
 
 
 def test_lifetime_voigt_full_size_sampled():
-    wl = synth.config(2)
+    wl = synth.workload("voigt_1e7")
     synth.with_lifetimes(wl, frac=0.33, seed=5)
     ln = wl.lines()
     got, st, _ = gpu_sigma(wl, ln, FP32, config=CFG)

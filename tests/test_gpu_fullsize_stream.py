@@ -34,7 +34,7 @@ def stream1e9():
     import torch
     from concurrent.futures import ThreadPoolExecutor
     P = X()
-    wl = synth.config(5)
+    wl = synth.workload("twotemp_1e9")
     sizes = wl.chunk_sizes()
     with ThreadPoolExecutor(max_workers=min(wl.n_chunks, 16)) as ex:
         chunks = list(ex.map(wl.chunk, range(wl.n_chunks)))

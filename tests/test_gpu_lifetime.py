@@ -22,7 +22,7 @@ FP64, FP32 = 0, 1
 
 
 def _wl(profile, n_lines=3000, nu_hi=300.0, conditions=None):
-    wl = synth.config(2, n_states=20000, n_lines=n_lines, nu_hi=nu_hi, profile=profile, seed=1231,
+    wl = synth.workload("voigt_1e7", n_states=20000, n_lines=n_lines, nu_hi=nu_hi, profile=profile, seed=1231,
                       conditions=conditions)
     return synth.with_lifetimes(wl, frac=0.33, seed=5)
 

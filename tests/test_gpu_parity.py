@@ -33,7 +33,8 @@ def _check_sigma(name, got, ref, prec, st=None):
 @pytest.mark.parametrize("prec", [FP64, FP32])
 def test_partition_functions(prec):
     import torch
-    for k, kw in [(2, dict(n_states=200000, n_lines=10)), (5, dict(n_states=200000, n_lines=10, n_chunks=1))]:
+    for k, kw in [("voigt_1e7", dict(n_states=200000, n_lines=10)),
+                  ("twotemp_1e9", dict(n_states=200000, n_lines=10, n_chunks=1))]:
         wl = workload(k, **kw)
         plan = make_plan(wl, prec, 16)
         ds, _ = gpu_inputs(wl, wl.lines())
@@ -47,14 +48,15 @@ def test_partition_functions(prec):
                 assert dQ[c] == pytest.approx(dq, rel=1e-12, abs=0)
             else:
                 assert np.isnan(dQ[c])
-        log(f"[Q] config{k} Q={Q}")
+        log(f"[Q] {k} Q={Q}")
         plan.close()
 
 
-@pytest.mark.parametrize("k,prec", [(2, FP64), (2, FP32), (5, FP64), (5, FP32)])
+@pytest.mark.parametrize("k,prec", [("voigt_1e7", FP64), ("voigt_1e7", FP32),
+                                    ("twotemp_1e9", FP64), ("twotemp_1e9", FP32)])
 def test_line_intensities(k, prec):
     import torch
-    kw = dict(n_states=50000, n_lines=200000) if k == 2 else dict(n_states=50000, n_lines=200000, n_chunks=1)
+    kw = dict(n_states=50000, n_lines=200000) if k == "voigt_1e7" else dict(n_states=50000, n_lines=200000, n_chunks=1)
     wl = workload(k, **kw)
     ln = wl.lines()
     plan = make_plan(wl, prec, ln.n)
@@ -73,25 +75,25 @@ def test_line_intensities(k, prec):
         if prec == FP32:  # entries below the FP32 range of the chunk's maximum flush to zero
             m &= np.abs(Sref) >= np.abs(Sref).max() * 1e-30
         err = np.max(np.abs(got[m] - Sref[m]) / np.abs(Sref[m]))
-        log(f"[S] config{k} cond{c} prec={prec} max_rel={err:.3e}")
+        log(f"[S] {k} cond{c} prec={prec} max_rel={err:.3e}")
         assert err <= tol
         assert np.all(got[keep == 0] == 0.0)
     plan.close()
 
 
 SMALL = {
-    "doppler": (1, dict(n_lines=3000, nu_hi=1500.0)),
-    "voigt": (2, dict(n_states=20000, n_lines=20000, nu_hi=1200.0)),
-    "voigt_lowP": (2, dict(n_states=20000, n_lines=15000, nu_hi=1000.0, seed=1202)),
-    "lorentz": (2, dict(n_states=20000, n_lines=20000, nu_hi=1000.0, profile=synth.LORENTZ)),
-    "em2T": (5, dict(n_states=20000, n_lines=30000, n_chunks=1, nu_hi=2000.0)),
+    "doppler": ("doppler_1e4", dict(n_lines=3000, nu_hi=1500.0)),
+    "voigt": ("voigt_1e7", dict(n_states=20000, n_lines=20000, nu_hi=1200.0)),
+    "voigt_lowP": ("voigt_1e7", dict(n_states=20000, n_lines=15000, nu_hi=1000.0, seed=1202)),
+    "lorentz": ("voigt_1e7", dict(n_states=20000, n_lines=20000, nu_hi=1000.0, profile=synth.LORENTZ)),
+    "em2T": ("twotemp_1e9", dict(n_states=20000, n_lines=30000, n_chunks=1, nu_hi=2000.0)),
 }
 
 
 def _wl(name):
     k, kw = SMALL[name]
     wl = workload(k, **kw)
-    if name == "voigt_lowP":  # near-Doppler Voigt: y ~ 1e-6..1e-3 (the C3 low-pressure corner)
+    if name == "voigt_lowP":  # near-Doppler Voigt: y ~ 1e-6..1e-3 (the 48-condition grid's low-pressure corner)
         wl.conditions = [synth.Condition(300.0, 1e-4, 25.0)]
     return wl
 
@@ -116,7 +118,7 @@ def test_sigma_gaussian_fixed_hwhm(hwhm, tile):
     """Fixed-HWHM Gaussian at step 0.01: lines with a few nonzero points (one
     line per lane), about a hundred (FP32) or a few hundred (FP64) nonzero
     points (64 points per wave step), and more than a tile (whole-tile rows)."""
-    wl = synth.config(2, n_states=5000, n_lines=5000, nu_hi=600.0, profile=synth.GAUSSIAN)
+    wl = synth.workload("voigt_1e7", n_states=5000, n_lines=5000, nu_hi=600.0, profile=synth.GAUSSIAN)
     wl.hwhm_fixed = hwhm
     ref = oracle.run_condition(wl, wl.lines(), wl.conditions[0]).sigma
     for prec in (FP64, FP32):
@@ -145,18 +147,18 @@ def test_window_pair_count_matches_oracle():
 
 
 @pytest.mark.parametrize("algo", [0, 1])
-def test_config1_full_size_every_point(algo):
+def test_doppler_1e4_full_size_every_point(algo):
     """The small FP64 workload at its stated size: 2,000 states, 1e4 lines,
     LTE absorption at T = 1000 K, mass 18, Doppler profile, grid 0-10000
     cm^-1 step 0.01 (1,000,001 points), cut-off 25 cm^-1; the oracle at every
     point; FP64 (the workload's form) and FP32."""
-    wl = synth.config(1)
+    wl = synth.workload("doppler_1e4")
     ln = wl.lines()
     assert ln.n == 10_000 and wl.grid.n_bins == 1_000_001
     ref = oracle.run_condition(wl, ln, wl.conditions[0]).sigma
     for prec in (FP64, FP32):
         got, st, _ = gpu_sigma(wl, ln, prec, algo=algo)
-        _check_sigma(f"config1 full algo={algo}", got[0], ref, prec, st)
+        _check_sigma(f"doppler_1e4 full algo={algo}", got[0], ref, prec, st)
         assert st["lines_in"] == 10_000
 
 
@@ -170,7 +172,7 @@ def _tie_workload(profile):
     lines = synth.Lines(np.array([1, 2, 0, 4, 3], np.int32), np.array([0, 0, 1, 3, 3], np.int32),
                         np.array([1.0, 2.0, 1.0, 1.0, 1.0], np.float32),
                         np.full(5, 0.3, np.float32), np.full(5, 0.5, np.float32))
-    wl = synth.config(2, n_states=5, n_lines=5, nu_hi=25.0, profile=profile)
+    wl = synth.workload("voigt_1e7", n_states=5, n_lines=5, nu_hi=25.0, profile=profile)
     wl.states = states
     wl.grid = synth.Grid(0.0, 0.25, 101)
     wl.conditions = [synth.Condition(1000.0, 1.0, 2.0)]

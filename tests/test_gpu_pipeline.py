@@ -17,7 +17,7 @@ FP64, FP32 = 0, 1
 
 
 def _voigt_small():
-    return workload(2, n_states=20000, n_lines=20000, nu_hi=1200.0)
+    return workload("voigt_1e7", n_states=20000, n_lines=20000, nu_hi=1200.0)
 
 
 def test_graph_replay_equals_eager():
@@ -61,7 +61,7 @@ def test_gaussian_rows_repeatable_and_replayed(prec):
     """Narrow Doppler lines go through the per-lane LDS row adds: two eager
     runs are bitwise equal, and so are three graph replays."""
     import torch
-    wl = workload(5, n_states=20000, n_lines=30000, n_chunks=1, nu_hi=2000.0)
+    wl = workload("twotemp_1e9", n_states=20000, n_lines=30000, n_chunks=1, nu_hi=2000.0)
     ln = wl.lines()
     plan = make_plan(wl, prec, ln.n)
     ds, dl = gpu_inputs(wl, ln)
@@ -108,7 +108,7 @@ def test_autotuned_doppler_plan(prec):
     Doppler plan's 64), re-bucketing the lines in place; the tuned plan still
     matches the oracle."""
     import torch
-    wl = workload(5, n_states=20000, n_lines=30000, n_chunks=1, nu_hi=2000.0)
+    wl = workload("twotemp_1e9", n_states=20000, n_lines=30000, n_chunks=1, nu_hi=2000.0)
     ln = wl.lines()
     plan = make_plan(wl, prec, ln.n)
     ds, dl = gpu_inputs(wl, ln)
@@ -127,7 +127,7 @@ def test_autotuned_doppler_plan(prec):
 @pytest.mark.parametrize("prec", [FP64, FP32])
 def test_chunked_accumulation_equals_whole(prec):
     import torch
-    wl = workload(5, n_states=20000, n_lines=40000, n_chunks=4, nu_hi=2000.0)
+    wl = workload("twotemp_1e9", n_states=20000, n_lines=40000, n_chunks=4, nu_hi=2000.0)
     whole = wl.lines()
     plan = make_plan(wl, prec, max(wl.chunk_sizes()))
     ds = X().DeviceStates.from_numpy(wl.states)
@@ -150,7 +150,7 @@ def test_batched_conditions_equal_separate_and_oracle():
     import torch
     conds = [synth.Condition(T, P, 100.0 if P >= 10 else 25.0) for T in (300.0, 1200.0, 5000.0)
              for P in (1e-4, 1.0, 50.0)]
-    wl = synth.config(2, n_states=20000, n_lines=30000, nu_hi=2000.0, conditions=conds)
+    wl = synth.workload("voigt_1e7", n_states=20000, n_lines=30000, nu_hi=2000.0, conditions=conds)
     ln = wl.lines()
     plan = make_plan(wl, FP32, ln.n)
     ds, dl = gpu_inputs(wl, ln)
@@ -174,7 +174,7 @@ def test_batched_conditions_equal_separate_and_oracle():
 def test_edge_cases():
     import torch
     P = X()
-    wl = synth.config(2, n_states=2000, n_lines=500, nu_hi=100.0)
+    wl = synth.workload("voigt_1e7", n_states=2000, n_lines=500, nu_hi=100.0)
     ln = wl.lines()
     ds, dl = gpu_inputs(wl, ln)
     # no lines
@@ -199,7 +199,7 @@ def test_edge_cases():
     plan.close()
     # a one-point grid and a grid whose lines all lie beyond its ends
     for grid in (synth.Grid(50.0, 0.01, 1), synth.Grid(150.0, 0.01, 1000), synth.Grid(-30.0, 0.01, 2001)):
-        wl2 = synth.config(2, n_states=2000, n_lines=500, nu_hi=100.0)
+        wl2 = synth.workload("voigt_1e7", n_states=2000, n_lines=500, nu_hi=100.0)
         wl2.grid = grid
         for prec in (FP64, FP32):
             plan = make_plan(wl2, prec, ln.n)

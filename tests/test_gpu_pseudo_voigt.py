@@ -23,7 +23,7 @@ CASES = {
 
 
 def _wl(kind, case):
-    wl = synth.config(2, n_states=20000, n_lines=3000, nu_hi=300.0, profile=kind, seed=1241,
+    wl = synth.workload("voigt_1e7", n_states=20000, n_lines=3000, nu_hi=300.0, profile=kind, seed=1241,
                       conditions=CASES[case])
     if case == "mid":
         synth.with_lifetimes(wl, frac=0.33, seed=9)

@@ -20,7 +20,7 @@ FP64, FP32 = 0, 1
 def test_streamed_chunks_equal_resident_and_oracle(prec):
     import torch
     P = X()
-    wl = synth.config(5, n_lines=240_000, n_chunks=4, n_states=100_000)
+    wl = synth.workload("twotemp_1e9", n_lines=240_000, n_chunks=4, n_states=100_000)
     sizes = wl.chunk_sizes()
     assert len(sizes) == 4 and len(wl.conditions) == 4
     ds = P.DeviceStates.from_numpy(wl.states)

@@ -16,7 +16,7 @@ import synth
 
 
 def _wl(prof, n_lines=60, seed=21):
-    wl = synth.config(2, n_states=300, n_lines=n_lines, nu_hi=30.0, seed=seed, profile=prof,
+    wl = synth.workload("voigt_1e7", n_states=300, n_lines=n_lines, nu_hi=30.0, seed=seed, profile=prof,
                       conditions=[synth.Condition(1900.0, 0.7, 4.0)])
     return wl, wl.lines()
 

@@ -173,7 +173,7 @@ def test_sigma_binned_mass_and_brute_force(orc):
     # Lines on a small grid: sum_k sigma_k dnu equals sum_i S_i times the exact
     # Lorentzian mass between the outer edges of line i's window; and sigma
     # equals the double loop over (line, bin) of S_i fbar_ik.
-    wl = synth.config(2, n_states=60, n_lines=12, nu_hi=20.0, seed=4, profile=synth.BIN_LORENTZ,
+    wl = synth.workload("voigt_1e7", n_states=60, n_lines=12, nu_hi=20.0, seed=4, profile=synth.BIN_LORENTZ,
                       conditions=[synth.Condition(2000.0, 1.0, 2.0)])
     ln = wl.lines()
     cond = wl.conditions[0]

@@ -52,7 +52,7 @@ def test_two_level(orc):
 
 
 def test_equals_sum_of_emission_intensities(orc):
-    wl = synth.config(2, n_states=3000, n_lines=20000, nu_hi=20000.0, seed=31)
+    wl = synth.workload("voigt_1e7", n_states=3000, n_lines=20000, nu_hi=20000.0, seed=31)
     ln = wl.lines()
     T = np.array([200.0, 1000.0, 4000.0])
     W, Q = orc.cooling(wl.states, ln, T)

@@ -23,7 +23,7 @@ import synth
 
 
 def _wl(n_states=400, n_lines=3000, seed=5):
-    wl = synth.config(5, n_states=n_states, n_lines=n_lines, n_chunks=1, nu_hi=30000.0, seed=seed)
+    wl = synth.workload("twotemp_1e9", n_states=n_states, n_lines=n_lines, n_chunks=1, nu_hi=30000.0, seed=seed)
     return wl
 
 

@@ -77,7 +77,7 @@ def test_lorentzians_convolve_to_summed_width():
 
 
 def test_sigma_with_lifetimes_brute_force(orc):
-    wl = synth.config(2, n_states=60, n_lines=14, nu_hi=20.0, seed=9,
+    wl = synth.workload("voigt_1e7", n_states=60, n_lines=14, nu_hi=20.0, seed=9,
                       conditions=[synth.Condition(2000.0, 0.5, 5.0)])
     synth.with_lifetimes(wl, frac=0.5, seed=3)
     ln = wl.lines()

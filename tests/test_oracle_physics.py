@@ -110,7 +110,7 @@ def test_Q_two_temperature_factorises(orc):
 
 
 def test_dQdT_finite_difference(orc):
-    wl = synth.config(1, n_states=500)
+    wl = synth.workload("doppler_1e4", n_states=500)
     for T in [300.0, 1000.0, 4000.0]:
         Q, dQ = orc.partition(wl.states, orc.LTE, T)
         h = 1e-4 * T
@@ -119,7 +119,7 @@ def test_dQdT_finite_difference(orc):
 
 
 def _few_lines(n_states=300, n_lines=400, seed=5):
-    wl = synth.config(2, n_states=n_states, n_lines=n_lines, seed=seed)
+    wl = synth.workload("voigt_1e7", n_states=n_states, n_lines=n_lines, seed=seed)
     return wl, wl.lines()
 
 
@@ -140,7 +140,7 @@ def test_kirchhoff_emission_over_absorption(orc):
 
 
 def test_two_temperature_equal_T_is_lte(orc):
-    wl = synth.config(5, n_states=2000, n_lines=500, n_chunks=1)
+    wl = synth.workload("twotemp_1e9", n_states=2000, n_lines=500, n_chunks=1)
     ln = wl.lines()
     for mode in (orc.ABSORPTION, orc.EMISSION):
         T = 2345.0
@@ -154,7 +154,7 @@ def test_two_temperature_equal_T_is_lte(orc):
 def test_two_temperature_vibrational_scaling(orc):
     # Emission, Eq. (nlte em 2T): at fixed T_rot, changing T_vib multiplies each
     # line by exp(-c2 E_u,vib (1/Tv' - 1/Tv)) times the ratio of partition functions.
-    wl = synth.config(5, n_states=2000, n_lines=500, n_chunks=1)
+    wl = synth.workload("twotemp_1e9", n_states=2000, n_lines=500, n_chunks=1)
     ln = wl.lines()
     c2 = orc.c2()
     Tr, Tv1, Tv2 = 1500.0, 3000.0, 6000.0

@@ -19,7 +19,7 @@ LN2 = math.log(2.0)
 
 
 def _small(prof=synth.VOIGT, n_lines=14, nu_hi=20.0, seed=9, P=1.0, T=2000.0, cut=5.0):
-    wl = synth.config(2, n_states=60, n_lines=n_lines, nu_hi=nu_hi, seed=seed, profile=prof,
+    wl = synth.workload("voigt_1e7", n_states=60, n_lines=n_lines, nu_hi=nu_hi, seed=seed, profile=prof,
                       conditions=[synth.Condition(T, P, cut)])
     if prof == synth.GAUSSIAN:
         wl.hwhm_fixed = 0.05

@@ -6,19 +6,19 @@ import synth
 
 
 def test_deterministic_per_seed_and_chunk():
-    a = synth.config(2, n_states=5000, n_lines=20000)
-    b = synth.config(2, n_states=5000, n_lines=20000)
+    a = synth.workload("voigt_1e7", n_states=5000, n_lines=20000)
+    b = synth.workload("voigt_1e7", n_states=5000, n_lines=20000)
     np.testing.assert_array_equal(a.states.energy, b.states.energy)
     la, lb = a.lines(), b.lines()
     for f in ("upper", "lower", "einstein_a", "gamma_ref", "n_exp"):
         np.testing.assert_array_equal(getattr(la, f), getattr(lb, f))
-    c = synth.config(5, n_states=3000, n_lines=40000, n_chunks=4)
+    c = synth.workload("twotemp_1e9", n_states=3000, n_lines=40000, n_chunks=4)
     np.testing.assert_array_equal(c.chunk(2).upper, c.chunk(2).upper)
     assert not np.array_equal(c.chunk(1).upper, c.chunk(2).upper)
 
 
 def test_ranges_and_distributions():
-    wl = synth.config(2, n_states=20000, n_lines=100000)
+    wl = synth.workload("voigt_1e7", n_states=20000, n_lines=100000)
     st, ln = wl.states, wl.lines()
     assert st.energy[0] == 0.0 and st.g_tot[0] == 1.0
     assert st.energy.max() <= 40000.0
@@ -37,7 +37,7 @@ def test_ranges_and_distributions():
 
 
 def test_two_temperature_states():
-    wl = synth.config(5, n_states=10000, n_lines=1000, n_chunks=1)
+    wl = synth.workload("twotemp_1e9", n_states=10000, n_lines=1000, n_chunks=1)
     st = wl.states
     v = st.v
     assert v.min() == 0 and v.max() == 10
@@ -50,7 +50,7 @@ def test_two_temperature_states():
 
 
 def test_full_size_shapes_without_drawing_lines():
-    assert synth.config(3).n_lines == 100_000_000 and len(synth.config(3).conditions) == 48
-    c5 = synth.config(5)
-    assert c5.n_lines == 1_000_000_000 and c5.n_chunks == 10 and c5.chunk_sizes()[0] == 100_000_000
-    assert [c.cutoff for c in synth.config(3).conditions[:6]] == [25.0, 25.0, 25.0, 100.0, 100.0, 100.0]
+    assert synth.workload("voigt_grid48_1e8").n_lines == 100_000_000 and len(synth.workload("voigt_grid48_1e8").conditions) == 48
+    tt = synth.workload("twotemp_1e9")
+    assert tt.n_lines == 1_000_000_000 and tt.n_chunks == 10 and tt.chunk_sizes()[0] == 100_000_000
+    assert [c.cutoff for c in synth.workload("voigt_grid48_1e8").conditions[:6]] == [25.0, 25.0, 25.0, 100.0, 100.0, 100.0]

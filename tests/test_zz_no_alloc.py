@@ -19,7 +19,7 @@ FP64, FP32 = 0, 1
 @pytest.mark.parametrize("prec", [FP64, FP32])
 def test_noalloc_matches_cross_section(prec):
     import torch
-    wl = synth.config(2, n_states=20000, n_lines=12000, nu_hi=800.0, seed=2077,
+    wl = synth.workload("voigt_1e7", n_states=20000, n_lines=12000, nu_hi=800.0, seed=2077,
                       conditions=[synth.Condition(1800.0, 0.8, 25.0), synth.Condition(2600.0, 4.0, 25.0)])
     ln = wl.lines()
     plan = make_plan(wl, prec, ln.n)
@@ -54,7 +54,7 @@ def test_noalloc_matches_cross_section(prec):
 
 def test_noalloc_refuses_a_plan_beyond_the_scratch():
     P = X()
-    wl = synth.config(2, n_states=1000, n_lines=1000, nu_hi=100.0)
+    wl = synth.workload("voigt_1e7", n_states=1000, n_lines=1000, nu_hi=100.0)
     ln = wl.lines()
     plan = make_plan(wl, FP32, 5_000_000)   # ~0.7 GB of workspace
     ds, dl = gpu_inputs(wl, ln)

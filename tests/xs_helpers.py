@@ -72,7 +72,7 @@ def gpu_sigma(wl, lines, precision, algo=0, config=None, log_scale=None):
 @functools.lru_cache(maxsize=16)
 def _cached_workload(key):
     k, kw = key
-    return synth.config(k, **dict(kw))
+    return synth.workload(k, **dict(kw))
 
 
 def workload(k, **kw):
