@@ -116,10 +116,9 @@ struct AdjArgs {
   const float* rnexp;
   const double* rgpre;
   const int32_t* ridx;
+  const double* rEs;
   const void* rS;
   int64_t max_lines;
-  StatesView st;
-  LinesView ln;
   const double* g;
   const unsigned long long* gmax;  // [n_cond] bits of max_k |g_k| per condition
   double* dgref;
@@ -649,7 +648,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 4 : 3) void k_adjoint(AdjArgs
   for (int64_t bt = (int64_t)blockIdx.x * 4 + wave; bt < nbatch; bt += (int64_t)gridDim.x * 4) {
     const int64_t p = bt * 64 + lane;
     const bool have = p < nk;
-    double nu = 0.0, gref = 0.0, nexp = 0.0, gpre = 0.0, Eu = 0.0, El = 0.0;
+    double nu = 0.0, gref = 0.0, nexp = 0.0, gpre = 0.0, Es = 0.0;
     int32_t i = 0;
     if (have) {
       nu = a.rnu[p];
@@ -657,8 +656,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 4 : 3) void k_adjoint(AdjArgs
       nexp = (double)a.rnexp[p];
       gpre = a.rgpre ? a.rgpre[p] : 0.0;
       i = a.ridx[p];
-      Eu = a.st.E[a.ln.up[i]];
-      El = a.st.E[a.ln.lo[i]];
+      Es = a.rEs[p];
     }
     double dls = 0.0, dgr = 0.0, dne = 0.0;
     for (int c = 0; c < m.n_cond; ++c) {
@@ -727,10 +725,10 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 4 : 3) void k_adjoint(AdjArgs
       if (on) {
         const double T = cd.Tk;
         double dlnS;
-        if (m.mode == XS_ABSORPTION)
-          dlnS = kC2 * El / (T * T) - (kC2 * nu / (T * T)) / expm1(kC2 * nu / T) - a.dQ[cd.slot] / a.Q[cd.slot];
-        else
-          dlnS = kC2 * Eu / (T * T) - a.dQ[cd.slot] / a.Q[cd.slot];
+        if (m.mode == XS_ABSORPTION)  // Es = E of the lower state
+          dlnS = kC2 * Es / (T * T) - (kC2 * nu / (T * T)) / expm1(kC2 * nu / T) - a.dQ[cd.slot] / a.Q[cd.slot];
+        else                          // Es = E of the upper state
+          dlnS = kC2 * Es / (T * T) - a.dQ[cd.slot] / a.Q[cd.slot];
         const double dsg_dT = (PROF == XS_GAUSSIAN) ? 0.0 : sgm / (2.0 * T);
         dls += S * A;
         dgr += S * C * gpow * cd.pfac;
@@ -828,10 +826,9 @@ void launch_adjoint(const ModelDev& m, const Work& w, const StatesView& st, cons
   a.rnexp = w.rnexp;
   a.rgpre = w.rgpre;
   a.ridx = w.ridx;
+  a.rEs = w.rEs;
   a.rS = w.rS;
   a.max_lines = w.max_lines;
-  a.st = st;
-  a.ln = ln;
   a.g = g;
   a.gmax = w.gmax;
   a.dgref = dgref;

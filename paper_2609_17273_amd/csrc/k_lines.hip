@@ -556,7 +556,8 @@ __global__ __launch_bounds__(256) void k_records(ModelDev m, const SlotDev* slot
                                                  const LinePack* lpack,
                                                  const int32_t* svals, const int32_t* off,
                                                  int64_t max_lines, double* rnu, float* rgref,
-                                                 float* rnexp, double* rgpre, int32_t* ridx, void* rS,
+                                                 float* rnexp, double* rgpre, int32_t* ridx, double* rEs,
+                                                 void* rS,
                                                  const double* cut_class, int32_t* rkc, float* rdel,
                                                  int32_t* rwin) {
   __shared__ double lnQ[kMaxCond];  // ln Q of every slot, once per block
@@ -578,6 +579,7 @@ __global__ __launch_bounds__(256) void k_records(ModelDev m, const SlotDev* slot
       rgpre[p] = (tau > 0.0 && tau < INFINITY) ? 1.0 / (4.0 * kPI * kC * tau) : 0.0;
     }
     ridx[p] = i;
+    rEs[p] = (m.mode == XS_ABSORPTION) ? lp.El : lp.Eu;
     // home bin, offset from it, and the exact window of every cut-off class
     const int64_t kc = home_bin(nu, m.nu0, m.dnu);
     rkc[p] = (int32_t)kc;
@@ -615,7 +617,7 @@ void launch_offsets_records(const ModelDev& m, const Work& w, const StatesView& 
   hipLaunchKernelGGL(k_offsets, dim3((unsigned)blocks), dim3(256), 0, s, skeys, n, m.n_buckets,
                      w.off);
   hipLaunchKernelGGL(k_records, dim3((unsigned)blocks), dim3(256), 0, s, m, w.slot, w.Q, w.sb, st,
-                     w.lpack, svals, w.off, w.max_lines, w.rnu, w.rgref, w.rnexp, w.rgpre, w.ridx, w.rS,
+                     w.lpack, svals, w.off, w.max_lines, w.rnu, w.rgref, w.rnexp, w.rgpre, w.ridx, w.rEs, w.rS,
                      w.cut_class, w.rkc, w.rdel, w.rwin);
 }
 
@@ -665,7 +667,7 @@ void launch_intensity_out(const ModelDev& m, const Work& w, const StatesView& st
 // the step can be captured in a graph).
 __global__ void k_reset(int32_t* counter, unsigned long long* stats) {
   const int t = threadIdx.x;
-  if (t < 64) counter[t] = 0;
+  for (int q = t; q < kCounterInts; q += 64) counter[q] = 0;
   if (t < 8) stats[t] = 0ull;
 }
 
@@ -675,7 +677,7 @@ void launch_reset(const Work& w, hipStream_t s) {
 
 // Only the work queue (the counters of xs_prepare are kept).
 __global__ void k_reset_queue(int32_t* counter) {
-  if (threadIdx.x < 64) counter[threadIdx.x] = 0;
+  for (int q = threadIdx.x; q < kCounterInts; q += 64) counter[q] = 0;
 }
 
 void launch_scan_i32(int32_t* a, int64_t n, int32_t* sums, hipStream_t s) { scan_excl(a, n, sums, s); }

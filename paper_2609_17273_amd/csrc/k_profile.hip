@@ -146,15 +146,60 @@ struct __attribute__((aligned(16))) RecF {
   float y;
   int pad0;
 };
+// FP64 two node pairs (tau_1, W_1), (tau_2, W_2) of the four-point rule as
+// one fraction N(s)/D(s) in s = x^2 + y^2 - tau_1 = |z|^2 - tau_1.  With
+// d = tau_1 - tau_2, c_j = 4 y^2 tau_j and cw_j = c0 (2 y/pi) W_j the pairs
+// are cw_1 (s + e_1)/(s^2 + c_1) + cw_2 (s + e_2)/((s + d)^2 + c_2),
+// e_1 = 2 tau_1, e_2 = tau_1 + tau_2, so
+//   N = cw_1 (s + e_1)(s^2 + 2 d s + q) + cw_2 (s + e_2)(s^2 + c_1),
+//   D = (s^2 + c_1)(s^2 + 2 d s + q),  q = d^2 + c_2,
+// expanded into a cubic and a monic quartic.  Where the rule is used,
+// s >= 6400 - tau_1 and c_j <= 4 tau_j (s + tau_1), so every lower term of
+// either polynomial is below 2e-3 of the leading one: Horner's rule keeps the
+// relative error at a few units of rounding, with one FMA per degree.
+struct Poly2 {
+  double h, n3, n2, n1, n0, d3, d2, d1, d0;  // h = y^2 - tau_1
+};
+__device__ __forceinline__ Poly2 make_poly2(double c0, double y) {
+  const double t1 = GH::t4[0], t2 = GH::t4[1];
+  const double y2 = y * y, k = c0 * (2.0 * y / kPI);
+  const double cw1 = k * GH::w4[0], cw2 = k * GH::w4[1];
+  const double d = t1 - t2, c1 = 4.0 * y2 * t1, q = d * d + 4.0 * y2 * t2;
+  const double e1 = 2.0 * t1, e2 = t1 + t2;
+  Poly2 B;
+  B.h = y2 - t1;
+  B.n3 = cw1 + cw2;
+  B.n2 = cw1 * (2.0 * d + e1) + cw2 * e2;
+  B.n1 = cw1 * (q + 2.0 * d * e1) + cw2 * c1;
+  B.n0 = cw1 * e1 * q + cw2 * e2 * c1;
+  B.d3 = 2.0 * d;
+  B.d2 = q + c1;
+  B.d1 = 2.0 * d * c1;
+  B.d0 = c1 * q;
+  return B;
+}
+__device__ __forceinline__ void poly2_nd(const Poly2& B, double x, double& N, double& D) {
+  const double s = fma(x, x, B.h);
+  N = fma(fma(fma(B.n3, s, B.n2), s, B.n1), s, B.n0);
+  D = fma(fma(fma(s + B.d3, s, B.d2), s, B.d1), s, B.d0);
+}
+
 // FP64 form.  r[0..4]: bins with |z|^2 below 9e6, 6400, 400, 144, 64 (the
 // thresholds of the 1, 2, 3, 4 and 6 node-pair bands); for the Gaussian,
-// r[0] holds the bins where 2^{-x^2} is not zero in FP64.
+// r[0] holds the bins where 2^{-x^2} is not zero in FP64.  The far-region
+// rows of the Voigt take x = (offset of the point in the row) a + xb.  A line
+// stores the one-pair constants A when its row takes the first formula, else
+// the two-pair fraction B.
 struct __attribute__((aligned(16))) RecD {
   double nu, inv, c0, y;
-  Pair<double> A, B1, B2;
+  double a, xb;  // a = dnu / width; xb = x at the row's first point
   int klo, khi, flag, kc;
   KRange r[5];
   int pad0, pad1;
+  union {
+    Pair<double> A;
+    Poly2 B;
+  };
 };
 
 // the staging precision of a record type
@@ -362,11 +407,20 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, const LineIn<L
       nz = r.r[0];
       gauss = true;
     } else if (PROF == XS_VOIGT) {
-      r.A = make_pair<double>(lp.c0, lp.y, GH::t2[0], GH::w2[0]);
+      r.a = a;
+      r.xb = fma((double)(lo - kc), a, -b);
+      // The first and second formulas share one reciprocal among four
+      // points, a product of up to eight fourth-degree factors in x^2 + y^2:
+      // lines reaching |x| or y beyond 1e9 (nu below about 1e-5 cm^-1) take
+      // the general path, with a reciprocal per point.
+      const double xmax = fmax(fabs((double)(klo - kc) * a - b), fabs((double)(khi - kc) * a - b));
+      if (!(xmax <= 1.0e9) || !(lp.y <= 1.0e9)) r.flag = 1;
       r.r[0] = xr(9.0e6 * 1.001);
-      if (!meets(lo, hi, r.r[0])) return inside ? kRowF1 : kRowF1M;  // one-pair row
-      r.B1 = make_pair<double>(lp.c0, lp.y, GH::t4[0], GH::w4[0]);
-      r.B2 = make_pair<double>(lp.c0, lp.y, GH::t4[1], GH::w4[1]);
+      if (!r.flag && !meets(lo, hi, r.r[0])) {  // one-pair row
+        r.A = make_pair<double>(lp.c0, lp.y, GH::t2[0], GH::w2[0]);
+        return inside ? kRowF1 : kRowF1M;
+      }
+      r.B = make_poly2(lp.c0, lp.y);
       r.r[1] = xr(6400.0 * 1.001);
       r.r[2] = xr(400.0 * 1.001);
       r.r[3] = xr(144.0 * 1.001);
@@ -642,6 +696,11 @@ __device__ __forceinline__ double pair2_term(const Pair<double>& P, const Pair<d
   const double n2 = fma(Q.cw, s2, Q.cwt), d2 = fma(s2, s2, Q.c);
   return fma(n1, d2, n2 * d1) * rcp64(d1 * d2);
 }
+__device__ __forceinline__ double poly2_term(const Poly2& B, double x) {
+  double N, D;
+  poly2_nd(B, x, N, D);
+  return N * rcp64(D);
+}
 // NP node pairs from y (near-core chunks of the FP64 form; out of line, rare)
 template <int NP>
 __device__ __noinline__ double gh_pairs_y(double c0, double y, double u) {
@@ -720,8 +779,12 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
   const int64_t chunk = *(const int64_t*)(g.counter + 4);
   const float lane_off = (float)lane;
   float lane_j[M];  // lane + 64 j: a point's offset from the tile's first point
+  double lane_d[M];
 #pragma unroll
-  for (int j = 0; j < M; ++j) lane_j[j] = (float)(lane + 64 * j);
+  for (int j = 0; j < M; ++j) {
+    lane_j[j] = (float)(lane + 64 * j);
+    lane_d[j] = (double)(lane + 64 * j);
+  }
   int item = blockIdx.x;
   for (;;) {
     if (g.persistent) {
@@ -1357,26 +1420,38 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
               R1 = KRange{uni(rr.r[1].lo), uni(rr.r[1].hi)};
             }
             double t[M];
-            if (PROF == XS_VOIGT && NP == 2) {
-              // two node pairs as one fraction N/D per point, and one
-              // reciprocal (with its Newton step) per two points:
-              // 1/D_j = D_j' r, 1/D_j' = D_j r with r = 1/(D_j D_j'); D is
-              // at least 6400^4 here and D_j D_j' stays below 1e170
+            if (PROF == XS_VOIGT && NP <= 2) {
+              // The far region (one node pair, or two as one fraction N/D),
+              // x from the row's first point: x = (lane + 64 j) a + xb.  (It
+              // differs from (nu_k - nu) inv by the rounding of nu_k, ~1e-10
+              // absolute at most, which moves a value at |x| >= 80 by a
+              // relative 3e-12 at most.)  One reciprocal, with its Newton
+              // step, serves the four points j..j+3 of the lane:
+              // r = 1/(D_0 D_1 D_2 D_3), 1/D_0 = D_1 (D_2 D_3 r) and so on;
+              // the product stays finite for |x|, y <= 1e9 (staging sends
+              // wider lines to the general path).
+              const double a = rr.a, xb = rr.xb;
 #pragma unroll
-              for (int j = 0; j + 1 < M; j += 2) {
-                double N[2], D[2];
+              for (int j = 0; j < M; j += 4) {
+                double N[4], D[4];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                  const double x = xs[j + h];
-                  const double s1 = fma(x, x, rr.B1.h), s2 = fma(x, x, rr.B2.h);
-                  const double n1 = fma(rr.B1.cw, s1, rr.B1.cwt), d1 = fma(s1, s1, rr.B1.c);
-                  const double n2 = fma(rr.B2.cw, s2, rr.B2.cwt), d2 = fma(s2, s2, rr.B2.c);
-                  N[h] = fma(n1, d2, n2 * d1);
-                  D[h] = d1 * d2;
+                for (int h = 0; h < 4; ++h) {
+                  const double x = fma(lane_d[j + h], a, xb);
+                  if constexpr (NP == 1) {
+                    const double sv = fma(x, x, rr.A.h);
+                    N[h] = fma(rr.A.cw, sv, rr.A.cwt);
+                    D[h] = fma(sv, sv, rr.A.c);
+                  } else {
+                    poly2_nd(rr.B, x, N[h], D[h]);
+                  }
                 }
-                const double r = rcp64(D[0] * D[1]);
-                t[j] = N[0] * (D[1] * r);
-                t[j + 1] = N[1] * (D[0] * r);
+                const double p01 = D[0] * D[1], p23 = D[2] * D[3];
+                const double r = rcp64(p01 * p23);
+                const double r01 = p23 * r, r23 = p01 * r;
+                t[j] = N[0] * (D[1] * r01);
+                t[j + 1] = N[1] * (D[0] * r01);
+                t[j + 2] = N[2] * (D[3] * r23);
+                t[j + 3] = N[3] * (D[2] * r23);
               }
             } else {
 #pragma unroll
@@ -1388,7 +1463,7 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
                 else {
                   // three-pair row: chunks wholly at |z|^2 >= 6400 take two pairs
                   const int cl = row_lo + 64 * j;
-                  if (!meets(cl, cl + 63, R1)) t[j] = pair2_term(rr.B1, rr.B2, xs[j]);
+                  if (!meets(cl, cl + 63, R1)) t[j] = poly2_term(rr.B, xs[j]);
                   else t[j] = pair_term<double>(C[0], xs[j]) + pair2_term(C[1], C[2], xs[j]);
                 }
               }
@@ -1436,9 +1511,9 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
             } else {
               const double u = x * x;
               if (!meets(cl, ch, KRange{uni(rr.r[0].lo), uni(rr.r[0].hi)})) {
-                v = pair_term<double>(rr.A, x);
+                v = pair_term<double>(make_pair<double>(rr.c0, rr.y, GH::t2[0], GH::w2[0]), x);
               } else if (!meets(cl, ch, KRange{uni(rr.r[1].lo), uni(rr.r[1].hi)})) {
-                v = pair2_term(rr.B1, rr.B2, x);
+                v = poly2_term(rr.B, x);
               } else if (!meets(cl, ch, KRange{uni(rr.r[2].lo), uni(rr.r[2].hi)})) {
                 v = pair_term<double>(make_pair<double>(rr.c0, rr.y, GH::t6[0], GH::w6[0]), x) +
                     pair2_term(make_pair<double>(rr.c0, rr.y, GH::t6[1], GH::w6[1]),

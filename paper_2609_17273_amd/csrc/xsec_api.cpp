@@ -335,12 +335,13 @@ size_t layout(xs_plan* p, char* base, Work* w, int64_t item_target = 0) {
   x.rnexp = (float*)take(4 * L);
   x.rgpre = (double*)take(8 * L);
   x.ridx = (int32_t*)take(4 * L);
+  x.rEs = (double*)take(8 * L);
   x.lpack = (LinePack*)take(sizeof(LinePack) * L);
   x.rkc = (int32_t*)take(4 * L);
   x.rdel = (float*)take(4 * L);
   x.rwin = (int32_t*)take(8 * (size_t)d.n_cut_classes * L);
   x.rS = take((size_t)(d.prec == XS_FP32 ? 4 : 8) * d.n_slots * L);
-  x.counter = (int32_t*)take(4 * 64);
+  x.counter = (int32_t*)take(4 * kCounterInts);
   {
     // work items of the gather: sized for the smallest tile (256 bins)
     const int64_t n_ct = (int64_t)d.n_cond * ((p->grid.n_bins + 255) / 256);

@@ -28,6 +28,9 @@ constexpr int kItemsPerCU = 64;   // gather work items aimed at per compute unit
 constexpr int kAdjBlocks = 2048;     // persistent blocks of the adjoint in a new plan
 constexpr int kAdjBlocksMax = 8192;  // the most the configuration allows (sizes the partial sums)
 constexpr int kSortItems = 16;    // keys per thread in the radix sort (4096 per block)
+// Device counters (int32): [0] gather work queue, [2..3] candidate total,
+// [4..5] lines per item, [8] cooling-function runs.
+constexpr int kCounterInts = 64;
 constexpr int kSortBlock = 256 * kSortItems;
 
 // Per-condition scalars, uploaded with the workspace.
@@ -118,12 +121,14 @@ struct Work {
   double* rgpre;            //                 lifetime HWHM of the upper state, 1/(4 pi c tau) or 0
                             //                 (kernels get null when the states carry no lifetimes)
   int32_t* ridx;            //                 original line index
+  double* rEs;              //                 energy of the state whose population enters S
+                            //                 (lower: absorption, upper: emission; LTE adjoint)
   LinePack* lpack;          // [max_lines] line inputs in input order (first pass -> record pass)
   int32_t* rkc;             //                 home bin k_c = rint((nu - nu0)/dnu)
   float* rdel;              //                 nu - nu_{k_c}
   int32_t* rwin;            //                 [n_cut_classes][max_lines][2] window (klo, khi), klo > khi if empty
   void* rS;                 //                 S (f64) or S~ (f32), [n_slots][max_lines]
-  int32_t* counter;         // [64] work queue, candidate total, lines per item
+  int32_t* counter;         // [kCounterInts] work queues, candidate total, lines per item
   int32_t* item_cnt;        // [n_ct_max] candidate lines of each (tile, condition)
   int32_t* item_base;       // [n_ct_max + 1] work items of each (tile, condition), scanned
   int32_t* part_base;       // [n_ct_max + 1] partial rows of split tiles, scanned
