@@ -250,6 +250,27 @@ __device__ __forceinline__ double rcp_nr(double d) {
   return fma(r, fma(-d, r, 1.0), r);
 }
 
+// p(Z) = sum_{n<N} c_n Z^n with real c_n at a complex Z: Horner's rule for
+// the real quadratic Z^2 - t Z + m (t = 2 Re Z, m = |Z|^2), which Z solves
+// (Knuth, TAOCP vol. 2, sec. 4.6.4):  b_k = c_k + t b_(k+1) - m b_(k+2) for
+// k = N-1 .. 1, then p = b_1 Z + c_0 - m b_2.  Two FMAs per degree instead of
+// the four of complex Horner; for |Z| <= 1 (every z of the upper half-plane)
+// and the Weideman coefficients its rounding matches complex Horner's (both
+// 1.5e-15 of |w| over |z|^2 < 64 for N = 40, against 40-digit values).
+template <int N>
+__device__ __forceinline__ void poly_real_at(const double (&c)[N], double Zr, double Zi, double& pr, double& pi) {
+  const double t = 2.0 * Zr, mm = -fma(Zr, Zr, Zi * Zi);
+  double b1 = c[N - 1], b2 = 0.0;
+#pragma unroll
+  for (int k = N - 2; k >= 1; --k) {
+    const double b = fma(t, b1, fma(mm, b2, c[k]));
+    b2 = b1;
+    b1 = b;
+  }
+  pr = fma(b1, Zr, fma(mm, b2, c[0]));
+  pi = b1 * Zi;
+}
+
 template <int N>
 __device__ __forceinline__ void w_weideman(double x, double y, double& wr, double& wi) {
   constexpr double L = WM<N>::L;
@@ -260,14 +281,8 @@ __device__ __forceinline__ void w_weideman(double x, double y, double& wr, doubl
   // Z = ((L - y) + i x) q
   const double ly = L - y;
   const double Zr = fma(ly, qr, -x * qi), Zi = fma(ly, qi, x * qr);
-  double pr = WM<N>::a[N - 1], pi = 0.0;
-#pragma unroll
-  for (int n = N - 2; n >= 0; --n) {
-    const double nr = fma(pr, Zr, fma(-pi, Zi, WM<N>::a[n]));
-    const double ni = fma(pr, Zi, pi * Zr);
-    pr = nr;
-    pi = ni;
-  }
+  double pr, pi;
+  poly_real_at<N>(WM<N>::a, Zr, Zi, pr, pi);
   const double q2r = fma(qr, qr, -qi * qi), q2i = 2.0 * qr * qi;
   constexpr double rsp = 0.56418958354775628695;  // 1/sqrt(pi)
   wr = fma(2.0, fma(pr, q2r, -pi * q2i), rsp * qr);
@@ -418,14 +433,8 @@ __device__ __forceinline__ double w_int_im(double x, double y) {
   const double qr = lr * iD, qi = x * iD;
   const double ly = L - y;
   const double Zr = fma(ly, qr, -x * qi), Zi = fma(ly, qi, x * qr);
-  double pr = WM<N>::b[N - 1], pi = 0.0;
-#pragma unroll
-  for (int n = N - 2; n >= 0; --n) {
-    const double nr = fma(pr, Zr, fma(-pi, Zi, WM<N>::b[n]));
-    const double ni = fma(pr, Zi, pi * Zr);
-    pr = nr;
-    pi = ni;
-  }
+  double pr, pi;
+  poly_real_at<N>(WM<N>::b, Zr, Zi, pr, pi);
   return fma(pr, Zi, pi * Zr);  // Im(Z p)
 }
 

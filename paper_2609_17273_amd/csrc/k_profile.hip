@@ -1520,7 +1520,16 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
                                make_pair<double>(rr.c0, rr.y, GH::t6[2], GH::w6[2]), x);
               } else if (!meets(cl, ch, KRange{uni(rr.r[3].lo), uni(rr.r[3].hi)})) {
                 v = gh_pairs_y<4>(rr.c0, rr.y, u);
-              } else if (!meets(cl, ch, KRange{uni(rr.r[4].lo), uni(rr.r[4].hi)}) || u + rr.y * rr.y >= 64.0) {
+              } else if (!meets(cl, ch, KRange{uni(rr.r[4].lo), uni(rr.r[4].hi)})) {
+                v = gh_pairs_y<6>(rr.c0, rr.y, u);
+              } else if (rr.y >= 1.0e-3 && rr.a <= 1.0) {
+                // a chunk that reaches |z|^2 < 64: the rational approximation
+                // on every lane.  Its points have |x| <= 8 + 64 a <= 72, where
+                // it keeps Re w within 4e-12 relative for y >= 1e-3 (its
+                // absolute error, 1.5e-15 of |w|, against Re w >= ~y |w| / |z|),
+                // so the lanes need not split between it and six node pairs.
+                v = rr.c0 * re_w_core<40>(x, rr.y);
+              } else if (u + rr.y * rr.y >= 64.0) {
                 v = gh_pairs_y<6>(rr.c0, rr.y, u);
               } else {
                 v = rr.c0 * re_w_core<40>(x, rr.y);
