@@ -223,7 +223,11 @@ __device__ __forceinline__ bool gather_line_states(const ModelDev& m, const Stat
   return true;
 }
 
-// MODE 1: states from the packed table; 0: from the caller's tables.
+// MODE 1: states from the packed table; 0: from the caller's tables.  The
+// running maximum of ln|S| of each slot (FP32 form) is kept per thread in LDS
+// rather than in registers, so the pass holds few registers and many waves
+// keep its random state loads in flight.
+constexpr int kPass1Slots = 8;  // slots whose maximum is kept per thread; more use atomics
 template <int MODE>
 __global__ __launch_bounds__(256) void k_lines_pass1(ModelDev m, const SlotDev* slots,
                                                      const double* Q, const double* cutc,
@@ -232,18 +236,18 @@ __global__ __launch_bounds__(256) void k_lines_pass1(ModelDev m, const SlotDev* 
                                                      LinePack* lpack,
                                                      unsigned long long* smax,
                                                      unsigned long long* stats) {
-  __shared__ double smx[256];
+  __shared__ double lmax[kPass1Slots][256];
+  __shared__ double lnq[kPass1Slots];
   __shared__ unsigned long long scnt[3];
-  if (threadIdx.x < 3) scnt[threadIdx.x] = 0;
+  const int tid = threadIdx.x;
+  const bool f32 = m.prec == XS_FP32;
+  const int ns = min(m.n_slots, kPass1Slots);
+  if (tid < 3) scnt[tid] = 0;
+  if (tid < ns && f32) lnq[tid] = log(Q[tid]);
+  for (int q = 0; q < ns; ++q) lmax[q][tid] = -INFINITY;
   __syncthreads();
-  double lmax[8], lnq[8];
-  for (int q = 0; q < 8; ++q) {
-    lmax[q] = -INFINITY;
-    lnq[q] = (q < m.n_slots && m.prec == XS_FP32) ? log(Q[q]) : 0.0;
-  }
   unsigned long long kept = 0, pairs = 0, bad = 0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ln.n;
-       i += (int64_t)gridDim.x * 256) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < ln.n; i += (int64_t)gridDim.x * 256) {
     const int32_t u = ln.up[i], l = ln.lo[i];
     int32_t kk = m.n_buckets;
     LineState ls;
@@ -275,24 +279,28 @@ __global__ __launch_bounds__(256) void k_lines_pass1(ModelDev m, const SlotDev* 
       lp.evu = ls.evu;
       lp.evl = ls.evl;
       lpack[i] = lp;
-      for (int q = 0; q < m.n_cut_classes; ++q) {
-        if (line_window(nu, cutc[q], m.nu0, m.dnu, m.n_bins, a, b))
-          pairs += (unsigned long long)(b - a + 1) * (unsigned long long)cutm[q];
+      if (m.n_cut_classes == 1 && cutc[0] == m.max_cut) {
+        pairs += (unsigned long long)(b - a + 1) * (unsigned long long)cutm[0];
+      } else {
+#pragma unroll 1
+        for (int q = 0; q < m.n_cut_classes; ++q) {
+          if (line_window(nu, cutc[q], m.nu0, m.dnu, m.n_bins, a, b))
+            pairs += (unsigned long long)(b - a + 1) * (unsigned long long)cutm[q];
+        }
       }
-      if (m.prec == XS_FP32) {
+      if (f32) {
         const double sc = (double)lsf;
         const double base = ln_line(m.mode, ls, (double)Af, nu);
-        for (int q = 0; q < m.n_slots && q < 8; ++q) {
+#pragma unroll 1
+        for (int q = 0; q < m.n_slots; ++q) {
           const SlotDev sd = slots[q];
           int sg;
-          double lS = (base + ln_pop(m.mode, m.pop, ls, nu, sd.T, sd.Tv, sd.Tr, sg)) - lnq[q] + sc;
-          if (lS > lmax[q]) lmax[q] = lS;
-        }
-        for (int q = 8; q < m.n_slots; ++q) {  // rare: more than 8 temperatures
-          const SlotDev sd = slots[q];
-          int sg;
-          double lS = (base + ln_pop(m.mode, m.pop, ls, nu, sd.T, sd.Tv, sd.Tr, sg)) - log(Q[q]) + sc;
-          if (lS > -INFINITY) atomicMax(smax + q, dbl_key(lS));
+          const double lS = base + ln_pop(m.mode, m.pop, ls, nu, sd.T, sd.Tv, sd.Tr, sg) + sc;
+          if (q < kPass1Slots) {
+            lmax[q][tid] = fmax(lmax[q][tid], lS - lnq[q]);
+          } else if (lS - log(Q[q]) > -INFINITY) {  // rare: more than kPass1Slots temperatures
+            atomicMax(smax + q, dbl_key(lS - log(Q[q])));
+          }
         }
       }
     }
@@ -301,20 +309,18 @@ __global__ __launch_bounds__(256) void k_lines_pass1(ModelDev m, const SlotDev* 
   atomicAdd(&scnt[0], kept);
   atomicAdd(&scnt[1], pairs);
   atomicAdd(&scnt[2], bad);
-  if (m.prec == XS_FP32) {
-    for (int q = 0; q < m.n_slots && q < 8; ++q) {
-      smx[threadIdx.x] = lmax[q];
+  if (f32) {
+    for (int q = 0; q < ns; ++q) {
       __syncthreads();
       for (int s2 = 128; s2 > 0; s2 >>= 1) {
-        if (threadIdx.x < s2) smx[threadIdx.x] = fmax(smx[threadIdx.x], smx[threadIdx.x + s2]);
+        if (tid < s2) lmax[q][tid] = fmax(lmax[q][tid], lmax[q][tid + s2]);
         __syncthreads();
       }
-      if (threadIdx.x == 0 && smx[0] > -INFINITY) atomicMax(smax + q, dbl_key(smx[0]));
-      __syncthreads();
+      if (tid == 0 && lmax[q][0] > -INFINITY) atomicMax(smax + q, dbl_key(lmax[q][0]));
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     atomicAdd(stats + 1, scnt[0]);
     atomicAdd(stats + 2, scnt[1]);
     atomicAdd(stats + 3, scnt[2]);
