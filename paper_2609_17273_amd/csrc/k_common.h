@@ -300,7 +300,7 @@ __device__ __noinline__ double re_w_core(double x, double y) {
 // FP64 Re w(x + iy), y >= 0, relative accuracy ~1e-14 (bands chosen per |z|).
 __device__ __noinline__ double re_w_f64(double x, double y) {
   const double u = x * x, y2 = y * y, rho = u + y2, q = 4.0 * y2;
-  const double cy = 2.0 * y / kPI;
+  const double cy = y * (2.0 / kPI);
   if (rho >= 9.0e6) return cy * gh_re_sum<1>(u, y2, q);
   if (rho >= 6400.0) return cy * gh_re_sum<2>(u, y2, q);
   if (rho >= 400.0) return cy * gh_re_sum<3>(u, y2, q);

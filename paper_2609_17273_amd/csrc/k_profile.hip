@@ -68,7 +68,7 @@ struct Pair {
 template <typename R>
 __device__ __forceinline__ Pair<R> make_pair(double c0, double y, double tau, double W) {
   const double y2 = y * y;
-  const double cw = c0 * (2.0 * y / kPI) * W;
+  const double cw = c0 * (y * (2.0 / kPI)) * W;
   Pair<R> r;
   r.cw = (R)cw;
   r.cwt = (R)(cw * (2.0 * tau));
@@ -162,7 +162,7 @@ struct Poly2 {
 };
 __device__ __forceinline__ Poly2 make_poly2(double c0, double y) {
   const double t1 = GH::t4[0], t2 = GH::t4[1];
-  const double y2 = y * y, k = c0 * (2.0 * y / kPI);
+  const double y2 = y * y, k = c0 * (y * (2.0 / kPI));
   const double cw1 = k * GH::w4[0], cw2 = k * GH::w4[1];
   const double d = t1 - t2, c1 = 4.0 * y2 * t1, q = d * d + 4.0 * y2 * t2;
   const double e1 = 2.0 * t1, e2 = t1 + t2;
@@ -706,7 +706,7 @@ template <int NP>
 __device__ __noinline__ double gh_pairs_y(double c0, double y, double u) {
   const double* tau = gh_tau<NP>();
   const double* W = gh_w<NP>();
-  const double y2 = y * y, cy = c0 * 2.0 * y / kPI;
+  const double y2 = y * y, cy = c0 * (y * (2.0 / kPI));
   double s = 0.0;
 #pragma unroll
   for (int j = 0; j < NP; ++j) {
@@ -1489,8 +1489,14 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
         if constexpr (GN) gauss_rows(e3m, eg);
         else for (int l = e3m; l < eg; ++l) {
           const RecD& rr = srec[l];
-          const double nu = rr.nu, inv = rr.inv;
+          const double nu = rr.nu, inv = rr.inv, c0 = rr.c0, y = rr.y;
           const int klo = uni(rr.klo), khi = uni(rr.khi);
+          // the band ranges of the line, read from LDS once (per-chunk reads
+          // would put an LDS round trip before every band decision)
+          KRange R[5];
+#pragma unroll
+          for (int q = 0; q < 5; ++q) R[q] = KRange{uni(rr.r[q].lo), uni(rr.r[q].hi)};
+          const bool core_all = uni((int)(y >= 1.0e-3 && rr.a <= 1.0)) != 0;
 #pragma unroll
           for (int j = 0; j < M; ++j) {
             const int cl = row_lo + 64 * j, ch = cl + 63;
@@ -1504,35 +1510,36 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
             }
             double v;
             if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) {
-              if (!meets(cl, ch, KRange{uni(rr.r[0].lo), uni(rr.r[0].hi)})) continue;
-              v = rr.c0 * exp2(-(x * x));
+              if (!meets(cl, ch, R[0])) continue;
+              v = c0 * exp2(-(x * x));
             } else if (PROF == XS_LORENTZ) {
-              v = rr.c0 * rcp64(fma(x, x, 1.0));
+              v = c0 * rcp64(fma(x, x, 1.0));
             } else {
               const double u = x * x;
-              if (!meets(cl, ch, KRange{uni(rr.r[0].lo), uni(rr.r[0].hi)})) {
-                v = pair_term<double>(make_pair<double>(rr.c0, rr.y, GH::t2[0], GH::w2[0]), x);
-              } else if (!meets(cl, ch, KRange{uni(rr.r[1].lo), uni(rr.r[1].hi)})) {
+              if (!meets(cl, ch, R[0])) {
+                v = pair_term<double>(make_pair<double>(c0, y, GH::t2[0], GH::w2[0]), x);
+              } else if (!meets(cl, ch, R[1])) {
                 v = poly2_term(rr.B, x);
-              } else if (!meets(cl, ch, KRange{uni(rr.r[2].lo), uni(rr.r[2].hi)})) {
-                v = pair_term<double>(make_pair<double>(rr.c0, rr.y, GH::t6[0], GH::w6[0]), x) +
-                    pair2_term(make_pair<double>(rr.c0, rr.y, GH::t6[1], GH::w6[1]),
-                               make_pair<double>(rr.c0, rr.y, GH::t6[2], GH::w6[2]), x);
-              } else if (!meets(cl, ch, KRange{uni(rr.r[3].lo), uni(rr.r[3].hi)})) {
-                v = gh_pairs_y<4>(rr.c0, rr.y, u);
-              } else if (!meets(cl, ch, KRange{uni(rr.r[4].lo), uni(rr.r[4].hi)})) {
-                v = gh_pairs_y<6>(rr.c0, rr.y, u);
-              } else if (rr.y >= 1.0e-3 && rr.a <= 1.0) {
-                // a chunk that reaches |z|^2 < 64: the rational approximation
-                // on every lane.  Its points have |x| <= 8 + 64 a <= 72, where
-                // it keeps Re w within 4e-12 relative for y >= 1e-3 (its
-                // absolute error, 1.5e-15 of |w|, against Re w >= ~y |w| / |z|),
-                // so the lanes need not split between it and six node pairs.
-                v = rr.c0 * re_w_core<40>(x, rr.y);
-              } else if (u + rr.y * rr.y >= 64.0) {
-                v = gh_pairs_y<6>(rr.c0, rr.y, u);
+              } else if (!meets(cl, ch, R[2])) {
+                v = pair_term<double>(make_pair<double>(c0, y, GH::t6[0], GH::w6[0]), x) +
+                    pair2_term(make_pair<double>(c0, y, GH::t6[1], GH::w6[1]),
+                               make_pair<double>(c0, y, GH::t6[2], GH::w6[2]), x);
+              } else if (!meets(cl, ch, R[3])) {
+                v = gh_pairs_y<4>(c0, y, u);
+              } else if (!meets(cl, ch, R[4])) {
+                v = gh_pairs_y<6>(c0, y, u);
+              } else if (core_all) {
+                // a chunk that reaches |z|^2 < 64 of a line with y >= 1e-3
+                // and a <= 1: the rational approximation on every lane.  Its
+                // points have |x| <= 8 + 64 a <= 72, where it keeps Re w
+                // within 4e-12 relative for y >= 1e-3 (its absolute error,
+                // 1.5e-15 of |w|, against Re w >= ~y |w| / |z|), so the lanes
+                // need not split between it and six node pairs.
+                v = c0 * re_w_core<40>(x, y);
+              } else if (u + y * y >= 64.0) {
+                v = gh_pairs_y<6>(c0, y, u);
               } else {
-                v = rr.c0 * re_w_core<40>(x, rr.y);
+                v = c0 * re_w_core<40>(x, y);
               }
             }
             if (full || (k >= klo && k <= khi)) acc64[j] += v;
