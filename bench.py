@@ -45,10 +45,12 @@ sys.path.insert(0, ROOT)
 #                 = 11; 2 pairs: x 2, per pair s, d, rcp, numerator, product 8,
 #                 sum and accumulate 2 = 20;
 #                 core: Weideman's rational approximation with N = 24 terms in
-#                 FP64 (q and Z 14, 23 complex Horner steps x 7 = 161, Re w 11,
-#                 x, scale and accumulate 4) = 190.
+#                 FP64 (q and Z 14; the degree-23 polynomial by the real
+#                 quadratic-divisor recurrence, 22 steps of 2 FMAs plus setup
+#                 and the final product, 4 N + 1 = 97; Re w 11; x, scale and
+#                 accumulate 4) = 126.
 #   forward FP64: 1 pair 11; 2 pairs (one division) 19; 3/4/6 pairs 30/39/57;
-#                 core N = 40: 14 + 39 x 7 + 11 + 4 = 302.
+#                 core N = 40: 14 + 161 + 11 + 4 = 190.
 #   adjoint FP32: in a wave whose lines all have y^2 at most half the
 #                 region's rho bound (the block-summed form), x 2 and per
 #                 pair s 2, d 2, rcp 1, g/d and g/d^2 2, sums of g/d, g s/d,
@@ -57,16 +59,16 @@ sys.path.insert(0, ROOT)
 #                 rcp 1, e 2, t 6, four sums 8 = 23; 2 pairs: x 2, u 1, per pair
 #                 d, rcp, e, t 12 and their K-weighted sums 8, four
 #                 accumulations 8 = 51; core: w (N = 24, both
-#                 parts: 14 + 161 + 17), w' = -2zw + 2i/sqrt(pi) and Re G 13,
-#                 x, |z|^2 5, three accumulations 6 = 216.
+#                 parts: 14 + 97 + 17), w' = -2zw + 2i/sqrt(pi) and Re G 13,
+#                 x, |z|^2 5, three accumulations 6 = 152.
 #   adjoint FP64: 1/2/3 pairs 15/28/41 (per-point form 23/51/71); 4/6 pairs
 #                 (general form) 113/161;
-#                 core N = 40: 14 + 273 + 17 + 24 = 328.
+#                 core N = 40: 14 + 161 + 17 + 24 = 216.
 FLOP_REGIONS = {
-    ("fwd", "f32"): [(900.0, 11), (64.0, 20), (0.0, 190)],
-    ("fwd", "f64"): [(9.0e6, 11), (6400.0, 19), (400.0, 30), (144.0, 39), (64.0, 57), (0.0, 302)],
-    ("adj", "f32"): [(900.0, 15), (64.0, 28), (0.0, 216)],
-    ("adj", "f64"): [(9.0e6, 15), (6400.0, 28), (400.0, 41), (144.0, 113), (64.0, 161), (0.0, 328)],
+    ("fwd", "f32"): [(900.0, 11), (64.0, 20), (0.0, 126)],
+    ("fwd", "f64"): [(9.0e6, 11), (6400.0, 19), (400.0, 30), (144.0, 39), (64.0, 57), (0.0, 190)],
+    ("adj", "f32"): [(900.0, 15), (64.0, 28), (0.0, 152)],
+    ("adj", "f64"): [(9.0e6, 15), (6400.0, 28), (400.0, 41), (144.0, 113), (64.0, 161), (0.0, 216)],
 }
 # adjoint regions with a block-summed form (the table's figure): the flops of
 # the per-point form used in the other waves
