@@ -194,6 +194,7 @@ struct AdjLine {
   PairD<R> P[3];      // node pairs of the far-region levels (Voigt)
   double ad, bd, y;   // FP64 copies for the general path
   int kc, rlo, rhi;   // home bin; window in r
+  bool share4;        // FP64: one reciprocal may serve four points (wave-uniform)
 };
 
 // Far-region levels of the Voigt adjoint: level l uses the rule with l+1 node
@@ -398,12 +399,59 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
         s4 = fma(gk, E2, s4);
       }
     };
+    // FP64 block-summed one- and two-pair levels: the four points of a step
+    // share one reciprocal (with its Newton step) of the product of their
+    // denominators P_h (d_0, or d_0 d_1): r = 1/(P_0 P_1 P_2 P_3),
+    // 1/P_0 = P_1 (P_2 P_3 r) and so on (the hardware FP64 reciprocal issues
+    // at a quarter of the FMA rate)
+    auto body4 = [&](R rf, auto gsrc, int j) {
+      if constexpr (sizeof(R) == 8 && SY && NP <= 2 && PROF == XS_VOIGT) {
+        R sx[4][NP], d[4][NP], P[4], gk[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const R x = fma(rf, L.a, nbj[h]);
+          gk[h] = gsrc(j + h);
+#pragma unroll
+          for (int q = 0; q < NP; ++q) {
+            sx[h][q] = fma(x, x, hS[q]);
+            d[h][q] = fma(sx[h][q], sx[h][q], cS[q]);
+          }
+          P[h] = NP == 2 ? d[h][0] * d[h][1] : d[h][0];
+        }
+        const R p01 = P[0] * P[1], p23 = P[2] * P[3];
+        const R r = arcp(p01 * p23);
+        const R r01 = p23 * r, r23 = p01 * r;
+        const R iP[4] = {P[1] * r01, P[0] * r01, P[3] * r23, P[2] * r23};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          R rd[NP];
+          if constexpr (NP == 2) {
+            rd[0] = d[h][1] * iP[h];
+            rd[1] = d[h][0] * iP[h];
+          } else {
+            rd[0] = iP[h];
+          }
+#pragma unroll
+          for (int q = 0; q < NP; ++q) {
+            const R grd = gk[h] * rd[q], v = grd * rd[q];
+            B[q][0] += grd;
+            B[q][1] = fma(grd, sx[h][q], B[q][1]);
+            B[q][2] += v;
+            B[q][3] = fma(v, sx[h][q], B[q][3]);
+          }
+        }
+      }
+    };
     auto run = [&](auto gsrc) {
       int j = 0;
-      for (; j + 4 <= n; j += 4) {
-        const R rf = (R)(rb + j);
+      if (sizeof(R) == 8 && SY && NP <= 2 && PROF == XS_VOIGT && L.share4) {
+        for (; j + 4 <= n; j += 4) body4((R)(rb + j), gsrc, j);
+      } else {
+        for (; j + 4 <= n; j += 4) {
+          const R rf = (R)(rb + j);
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) body(fma(rf, L.a, nbj[jj]), gsrc(j + jj));
+          for (int jj = 0; jj < 4; ++jj) body(fma(rf, L.a, nbj[jj]), gsrc(j + jj));
+        }
       }
       for (; j < n; ++j) body(fma((R)(rb + j), L.a, L.nb), gsrc(j));
     };
@@ -529,6 +577,14 @@ __device__ __forceinline__ Sums3 window_sums(bool on, int64_t klo, int64_t khi, 
       const double xmax = fmax(fabs((double)L.rlo * L.ad - L.bd), fabs((double)L.rhi * L.ad - L.bd));
       wide = xmax > 1.0e9 || y > 1.0e9;
     }
+  }
+  // FP64 far levels share one reciprocal among four points when the product
+  // of their denominators (up to eight fourth-degree factors in x^2 + y^2)
+  // stays finite: |x| and y of every line of the wave below 1e9
+  L.share4 = false;
+  if (sizeof(R) == 8 && PROF == XS_VOIGT) {
+    const double xmax = on ? fmax(fabs((double)L.rlo * L.ad - L.bd), fabs((double)L.rhi * L.ad - L.bd)) : 0.0;
+    L.share4 = __ballot(on && !(xmax <= 1.0e9 && y <= 1.0e9)) == 0;
   }
   // uniform runs along r
   const int Rmin = wave_min(L.rlo), Rmax = wave_max(L.rhi);
