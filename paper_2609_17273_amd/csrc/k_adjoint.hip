@@ -39,7 +39,7 @@ __device__ __forceinline__ void gh_adj(R x, R y, R& rew, R& r1, R& rg) {
     const R d = A2 + zi2;
     R id;
     if constexpr (sizeof(R) == 4) id = __builtin_amdgcn_rcpf(d);
-    else id = (R)1 / d;
+    else id = rcp_nr(d);  // hardware reciprocal and one Newton step (3e-15), not a division
     const R id2 = id * id;
     sw += w * (u + y2 + t) * id;
     s1 += w * (A * id + (R)2 * t * (A2 - zi2) * id2);
@@ -66,7 +66,7 @@ __device__ __forceinline__ void prof_grad(R x, R y, double sgm, double gam, int 
     const R q = (R)1 + x * x;
     R iq;
     if constexpr (sizeof(R) == 4) iq = __builtin_amdgcn_rcpf(q);
-    else iq = (R)1 / q;
+    else iq = rcp_nr(q);
     f = iq;
     fs = 0;
     fg = (x * x - (R)1) * iq * iq;

@@ -182,6 +182,13 @@ __device__ __forceinline__ const double* gh_w() {
   else return GH::w12;
 }
 
+// 1/d by the hardware FP64 reciprocal (relative error below 5e-8 on gfx950)
+// and one Newton step (below 3e-15).
+__device__ __forceinline__ double rcp_nr(double d) {
+  const double r = __builtin_amdgcn_rcp(d);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
 // sum_j W_j n_j / d_j with n_j = u + y2 + tau_j, d_j = (u - y2 - tau_j)^2 + q u,
 // q = 4 y^2 (the caller multiplies by 2y/pi).  One node pair, or two pairs in
 // FP64: a single division of the combined fraction.  Otherwise one reciprocal
@@ -206,7 +213,7 @@ __device__ __forceinline__ R gh_re_sum(R u, R y2, R q) {
     if constexpr (sizeof(R) == 4)
       return num * __builtin_amdgcn_rcpf(den);
     else
-      return num / den;
+      return num * rcp_nr(den);
   } else {
     R sum = (R)0;
 #pragma unroll
@@ -216,7 +223,7 @@ __device__ __forceinline__ R gh_re_sum(R u, R y2, R q) {
       const R d = fma(a, a, qu);
       R id;
       if constexpr (sizeof(R) == 4) id = __builtin_amdgcn_rcpf(d);
-      else id = (R)1 / d;
+      else id = rcp_nr(d);
       sum = fma((R)W[j] * (u + p), id, sum);
     }
     return sum;
@@ -242,13 +249,6 @@ struct WM<40> {
   static constexpr double a[40] = XS_WM40_A;
   static constexpr double b[40] = XS_WM40_B;
 };
-
-// 1/d by the hardware FP64 reciprocal (relative error below 5e-8 on gfx950)
-// and one Newton step (below 3e-15).
-__device__ __forceinline__ double rcp_nr(double d) {
-  const double r = __builtin_amdgcn_rcp(d);
-  return fma(r, fma(-d, r, 1.0), r);
-}
 
 // p(Z) = sum_{n<N} c_n Z^n with real c_n at a complex Z: Horner's rule for
 // the real quadratic Z^2 - t Z + m (t = 2 Re Z, m = |Z|^2), which Z solves
