@@ -49,8 +49,10 @@ sys.path.insert(0, ROOT)
 #                 quadratic-divisor recurrence, 22 steps of 2 FMAs plus setup
 #                 and the final product, 4 N + 1 = 97; Re w 11; x, scale and
 #                 accumulate 4) = 126.
-#   forward FP64: 1 pair 11; 2 pairs (one division) 19; 3/4/6 pairs 30/39/57;
-#                 core N = 40: 14 + 161 + 11 + 4 = 190.
+#   forward FP64: 1 pair 11; the three-point rule (one pair and the node at
+#                 0, one division: x 2, s 2, N 4, D 5, division 1,
+#                 accumulate 1) 15; 2 pairs (one division) 19; 3/4/6 pairs
+#                 30/39/57; core N = 40: 14 + 161 + 11 + 4 = 190.
 #   adjoint FP32: in a wave whose lines all have y^2 at most half the
 #                 region's rho bound (the block-summed form), x 2 and per
 #                 pair s 2, d 2, rcp 1, g/d and g/d^2 2, sums of g/d, g s/d,
@@ -66,7 +68,7 @@ sys.path.insert(0, ROOT)
 #                 core N = 40: 14 + 161 + 17 + 24 = 216.
 FLOP_REGIONS = {
     ("fwd", "f32"): [(900.0, 11), (64.0, 20), (0.0, 126)],
-    ("fwd", "f64"): [(9.0e6, 11), (6400.0, 19), (400.0, 30), (144.0, 39), (64.0, 57), (0.0, 190)],
+    ("fwd", "f64"): [(9.0e6, 11), (4.5e4, 15), (4000.0, 19), (400.0, 30), (144.0, 39), (64.0, 57), (0.0, 190)],
     ("adj", "f32"): [(900.0, 15), (64.0, 28), (0.0, 152)],
     ("adj", "f64"): [(9.0e6, 15), (6400.0, 28), (400.0, 41), (144.0, 113), (64.0, 161), (0.0, 216)],
 }

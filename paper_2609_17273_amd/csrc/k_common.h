@@ -147,6 +147,9 @@ struct GH {
   static constexpr double s12[6] = XS_GH12_T;
   static constexpr double t2[1] = XS_GH2_TAU;
   static constexpr double w2[1] = XS_GH2_W;
+  static constexpr double t3[1] = XS_GH3_TAU;  // three points: +-t and 0
+  static constexpr double w3[1] = XS_GH3_W;
+  static constexpr double w3c = XS_GH3_W0;     // weight of the node t = 0
   static constexpr double t4[2] = XS_GH4_TAU;
   static constexpr double w4[2] = XS_GH4_W;
   static constexpr double t6[3] = XS_GH6_TAU;

@@ -114,8 +114,9 @@ __device__ __forceinline__ KRange x_range(double X, double a, double b, int64_t 
 // tile (the same formula under a window mask); 2 = general per-chunk path
 // (the core, the Gaussian's zero chunks, lines evaluated in FP64).
 constexpr int kRowSkip = 0, kRowF1 = 1, kRowGeneral = 2, kRowF2 = 3, kRowF1M = 4, kRowF2M = 5;
-// FP64 form only: third uniform formula (three node pairs), plain and masked.
-constexpr int kRowF3 = 6, kRowF3M = 7;
+// FP64 form only: third uniform formula (three node pairs), plain and masked;
+// the three-point formula of the sampled Voigt between the first and second.
+constexpr int kRowF3 = 6, kRowF3M = 7, kRowF15 = 8, kRowF15M = 9;
 
 // FP32 far-region node pair in shifted form.  With h = y^2 - tau and
 // s = u + h = |z|^2 - tau (positive wherever a node rule is used),
@@ -154,8 +155,8 @@ struct __attribute__((aligned(16))) RecF {
 //   N = cw_1 (s + e_1)(s^2 + 2 d s + q) + cw_2 (s + e_2)(s^2 + c_1),
 //   D = (s^2 + c_1)(s^2 + 2 d s + q),  q = d^2 + c_2,
 // expanded into a cubic and a monic quartic.  Where the rule is used,
-// s >= 6400 - tau_1 and c_j <= 4 tau_j (s + tau_1), so every lower term of
-// either polynomial is below 2e-3 of the leading one: Horner's rule keeps the
+// s >= 4000 - tau_1 and c_j <= 4 tau_j (s + tau_1), so every lower term of
+// either polynomial is below 3e-3 of the leading one: Horner's rule keeps the
 // relative error at a few units of rounding, with one FMA per degree.
 struct Poly2 {
   double h, n3, n2, n1, n0, d3, d2, d1, d0;  // h = y^2 - tau_1
@@ -184,12 +185,46 @@ __device__ __forceinline__ void poly2_nd(const Poly2& B, double x, double& N, do
   D = fma(fma(fma(s + B.d3, s, B.d2), s, B.d1), s, B.d0);
 }
 
-// FP64 form.  r[0..4]: bins with |z|^2 below 9e6, 6400, 400, 144, 64 (the
-// thresholds of the 1, 2, 3, 4 and 6 node-pair bands); for the Gaussian,
-// r[0] holds the bins where 2^{-x^2} is not zero in FP64.  The far-region
-// rows of the Voigt take x = (offset of the point in the row) a + xb.  A line
-// stores the one-pair constants A when its row takes the first formula, else
-// the two-pair fraction B.
+// FP64 three-point rule (nodes 0 and +-t, tau = t^2 = 3/2) as one fraction
+// in s = |z|^2 - tau.  The pair is cw (s + 2 tau)/(s^2 + c), c = 4 y^2 tau,
+// cw = c0 (2 y/pi) W; the node at 0 adds e/(x^2 + y^2) = e/(s + tau) with
+// e = c0 (y/pi) W_0.  Together
+//   N = (cw + e) s^2 + 3 cw tau s + (2 cw tau^2 + e c),
+//   D = (s^2 + c)(s + tau) = s^3 + tau s^2 + c s + c tau:
+// two FMAs for N and an add and two FMAs for D, against three and four for
+// the four-point fraction.  Where it is used, s >= 4.5e4 - tau, so the lower
+// terms are below 1e-4 of the leading ones.
+struct Poly3 {
+  double h, tau, n2, n1, n0, c, ct;  // h = y^2 - tau; ct = c tau
+};
+__device__ __forceinline__ Poly3 make_poly3(double c0, double y) {
+  const double tau = GH::t3[0];
+  const double y2 = y * y, k = c0 * (y * (2.0 / kPI));
+  const double cw = k * GH::w3[0], e = 0.5 * k * GH::w3c, c = 4.0 * y2 * tau;
+  Poly3 C;
+  C.h = y2 - tau;
+  C.tau = tau;
+  C.n2 = cw + e;
+  C.n1 = 3.0 * cw * tau;
+  C.n0 = 2.0 * cw * tau * tau + e * c;
+  C.c = c;
+  C.ct = c * tau;
+  return C;
+}
+__device__ __forceinline__ void poly3_nd(const Poly3& C, double x, double& N, double& D) {
+  const double s = fma(x, x, C.h);
+  N = fma(fma(C.n2, s, C.n1), s, C.n0);
+  D = fma(fma(s + C.tau, s, C.c), s, C.ct);
+}
+
+// FP64 form.  r[0..4]: bins with |z|^2 below 9e6, 4000, 400, 144, 64 (the
+// thresholds of the 1, 2, 3, 4 and 6 node-pair bands of the sampled Voigt;
+// the binned Voigt's second threshold is 6400); for the Gaussian, r[0] holds
+// the bins where 2^{-x^2} is not zero in FP64.  The far-region rows of the
+// Voigt take x = (offset of the point in the row) a + xb.  A line stores the
+// one-pair constants A when its row takes the first formula, the three-point
+// fraction C when the row lies wholly at |z|^2 >= 4.5e4 (sampled Voigt),
+// else the two-pair fraction B.
 struct __attribute__((aligned(16))) RecD {
   double nu, inv, c0, y;
   double a, xb;  // a = dnu / width; xb = x at the row's first point
@@ -199,6 +234,7 @@ struct __attribute__((aligned(16))) RecD {
   union {
     Pair<double> A;
     Poly2 B;
+    Poly3 C;
   };
 };
 
@@ -420,8 +456,12 @@ __device__ int stage_line(const GatherArgs& g, const CondDev& cd, const LineIn<L
         r.A = make_pair<double>(lp.c0, lp.y, GH::t2[0], GH::w2[0]);
         return inside ? kRowF1 : kRowF1M;
       }
+      if (!r.flag && !meets(lo, hi, xr(4.5e4 * 1.001))) {  // three-point row
+        r.C = make_poly3(lp.c0, lp.y);
+        return inside ? kRowF15 : kRowF15M;
+      }
       r.B = make_poly2(lp.c0, lp.y);
-      r.r[1] = xr(6400.0 * 1.001);
+      r.r[1] = xr(4000.0 * 1.001);
       r.r[2] = xr(400.0 * 1.001);
       r.r[3] = xr(144.0 * 1.001);
       r.r[4] = xr(64.0 * 1.001);
@@ -940,18 +980,23 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
         }
       }
       // LDS order: F1 (FP32 Voigt: those taking x from the tile's first
-      // point, then the others) | F1M | F2 | F2M | F3 | F3M (FP64) | general
+      // point, then the others) | F1M | F15 | F15M (FP64 Voigt) | F2 | F2M |
+      // F3 | F3M (FP64) | general
       bool xb_ok = false;
       if constexpr (F32 && PROF == XS_VOIGT) xb_ok = cls == kRowF1 && r.a <= 2.0f;
+      constexpr bool TP = !F32 && PROF == XS_VOIGT;  // three-point rows exist
       const unsigned long long b1x = __ballot(xb_ok);
       const unsigned long long b1 = __ballot(cls == kRowF1 && !xb_ok);
       const unsigned long long b1m = __ballot(cls == kRowF1M);
+      const unsigned long long b15 = TP ? __ballot(cls == kRowF15) : 0ull;
+      const unsigned long long b15m = TP ? __ballot(cls == kRowF15M) : 0ull;
       const unsigned long long b2 = __ballot(cls == kRowF2);
       const unsigned long long b2m = __ballot(cls == kRowF2M);
       const unsigned long long b3 = F32 ? 0ull : __ballot(cls == kRowF3);
       const unsigned long long b3m = F32 ? 0ull : __ballot(cls == kRowF3M);
       const unsigned long long bg = __ballot(cls == kRowGeneral);
-      const int e1x = __popcll(b1x), e1 = e1x + __popcll(b1), e1m = e1 + __popcll(b1m), e2 = e1m + __popcll(b2);
+      const int e1x = __popcll(b1x), e1 = e1x + __popcll(b1), e1m = e1 + __popcll(b1m);
+      const int e15 = e1m + __popcll(b15), e15m = e15 + __popcll(b15m), e2 = e15m + __popcll(b2);
       const int e2m = e2 + __popcll(b2m), e3 = e2m + __popcll(b3), e3m = e3 + __popcll(b3m);
       const int eg = e3m + __popcll(bg);
       if (eg == 0) continue;
@@ -960,7 +1005,9 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
       if (xb_ok) { mine = b1x; base = 0; }
       else if (cls == kRowF1) { mine = b1; base = e1x; }
       else if (cls == kRowF1M) { mine = b1m; base = e1; }
-      else if (cls == kRowF2) { mine = b2; base = e1m; }
+      else if (TP && cls == kRowF15) { mine = b15; base = e1m; }
+      else if (TP && cls == kRowF15M) { mine = b15m; base = e15; }
+      else if (cls == kRowF2) { mine = b2; base = e15m; }
       else if (cls == kRowF2M) { mine = b2m; base = e2; }
       else if (cls == kRowF3) { mine = b3; base = e2m; }
       else if (cls == kRowF3M) { mine = b3m; base = e3; }
@@ -1396,8 +1443,9 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
         // grid point nu_k rounded as the oracle rounds it.  (Stepping x from
         // the row's first point skips that rounding: up to an ulp of nu_k,
         // which moves the values of narrow lines near their core by ~1e-12.)
-        auto uniform = [&](int l0, int l1, auto masked, auto npairs) {
-          constexpr int NP = decltype(npairs)::value;
+        // NN: nodes of the Gauss-Hermite rule of the rows (2, 3, 4 or 6)
+        auto uniform = [&](int l0, int l1, auto masked, auto nodes) {
+          constexpr int NN = decltype(nodes)::value;
           for (int l = l0; l < l1; ++l) {
             const RecD& rr = srec[l];
             const double nu = rr.nu, inv = rr.inv;
@@ -1414,18 +1462,19 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
             }
             Pair<double> C[3];
             KRange R1 = KRange{0x7fffffff, -0x7fffffff};
-            if (PROF == XS_VOIGT && NP == 3) {
+            if (PROF == XS_VOIGT && NN == 6) {
 #pragma unroll
               for (int q = 0; q < 3; ++q) C[q] = make_pair<double>(rr.c0, rr.y, GH::t6[q], GH::w6[q]);
               R1 = KRange{uni(rr.r[1].lo), uni(rr.r[1].hi)};
             }
             double t[M];
-            if (PROF == XS_VOIGT && NP <= 2) {
-              // The far region (one node pair, or two as one fraction N/D),
-              // x from the row's first point: x = (lane + 64 j) a + xb.  (It
-              // differs from (nu_k - nu) inv by the rounding of nu_k, ~1e-10
-              // absolute at most, which moves a value at |x| >= 80 by a
-              // relative 3e-12 at most.)  One reciprocal, with its Newton
+            if (PROF == XS_VOIGT && NN <= 4) {
+              // The far region (one node pair, or the three- or four-point
+              // rule as one fraction N/D), x from the row's first point:
+              // x = (lane + 64 j) a + xb.  (It differs from (nu_k - nu) inv by
+              // the rounding of nu_k, ~1e-10 absolute at most, which moves a
+              // value at |x| >= 63 by a relative 3.2e-12 at most.)  One
+              // reciprocal, with its Newton
               // step, serves the four points j..j+3 of the lane:
               // r = 1/(D_0 D_1 D_2 D_3), 1/D_0 = D_1 (D_2 D_3 r) and so on;
               // the product stays finite for |x|, y <= 1e9 (staging sends
@@ -1437,10 +1486,12 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
 #pragma unroll
                 for (int h = 0; h < 4; ++h) {
                   const double x = fma(lane_d[j + h], a, xb);
-                  if constexpr (NP == 1) {
+                  if constexpr (NN == 2) {
                     const double sv = fma(x, x, rr.A.h);
                     N[h] = fma(rr.A.cw, sv, rr.A.cwt);
                     D[h] = fma(sv, sv, rr.A.c);
+                  } else if constexpr (NN == 3) {
+                    poly3_nd(rr.C, x, N[h], D[h]);
                   } else {
                     poly2_nd(rr.B, x, N[h], D[h]);
                   }
@@ -1459,9 +1510,9 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
                 const double u = xs[j] * xs[j];
                 if (PROF == XS_LORENTZ) t[j] = rr.c0 * rcp64(fma(xs[j], xs[j], 1.0));
                 else if (PROF == XS_DOPPLER || PROF == XS_GAUSSIAN) t[j] = rr.c0 * exp2(-u);
-                else if (NP == 1) t[j] = pair_term<double>(rr.A, xs[j]);
+                else if (NN == 2) t[j] = pair_term<double>(rr.A, xs[j]);
                 else {
-                  // three-pair row: chunks wholly at |z|^2 >= 6400 take two pairs
+                  // three-pair row: chunks wholly at |z|^2 >= 4000 take two pairs
                   const int cl = row_lo + 64 * j;
                   if (!meets(cl, cl + 63, R1)) t[j] = poly2_term(rr.B, xs[j]);
                   else t[j] = pair_term<double>(C[0], xs[j]) + pair2_term(C[1], C[2], xs[j]);
@@ -1475,16 +1526,19 @@ __global__ __launch_bounds__(64, sizeof(Real) == 8 ? 3 : (PROF == XS_BIN_VOIGT ?
             }
           }
         };
-        using P1 = std::integral_constant<int, 1>;
-        using P2 = std::integral_constant<int, 2>;
-        using P3 = std::integral_constant<int, 3>;
-        uniform(0, e1, std::false_type(), P1());
-        uniform(e1, e1m, std::true_type(), P1());
+        using N2 = std::integral_constant<int, 2>;
+        using N3 = std::integral_constant<int, 3>;
+        using N4 = std::integral_constant<int, 4>;
+        using N6 = std::integral_constant<int, 6>;
+        uniform(0, e1, std::false_type(), N2());
+        uniform(e1, e1m, std::true_type(), N2());
         if (PROF == XS_VOIGT) {
-          uniform(e1m, e2, std::false_type(), P2());
-          uniform(e2, e2m, std::true_type(), P2());
-          uniform(e2m, e3, std::false_type(), P3());
-          uniform(e3, e3m, std::true_type(), P3());
+          uniform(e1m, e15, std::false_type(), N3());
+          uniform(e15, e15m, std::true_type(), N3());
+          uniform(e15m, e2, std::false_type(), N4());
+          uniform(e2, e2m, std::true_type(), N4());
+          uniform(e2m, e3, std::false_type(), N6());
+          uniform(e3, e3m, std::true_type(), N6());
         }
         if constexpr (GN) gauss_rows(e3m, eg);
         else for (int l = e3m; l < eg; ++l) {
