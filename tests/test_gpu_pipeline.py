@@ -53,7 +53,13 @@ def test_gather_fp64_bitwise_repeatable_and_scatter_close():
     s = ps.cross_section(ds, dl)
     e, _, _ = rel_err(s[0].cpu().numpy(), a[0].cpu().numpy())
     log(f"[repeat] fp64 gather bitwise repeatable; scatter vs gather {e:.2e}")
-    assert e < 1e-12
+    # The gather's far rows (|z|^2 >= 4000, so |x| >= 63) step x from the
+    # row's first point, the scatter forms (nu_k - nu) inv at every point:
+    # they differ by the rounding of nu_k, at most ~1e-10 absolute in x here,
+    # which moves a value by at most 2 |dx| / |x| <= 3.2e-12 relative; the
+    # node rules of the two paths agree within 2e-13.  Every term is positive,
+    # so the sums differ by at most as much.
+    assert e < 4e-12
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
