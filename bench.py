@@ -63,18 +63,20 @@ sys.path.insert(0, ROOT)
 #                 accumulations 8 = 51; core: w (N = 24, both
 #                 parts: 14 + 97 + 17), w' = -2zw + 2i/sqrt(pi) and Re G 13,
 #                 x, |z|^2 5, three accumulations 6 = 152.
-#   adjoint FP64: 1/2/3 pairs 15/28/41 (per-point form 23/51/71); 4/6 pairs
-#                 (general form) 113/161;
+#   adjoint FP64: 1/2/3 pairs 15/28/41 (per-point form 23/51/71); the
+#                 three-point rule 22 (x 2, its pair 13, the node at 0: v 2,
+#                 rcp 1, g/v 1, sums of g/v and g/v^2 3; per-point form, as
+#                 two pairs, 51); 4/6 pairs (general form) 113/161;
 #                 core N = 40: 14 + 161 + 17 + 24 = 216.
 FLOP_REGIONS = {
     ("fwd", "f32"): [(900.0, 11), (64.0, 20), (0.0, 126)],
     ("fwd", "f64"): [(9.0e6, 11), (4.5e4, 15), (4000.0, 19), (400.0, 30), (144.0, 39), (64.0, 57), (0.0, 190)],
     ("adj", "f32"): [(900.0, 15), (64.0, 28), (0.0, 152)],
-    ("adj", "f64"): [(9.0e6, 15), (6400.0, 28), (400.0, 41), (144.0, 113), (64.0, 161), (0.0, 216)],
+    ("adj", "f64"): [(9.0e6, 15), (4.5e4, 22), (4000.0, 28), (400.0, 41), (144.0, 113), (64.0, 161), (0.0, 216)],
 }
 # adjoint regions with a block-summed form (the table's figure): the flops of
 # the per-point form used in the other waves
-ADJ_POINT_FLOPS = {"f32": [23, 51], "f64": [23, 51, 71]}
+ADJ_POINT_FLOPS = {"f32": [23, 51], "f64": [23, 51, 51, 71]}
 # MI355X vector peaks, no packed-FP32 (the kernels are compiled without packed FP32):
 # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP32
 # and FP64 alike.  The published 157.3 TFLOP/s FP32 figure needs packed math.

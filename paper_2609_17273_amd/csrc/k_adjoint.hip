@@ -197,9 +197,12 @@ struct AdjLine {
   bool share4;        // FP64: one reciprocal may serve four points (wave-uniform)
 };
 
-// Far-region levels of the Voigt adjoint: level l uses the rule with l+1 node
-// pairs where rho = x^2 + y^2 >= kLev[l]; inside the last level the general
-// per-lane path picks more pairs or the rational approximation.
+// Far-region levels of the Voigt adjoint, where rho = x^2 + y^2 >= rho[l];
+// inside the last level the general per-lane path picks more pairs or the
+// rational approximation.  FP32: one and two node pairs.  FP64: one pair, the
+// three-point rule (one pair and the node at 0), two pairs, three pairs.  The
+// node at 0 with weight W_0 is the pair formula with tau = 0 and weight
+// W_0 / 2 (then d = (u + y^2)^2, e = 1/(u + y^2), t = -u/d).
 template <typename R>
 struct Levels;
 template <>
@@ -209,8 +212,8 @@ struct Levels<float> {
 };
 template <>
 struct Levels<double> {
-  static constexpr int n = 3;
-  static constexpr double rho[3] = {9.0e6, 6400.0, 400.0};
+  static constexpr int n = 4;
+  static constexpr double rho[4] = {9.0e6, 4.5e4, 4000.0, 400.0};
 };
 
 // Voigt values for the general path, out of line (rational core and up to six
@@ -302,15 +305,19 @@ struct GSrc {
 //   sum g (u/d)[4 tau (p - u)/d - 1]
 //             = 4 tau [-(S0 - c S2) + (2 y^2 + h) S3 - 2 y^2 h S2] - (S1 - h S0),
 // formed once per block in FP64 and weighted by K; a point costs, per pair,
-// s, d, 1/d, g/d, g/d^2 and four sums.  The only difference of like terms is
+// s, d, 1/d, g/d, g/d^2 and four sums.  C0: the second pair is the node at 0
+// (tau = 0: h = y^2, c = m = 0, s = u + y^2 = v and d = v^2), for which only
+// S0 = sum g/v^2 and S1 = sum g/v enter: a point costs v, 1/v, g/v and two
+// sums.  The only difference of like terms is
 // S1 - h S0 = sum g u/d: in a level's region (rho >= R) y^2 <= R/2 gives
 // u = rho - y^2 >= R/2 >= h, so it loses at most a factor 2.  Per point the
 // other combinations are sums of positive terms (bar -c/d^2, with c/d below
 // 0.09 for every level) or enter scaled by 4 tau/d against it.  For larger y
 // (u may reach 0) the per-point form is kept.
-template <typename R, int PROF, int NP, bool SY = false>
+template <typename R, int PROF, int NP, bool SY = false, bool C0 = false>
 __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G, int r0, int r1,
                                            double& sA, double& sB, double& sC) {
+  static_assert(!C0 || (SY && NP == 2 && sizeof(R) == 8), "the node at 0 has its own form in FP64 block sums");
   // the lanes running this loop (the wave's active lines) share the refills
   const unsigned long long act = __ballot(1);
   const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(act >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)act, 0u));
@@ -355,7 +362,8 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
         if constexpr (sizeof(R) == 8 && NP >= 2) {
           // FP64: one reciprocal (and Newton step) for the first two pairs,
           // 1/d0 = d1/(d0 d1) and 1/d1 = d0/(d0 d1); d0 d1 stays finite
-          const R d0 = fma(sx[0], sx[0], cS[0]), d1 = fma(sx[1], sx[1], cS[1]);
+          // (C0: rd[1] = 1/v, v = sx[1])
+          const R d0 = fma(sx[0], sx[0], cS[0]), d1 = C0 ? sx[1] : fma(sx[1], sx[1], cS[1]);
           const R r = arcp(d0 * d1);
           rd[0] = d1 * r;
           rd[1] = d0 * r;
@@ -365,12 +373,17 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
           for (int q = 0; q < NP; ++q) rd[q] = arcp(fma(sx[q], sx[q], cS[q]));
         }
 #pragma unroll
-        for (int q = 0; q < NP; ++q) {
+        for (int q = 0; q < (C0 ? 1 : NP); ++q) {
           const R grd = gk * rd[q], v = grd * rd[q];
           B[q][0] += grd;
           B[q][1] = fma(grd, sx[q], B[q][1]);
           B[q][2] += v;
           B[q][3] = fma(v, sx[q], B[q][3]);
+        }
+        if constexpr (C0) {
+          const R gv = gk * rd[1];
+          B[1][0] = fma(gv, rd[1], B[1][0]);
+          B[1][1] += gv;
         }
       } else if constexpr (NP == 1) {
         // s1 = sum g e, s2 = sum g t, s3 = sum g / d, s4 = sum g e^2
@@ -399,11 +412,11 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
         s4 = fma(gk, E2, s4);
       }
     };
-    // FP64 block-summed one- and two-pair levels: the four points of a step
-    // share one reciprocal (with its Newton step) of the product of their
-    // denominators P_h (d_0, or d_0 d_1): r = 1/(P_0 P_1 P_2 P_3),
-    // 1/P_0 = P_1 (P_2 P_3 r) and so on (the hardware FP64 reciprocal issues
-    // at a quarter of the FMA rate)
+    // FP64 block-summed one-pair, three-point and two-pair levels: the four
+    // points of a step share one reciprocal (with its Newton step) of the
+    // product of their denominators P_h (d_0, d_0 v or d_0 d_1):
+    // r = 1/(P_0 P_1 P_2 P_3), 1/P_0 = P_1 (P_2 P_3 r) and so on (the
+    // hardware FP64 reciprocal issues at a quarter of the FMA rate)
     auto body4 = [&](R rf, auto gsrc, int j) {
       if constexpr (sizeof(R) == 8 && SY && NP <= 2 && PROF == XS_VOIGT) {
         R sx[4][NP], d[4][NP], P[4], gk[4];
@@ -414,7 +427,7 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
 #pragma unroll
           for (int q = 0; q < NP; ++q) {
             sx[h][q] = fma(x, x, hS[q]);
-            d[h][q] = fma(sx[h][q], sx[h][q], cS[q]);
+            d[h][q] = (C0 && q == 1) ? sx[h][q] : fma(sx[h][q], sx[h][q], cS[q]);
           }
           P[h] = NP == 2 ? d[h][0] * d[h][1] : d[h][0];
         }
@@ -432,12 +445,17 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
             rd[0] = iP[h];
           }
 #pragma unroll
-          for (int q = 0; q < NP; ++q) {
+          for (int q = 0; q < (C0 ? 1 : NP); ++q) {
             const R grd = gk[h] * rd[q], v = grd * rd[q];
             B[q][0] += grd;
             B[q][1] = fma(grd, sx[h][q], B[q][1]);
             B[q][2] += v;
             B[q][3] = fma(v, sx[h][q], B[q][3]);
+          }
+          if constexpr (C0) {
+            const R gv = gk[h] * rd[1];
+            B[1][0] = fma(gv, rd[1], B[1][0]);
+            B[1][1] += gv;
           }
         }
       }
@@ -510,17 +528,21 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
   }
 }
 
+// Level l of Levels<R> (the caller has put the level's pairs in L.P; the
+// node at 0 of the FP64 three-point level is L.P[1]).
 template <typename R, int PROF>
 __device__ __forceinline__ void fast_level(int level, const AdjLine<R>& L, const GSrc<R>& G, int r0, int r1,
                                            double& sA, double& sB, double& sC, bool blocksum = false) {
   if (PROF == XS_VOIGT && blocksum) {
     if (level == 0) fast_range<R, PROF, 1, true>(L, G, r0, r1, sA, sB, sC);
-    else if (level == 1) fast_range<R, PROF, 2, true>(L, G, r0, r1, sA, sB, sC);
-    else if constexpr (sizeof(R) == 8) fast_range<R, PROF, 3, true>(L, G, r0, r1, sA, sB, sC);
+    else if constexpr (sizeof(R) == 4) fast_range<R, PROF, 2, true>(L, G, r0, r1, sA, sB, sC);
+    else if (level == 1) fast_range<R, PROF, 2, true, true>(L, G, r0, r1, sA, sB, sC);
+    else if (level == 2) fast_range<R, PROF, 2, true>(L, G, r0, r1, sA, sB, sC);
+    else fast_range<R, PROF, 3, true>(L, G, r0, r1, sA, sB, sC);
     return;
   }
   if (PROF != XS_VOIGT || level == 0) fast_range<R, PROF, 1>(L, G, r0, r1, sA, sB, sC);
-  else if (level == 1) fast_range<R, PROF, 2>(L, G, r0, r1, sA, sB, sC);
+  else if (sizeof(R) == 4 || level <= 2) fast_range<R, PROF, 2>(L, G, r0, r1, sA, sB, sC);
   else if constexpr (sizeof(R) == 8) fast_range<R, PROF, 3>(L, G, r0, r1, sA, sB, sC);
 }
 
@@ -570,8 +592,9 @@ __device__ __forceinline__ Sums3 window_sums(bool on, int64_t klo, int64_t khi, 
     L.P[1] = pair_d<R>(y, GH::t4[0], GH::w4[0]);
     L.P[2] = pair_d<R>(y, GH::t4[1], GH::w4[1]);
     if (sizeof(R) == 8) {
-      // FP64 levels: 1, 2 and 3 node pairs; pairs of the 3-pair rule are
-      // set when that level is entered.
+      // FP64 levels: one pair, the three-point rule, two and three pairs;
+      // the pairs of the three-point and three-pair rules are set when those
+      // levels are entered.
     }
     if (sizeof(R) == 4 && on) {
       const double xmax = fmax(fabs((double)L.rlo * L.ad - L.bd), fabs((double)L.rhi * L.ad - L.bd));
@@ -651,20 +674,27 @@ __device__ __forceinline__ Sums3 window_sums(bool on, int64_t klo, int64_t khi, 
         }
       }
       if (mode >= 0) {
-        if (PROF == XS_VOIGT && sizeof(R) == 8 && mode == 2) {
+        // the level of the two-pair rule
+        constexpr int l2 = sizeof(R) == 8 ? 2 : 1;
+        if (PROF == XS_VOIGT && sizeof(R) == 8 && mode == 3) {
           AdjLine<R> L3 = L;
           L3.P[0] = pair_d<R>(y, GH::t6[0], GH::w6[0]);
           L3.P[1] = pair_d<R>(y, GH::t6[1], GH::w6[1]);
           L3.P[2] = pair_d<R>(y, GH::t6[2], GH::w6[2]);
-          fast_level<R, PROF>(2, L3, G, r, end, sA, sB, sC, (blk >> 2) & 1);
+          fast_level<R, PROF>(3, L3, G, r, end, sA, sB, sC, (blk >> 3) & 1);
+        } else if (PROF == XS_VOIGT && sizeof(R) == 8 && mode == 1) {
+          AdjLine<R> L15 = L;
+          L15.P[0] = pair_d<R>(y, GH::t3[0], GH::w3[0]);
+          L15.P[1] = pair_d<R>(y, 0.0, 0.5 * GH::w3c);
+          fast_level<R, PROF>(1, L15, G, r, end, sA, sB, sC, (blk >> 1) & 1);
         } else if (PROF == XS_VOIGT && mode == 0) {
           AdjLine<R> L1 = L;
           fast_level<R, PROF>(0, L1, G, r, end, sA, sB, sC, blk & 1);
-        } else if (PROF == XS_VOIGT && mode == 1) {
+        } else if (PROF == XS_VOIGT && mode == l2) {
           AdjLine<R> L2 = L;
           L2.P[0] = L.P[1];
           L2.P[1] = L.P[2];
-          fast_level<R, PROF>(1, L2, G, r, end, sA, sB, sC, (blk >> 1) & 1);
+          fast_level<R, PROF>(l2, L2, G, r, end, sA, sB, sC, (blk >> l2) & 1);
         } else {
           fast_level<R, PROF>(0, L, G, r, end, sA, sB, sC);
         }
