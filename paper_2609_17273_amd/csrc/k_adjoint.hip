@@ -588,14 +588,7 @@ __device__ __forceinline__ Sums3 window_sums(bool on, int64_t klo, int64_t khi, 
   L.nb = (R)(-L.bd);
   bool wide = false;
   if (PROF == XS_VOIGT) {
-    L.P[0] = pair_d<R>(y, GH::t2[0], GH::w2[0]);
-    L.P[1] = pair_d<R>(y, GH::t4[0], GH::w4[0]);
-    L.P[2] = pair_d<R>(y, GH::t4[1], GH::w4[1]);
-    if (sizeof(R) == 8) {
-      // FP64 levels: one pair, the three-point rule, two and three pairs;
-      // the pairs of the three-point and three-pair rules are set when those
-      // levels are entered.
-    }
+    // the node pairs of a far level are set in L.P when a run of it starts
     if (sizeof(R) == 4 && on) {
       const double xmax = fmax(fabs((double)L.rlo * L.ad - L.bd), fabs((double)L.rhi * L.ad - L.bd));
       wide = xmax > 1.0e9 || y > 1.0e9;
@@ -674,27 +667,24 @@ __device__ __forceinline__ Sums3 window_sums(bool on, int64_t klo, int64_t khi, 
         }
       }
       if (mode >= 0) {
-        // the level of the two-pair rule
-        constexpr int l2 = sizeof(R) == 8 ? 2 : 1;
-        if (PROF == XS_VOIGT && sizeof(R) == 8 && mode == 3) {
-          AdjLine<R> L3 = L;
-          L3.P[0] = pair_d<R>(y, GH::t6[0], GH::w6[0]);
-          L3.P[1] = pair_d<R>(y, GH::t6[1], GH::w6[1]);
-          L3.P[2] = pair_d<R>(y, GH::t6[2], GH::w6[2]);
-          fast_level<R, PROF>(3, L3, G, r, end, sA, sB, sC, (blk >> 3) & 1);
-        } else if (PROF == XS_VOIGT && sizeof(R) == 8 && mode == 1) {
-          AdjLine<R> L15 = L;
-          L15.P[0] = pair_d<R>(y, GH::t3[0], GH::w3[0]);
-          L15.P[1] = pair_d<R>(y, 0.0, 0.5 * GH::w3c);
-          fast_level<R, PROF>(1, L15, G, r, end, sA, sB, sC, (blk >> 1) & 1);
-        } else if (PROF == XS_VOIGT && mode == 0) {
-          AdjLine<R> L1 = L;
-          fast_level<R, PROF>(0, L1, G, r, end, sA, sB, sC, blk & 1);
-        } else if (PROF == XS_VOIGT && mode == l2) {
-          AdjLine<R> L2 = L;
-          L2.P[0] = L.P[1];
-          L2.P[1] = L.P[2];
-          fast_level<R, PROF>(l2, L2, G, r, end, sA, sB, sC, (blk >> l2) & 1);
+        if (PROF == XS_VOIGT) {
+          // the level's node pairs (FP64: one pair, the three-point rule,
+          // two pairs, three pairs; FP32: one pair, two pairs)
+          const bool two = sizeof(R) == 8 ? mode == 2 : mode == 1;
+          if (mode == 0) {
+            L.P[0] = pair_d<R>(y, GH::t2[0], GH::w2[0]);
+          } else if (two) {
+            L.P[0] = pair_d<R>(y, GH::t4[0], GH::w4[0]);
+            L.P[1] = pair_d<R>(y, GH::t4[1], GH::w4[1]);
+          } else if (mode == 1) {
+            L.P[0] = pair_d<R>(y, GH::t3[0], GH::w3[0]);
+            L.P[1] = pair_d<R>(y, 0.0, 0.5 * GH::w3c);
+          } else {
+            L.P[0] = pair_d<R>(y, GH::t6[0], GH::w6[0]);
+            L.P[1] = pair_d<R>(y, GH::t6[1], GH::w6[1]);
+            L.P[2] = pair_d<R>(y, GH::t6[2], GH::w6[2]);
+          }
+          fast_level<R, PROF>(mode, L, G, r, end, sA, sB, sC, (blk >> mode) & 1);
         } else {
           fast_level<R, PROF>(0, L, G, r, end, sA, sB, sC);
         }
