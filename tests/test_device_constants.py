@@ -157,3 +157,42 @@ def test_three_point_fraction_matches_rule_and_wofz():
     ex = wofz(Z).real
     keep = ex > 1e-300
     assert np.max(np.abs(frac[keep] - ex[keep]) / ex[keep]) < 1e-13
+
+
+def poly2_re(x, y):
+    """The four-point rule as the gather's FP64 fraction N(s)/D(s) in
+    s = |z|^2 - tau_1, coefficients formed as make_poly2 forms them (c0 = 1)."""
+    t1, t2 = D["XS_GH4_TAU"]
+    w1, w2 = D["XS_GH4_W"]
+    y2 = y * y
+    k = y * (2.0 / np.pi)
+    cw1, cw2 = k * w1, k * w2
+    d, c1 = t1 - t2, 4.0 * y2 * t1
+    q = d * d + 4.0 * y2 * t2
+    e1, e2 = 2.0 * t1, t1 + t2
+    n3, n2 = cw1 + cw2, cw1 * (2.0 * d + e1) + cw2 * e2
+    n1, n0 = cw1 * (q + 2.0 * d * e1) + cw2 * c1, cw1 * e1 * q + cw2 * e2 * c1
+    d3, d2, d1, d0 = 2.0 * d, q + c1, 2.0 * d * c1, c1 * q
+    s = x * x + (y2 - t1)
+    N = ((n3 * s + n2) * s + n1) * s + n0
+    Dn = (((s + d3) * s + d2) * s + d1) * s + d0
+    return N, Dn
+
+
+def test_two_pair_fraction_matches_rule_and_wofz():
+    """The gather's two-pair fraction (rows wholly at |z|^2 >= 4000) against
+    the four-point rule summed term by term and against Re w, on and beyond
+    the band edge for every direction of z, including y near 0 and y large."""
+    th = np.linspace(0.0, np.pi / 2, 721)
+    Z = np.concatenate([sc * np.sqrt(4000.0) * (np.cos(th) + 1j * np.sin(th))
+                        for sc in (1.0, 1.01, 1.1, 2.0, 10.0, 100.0, 1e3)])
+    Z = np.concatenate([Z, np.array([complex(x, y) for x in (63.3, 1e3, 1e5, 1e8)
+                                     for y in (1e-12, 1e-6, 1e-3, 1.0, 1e3, 1e6)])])
+    N, Dn = poly2_re(Z.real, Z.imag)
+    frac = N / Dn
+    ref = gh_re(4, Z.real, Z.imag)
+    keep = ref > 0
+    assert np.max(np.abs(frac[keep] - ref[keep]) / ref[keep]) < 2e-15
+    ex = wofz(Z).real
+    keep = ex > 1e-300
+    assert np.max(np.abs(frac[keep] - ex[keep]) / ex[keep]) < 1e-13
