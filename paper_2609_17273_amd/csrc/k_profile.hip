@@ -238,6 +238,11 @@ struct __attribute__((aligned(16))) RecD {
   };
 };
 
+// The kernels tell the two record types apart by size, and a wave's LDS
+// holds 64 records (12 KB of FP64 records, three waves per SIMD).
+static_assert(sizeof(RecF) != sizeof(RecD), "record types are told apart by size");
+static_assert(sizeof(RecD) == 192, "FP64 record: 64 per wave in 12 KB of LDS");
+
 // the staging precision of a record type
 template <typename Rec>
 using LReal = typename std::conditional<sizeof(Rec) == sizeof(RecF), float, double>::type;
