@@ -181,6 +181,29 @@ def traffic_from_profiles(kernel_key: str):
     return e.get("hbm_bytes_per_launch")
 
 
+def valu_from_profiles(kernel_key: str, ms: float, sclk_mhz):
+    """VALU issue of a kernel from the committed rocprofv3 SQ counters, if
+    they were taken on the current kernel sources (else None): wave64 VALU
+    instructions per launch, lane instructions per evaluation, and the share
+    of the SIMDs' issue cycles they fill over the measured launch time at the
+    measured shader clock, at one wave64 VALU instruction per 16-lane SIMD
+    per 4 cycles (transcendentals counted as one instruction).  A share near
+    1 means the kernel keeps the VALU saturated."""
+    path = os.path.join(ROOT, "profiles", "pmc_valu.json")
+    if not os.path.exists(path) or not sclk_mhz:
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    e = d.get(kernel_key)
+    if not e or e.get("source_hash") != source_hash():
+        return None
+    n = e["SQ_INSTS_VALU"]
+    cycles = 256 * 4 * sclk_mhz * 1e6 * (ms / 1e3)
+    return {"wave_instructions": n, "per_eval": round(n * 64 / e["evals"], 3),
+            "transcendental_per_eval": round(e["SQ_INSTS_VALU_TRANS"] * 64 / e["evals"], 3),
+            "issue_frac": round(4.0 * n / cycles, 4), "sclk_MHz": round(sclk_mhz, 1)}
+
+
 def run_step(plan, ds, dl, sig, w, target, ev):
     import torch
     ev[0].record()
@@ -797,6 +820,7 @@ def main():
         fpe = flops_per_eval(fracs, (kind, "f32"), shares["f32"])
         key = "gather_voigt1e7_f32" if kind == "fwd" else "adjoint_voigt1e7_f32"
         extra = {"traffic": traffic_from_profiles(key),
+                 "valu": valu_from_profiles(key, ms, ps32.summary().get("sclk_MHz_mean")),
                  "region_fractions": [round(f, 5) for f in fracs[(kind, "f32")]],
                  "peak_note": "78.6 TFLOP/s: FP32 FMA without packed math (256 CU x 4 SIMD x 16 lanes x 2 x "
                               "2.4 GHz), the rate this code can issue; the published 157.3 needs packed FP32"}
@@ -813,15 +837,17 @@ def main():
         p64 = plan_for(X.XS_FP64)
         cfg64 = p64.autotune(ds, dl, sig, cache_path=os.path.join("/tmp", "xsec_autotune.json"))
         log(f"autotuned fp64: {cfg64}")
-        ms64, per64, dist64 = time_steps(p64, ds, dl, sig, w, target, max(3, args.steps // 2), 2)
+        with PowerSampler() as ps64:
+            ms64, per64, dist64 = time_steps(p64, ds, dl, sig, w, target, max(3, args.steps // 2), 2)
         log(f"fp64 step {ms64:.2f} ms {per64}")
         rl64 = {}
         for kind, ms in (("fwd", per64["forward"]), ("adj", per64["adjoint"])):
             fpe = flops_per_eval(fracs, (kind, "f64"), shares["f64"])
+            key = "gather_voigt1e7_f64" if kind == "fwd" else "adjoint_voigt1e7_f64"
             rl64[kind] = alu_roofline(fpe, pairs, ms, "f64",
                                       "k_gather<double,Voigt>" if kind == "fwd" else "k_adjoint<double,Voigt>",
-                                      traffic=traffic_from_profiles("gather_voigt1e7_f64" if kind == "fwd"
-                                                                    else "adjoint_voigt1e7_f64"),
+                                      traffic=traffic_from_profiles(key),
+                                      valu=valu_from_profiles(key, ms, ps64.summary().get("sclk_MHz_mean")),
                                       region_fractions=[round(f, 5) for f in fracs[(kind, "f64")]])
         extras["fp64"] = {"ms_per_step": round(ms64, 3), "kernel_config": cfg64,
                           "stage_ms": {k: round(v, 3) for k, v in per64.items()},

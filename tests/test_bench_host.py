@@ -1,5 +1,6 @@
 """Host-side logic of bench.py (no GPU): the one-GPU refusal, the Voigt region
-fractions behind the flop counts, and the traffic figures' source check."""
+fractions behind the flop counts, and the traffic and VALU figures' source
+check."""
 import json
 import os
 import subprocess
@@ -69,6 +70,26 @@ def test_traffic_only_for_the_current_sources():
             assert got == d[key]["hbm_bytes_per_launch"] and got > 0
         else:
             assert got is None
+
+
+def test_valu_issue_only_for_the_current_sources():
+    """The VALU issue figures: None when the counters were taken on other
+    sources; otherwise wave instructions x 4 cycles over 1024 SIMDs x clock x
+    time, and lane instructions per evaluation."""
+    path = os.path.join(ROOT, "profiles", "pmc_valu.json")
+    with open(path) as f:
+        d = json.load(f)
+    for key in ("gather_voigt1e7_f32", "adjoint_voigt1e7_f64"):
+        got = bench.valu_from_profiles(key, 10.0, 2400.0)
+        e = d[key]
+        if e["source_hash"] != bench.source_hash():
+            assert got is None
+            continue
+        n = e["SQ_INSTS_VALU"]
+        assert got["wave_instructions"] == n
+        assert abs(got["issue_frac"] - 4.0 * n / (1024 * 2.4e9 * 0.010)) < 1e-4
+        assert abs(got["per_eval"] - n * 64 / e["evals"]) < 1e-3
+    assert bench.valu_from_profiles("gather_voigt1e7_f32", 10.0, None) is None
 
 
 def test_adjoint_block_share_limits():
