@@ -181,16 +181,18 @@ def traffic_from_profiles(kernel_key: str):
     return e.get("hbm_bytes_per_launch")
 
 
-def valu_from_profiles(kernel_key: str, ms: float, sclk_mhz):
+def valu_from_profiles(kernel_key: str, ms: float, sclk_mhz=None):
     """VALU issue of a kernel from the committed rocprofv3 SQ counters, if
     they were taken on the current kernel sources (else None): wave64 VALU
-    instructions per launch, lane instructions per evaluation, and the share
-    of the SIMDs' issue cycles they fill over the measured launch time at the
-    measured shader clock, at one wave64 VALU instruction per 16-lane SIMD
-    per 4 cycles (transcendentals counted as one instruction).  A share near
-    1 means the kernel keeps the VALU saturated."""
+    instructions per launch, lane instructions per evaluation, and their
+    share of the peak issue rate over the measured launch time: one wave64
+    VALU instruction per 16-lane SIMD per 4 cycles at 2.4 GHz, the clock of
+    the 78.6 TFLOP/s peak (transcendentals counted as one instruction).  A
+    share near 1 means the kernel keeps the VALU saturated.  The shader clock
+    sampled from sysfs during the timed steps (the DPM level) is reported
+    beside it, not used: against it the FP32 adjoint's share would exceed 1."""
     path = os.path.join(ROOT, "profiles", "pmc_valu.json")
-    if not os.path.exists(path) or not sclk_mhz:
+    if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
@@ -198,10 +200,11 @@ def valu_from_profiles(kernel_key: str, ms: float, sclk_mhz):
     if not e or e.get("source_hash") != source_hash():
         return None
     n = e["SQ_INSTS_VALU"]
-    cycles = 256 * 4 * sclk_mhz * 1e6 * (ms / 1e3)
+    cycles = 256 * 4 * 2.4e9 * (ms / 1e3)
     return {"wave_instructions": n, "per_eval": round(n * 64 / e["evals"], 3),
             "transcendental_per_eval": round(e["SQ_INSTS_VALU_TRANS"] * 64 / e["evals"], 3),
-            "issue_frac": round(4.0 * n / cycles, 4), "sclk_MHz": round(sclk_mhz, 1)}
+            "issue_frac": round(4.0 * n / cycles, 4),
+            "sclk_MHz_sampled": round(sclk_mhz, 1) if sclk_mhz else None}
 
 
 def run_step(plan, ds, dl, sig, w, target, ev):
