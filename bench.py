@@ -82,7 +82,8 @@ ADJ_POINT_FLOPS = {"f32": [23, 51], "f64": [23, 51, 51, 71]}
 # and FP64 alike.  The published 157.3 TFLOP/s FP32 figure needs packed math.
 PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
 KERNEL_SOURCES = ["paper_2609_17273_amd/csrc/k_profile.hip", "paper_2609_17273_amd/csrc/k_adjoint.hip",
-                  "paper_2609_17273_amd/csrc/k_common.h", "paper_2609_17273_amd/csrc/k_lines.hip"]
+                  "paper_2609_17273_amd/csrc/k_common.h", "paper_2609_17273_amd/csrc/k_lines.hip",
+                  "paper_2609_17273_amd/csrc/xsec_internal.h"]
 
 
 def region_fractions(wl, lines, cond):

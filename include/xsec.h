@@ -168,7 +168,7 @@ typedef struct {
  * A work item is one (tile, condition) and a slice of at most chunk_lines of
  * the tile's candidate lines; a tile split over several items is summed from
  * their partial rows in item order, so results do not depend on scheduling.
- * chunk_lines: 0 = automatic (about 64 items per compute unit when the
+ * chunk_lines: 0 = automatic (about 256 items per compute unit when the
  * tiles alone are too few), else a multiple of 64 (the automatic size wins
  * when it is larger).  bucket_bins: grid points per line bucket (power of two,
  * 64..4096; a new plan starts at 64 for the Doppler and fixed-width Gaussian,

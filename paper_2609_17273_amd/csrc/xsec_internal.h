@@ -24,7 +24,7 @@ constexpr int base_profile(int profile) {
   return profile < 4 ? profile : (profile < 8 ? profile - 4 : 3);
 }
 constexpr int kQBlocks = 256;     // partial sums per slot in the partition-function reduction
-constexpr int kItemsPerCU = 64;   // gather work items aimed at per compute unit when tiles are split
+constexpr int kItemsPerCU = 256;  // gather work items aimed at per compute unit when tiles are split
 constexpr int kAdjBlocks = 2048;     // persistent blocks of the adjoint in a new plan
 constexpr int kAdjBlocksMax = 8192;  // the most the configuration allows (sizes the partial sums)
 constexpr int kSortItems = 16;    // keys per thread in the radix sort (4096 per block)
