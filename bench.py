@@ -189,9 +189,11 @@ def valu_from_profiles(kernel_key: str, ms: float, sclk_mhz=None):
     share of the peak issue rate over the measured launch time: one wave64
     VALU instruction per 16-lane SIMD per 4 cycles at 2.4 GHz, the clock of
     the 78.6 TFLOP/s peak (transcendentals counted as one instruction).  A
-    share near 1 means the kernel keeps the VALU saturated.  The shader clock
-    sampled from sysfs during the timed steps (the DPM level) is reported
-    beside it, not used: against it the FP32 adjoint's share would exceed 1."""
+    share near 1 means the kernel keeps the VALU saturated; the FP32
+    adjoint reads 0.98-1.00, so some of its instructions (adds, products,
+    moves) take fewer than 4 cycles, and the share can come out slightly
+    above 1.  The shader clock sampled from sysfs during the timed steps (the
+    DPM level) is reported beside it, not used."""
     path = os.path.join(ROOT, "profiles", "pmc_valu.json")
     if not os.path.exists(path):
         return None
