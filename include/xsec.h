@@ -175,9 +175,10 @@ typedef struct {
  * 256 otherwise); persistent: 1 = one persistent launch pulling items from a
  * device queue, 0 = one workgroup per item; waves_per_cu: size of the
  * persistent grid in waves per compute unit (4..64); adj_blocks: blocks of
- * 256 threads of the adjoint's persistent grid (0 = 2048, else a multiple of
- * 256 in 256..8192; its per-block partial sums of dL/dT, dL/dP are added in
- * block order, so each value is deterministic). */
+ * 256 threads of the adjoint's grid, each wave taking every (4 adj_blocks)-th
+ * batch of 64 sorted lines (0 = 16384, else a multiple of 256 in
+ * 256..32768; its per-block partial sums of dL/dT, dL/dP are added in block
+ * order, so each value is deterministic). */
 typedef struct {
   int32_t tile_bins;
   int32_t bucket_bins;

@@ -163,7 +163,7 @@ int validate_config(const xs_config* c) {
   if (c->persistent != 0 && c->persistent != 1) return fail(XS_EINVAL, "config.persistent must be 0 or 1");
   if (c->waves_per_cu < 4 || c->waves_per_cu > 64) return fail(XS_EINVAL, "config.waves_per_cu must be in [4, 64]");
   if (c->adj_blocks != 0 && (c->adj_blocks < 256 || c->adj_blocks > kAdjBlocksMax || c->adj_blocks % 256))
-    return fail(XS_EINVAL, "config.adj_blocks must be 0 or a multiple of 256 in [256, 8192]");
+    return fail(XS_EINVAL, "config.adj_blocks must be 0 or a multiple of 256 in [256, 32768]");
   return XS_OK;
 }
 
@@ -933,11 +933,11 @@ int xs_plan_autotune(xs_plan* p, const xs_states* st, const xs_lines* ln, double
   double adj_ms = 0.0;
   if (!rc && p->model.population == XS_LTE && p->model.profile < XS_BIN_DOPPLER) {
     if ((rc = xs_plan_set_config(p, &best)) == XS_OK && !p->prepared) rc = preprocess(p, st, ln);
-    const int cand[3] = {1024, 2048, 4096};
+    const int cand[4] = {4096, 8192, 16384, 32768};
     double* outs = (double*)p->w.lpack;  // 64 B per line: room for three gradients
     double* dTP = p->w.part;             // dL/dT, dL/dP
     float adj_best = 1e30f;
-    for (int ci = 0; ci < 3 && !rc; ++ci) {
+    for (int ci = 0; ci < 4 && !rc; ++ci) {
       float ms_best;
       time3([&]() {
         launch_adjoint(p->md, kernel_work(p), view(st), view(ln), sigma, dTP, dTP + p->conds.size(), outs,

@@ -25,8 +25,8 @@ constexpr int base_profile(int profile) {
 }
 constexpr int kQBlocks = 256;     // partial sums per slot in the partition-function reduction
 constexpr int kItemsPerCU = 256;  // gather work items aimed at per compute unit when tiles are split
-constexpr int kAdjBlocks = 2048;     // persistent blocks of the adjoint in a new plan
-constexpr int kAdjBlocksMax = 8192;  // the most the configuration allows (sizes the partial sums)
+constexpr int kAdjBlocks = 16384;    // blocks of the adjoint's grid in a new plan
+constexpr int kAdjBlocksMax = 32768;  // the most the configuration allows (sizes the partial sums)
 constexpr int kSortItems = 16;    // keys per thread in the radix sort (4096 per block)
 // Device counters (int32): [0] gather work queue, [2..3] candidate total,
 // [4..5] lines per item, [8] cooling-function runs.
