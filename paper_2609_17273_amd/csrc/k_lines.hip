@@ -94,10 +94,10 @@ void launch_q_out(const ModelDev& m, const Work& w, double* Q, double* dQ, hipSt
 
 // ---------------------------------------------------------------------------
 // Intensity pass 1: nu_i = E_u - E_l; keep lines with nu > 0 whose window
-// (widest cut-off) reaches the grid; key = bucket of the home bin
-// k_c = rint((nu - nu0)/dnu), clamped to the grid's buckets (lines past
-// either end keep their wings, section "Spectral synthesis"); dropped lines
-// get key n_buckets.  FP32 form: running max of ln|S| per slot.  Counters:
+// (widest cut-off) reaches the grid; key = k_c / kFineBins for the home bin
+// k_c = rint((nu - nu0)/dnu), clamped to the grid (lines past either end
+// keep their wings, section "Spectral synthesis"); dropped lines get key
+// n_fine.  FP32 form: running max of ln|S| per slot.  Counters:
 // kept lines and window pairs (exact windows per distinct cut-off).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ LineState line_state(const StatesView& st, int32_t u, int32_t l,
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256) void k_lines_pass1(ModelDev m, const SlotDev* 
   unsigned long long kept = 0, pairs = 0, bad = 0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < ln.n; i += (int64_t)gridDim.x * 256) {
     const int32_t u = ln.up[i], l = ln.lo[i];
-    int32_t kk = m.n_buckets;
+    int32_t kk = m.n_fine;
     LineState ls;
     int32_t vu, vl;
     if (!gather_line_states<MODE>(m, st, spack, u, l, ls, vu, vl)) {
@@ -261,8 +261,8 @@ __global__ __launch_bounds__(256) void k_lines_pass1(ModelDev m, const SlotDev* 
     int64_t a, b;
     if (nu > 0.0 && line_window(nu, m.max_cut, m.nu0, m.dnu, m.n_bins, a, b)) {
       int64_t kc = home_bin(nu, m.nu0, m.dnu);
-      int64_t bk = kc < 0 ? 0 : kc / m.bucket_bins;
-      kk = (int32_t)(bk < m.n_buckets - 1 ? bk : m.n_buckets - 1);
+      int64_t fk = kc < 0 ? 0 : kc / kFineBins;
+      kk = (int32_t)(fk < m.n_fine - 1 ? fk : m.n_fine - 1);
       ++kept;
       LinePack lp;
       lp.Eu = ls.Eu;
@@ -542,17 +542,20 @@ void launch_radix_sort(const ModelDev& m, const Work& w, int64_t n, int64_t max_
 }
 
 // ---------------------------------------------------------------------------
-// Bucket offsets from the sorted keys (position n acts as key n_buckets + 1,
-// so every bucket 0..n_buckets gets its start; off[n_buckets] = kept lines),
+// Bucket offsets from the sorted fine keys (bucket = key / fine_per_bucket,
+// the dropped key n_fine is bucket n_buckets, and position n acts as bucket
+// n_buckets + 1, so every bucket 0..n_buckets gets its start;
+// off[n_buckets] = kept lines),
 // and the sorted line records: nu, gamma_ref, n_exp, original index, and the
 // intensity of every slot, S (FP64) or S~ = sign exp(ln|S| - s_b) (FP32).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_offsets(const int32_t* skeys, int64_t n, int nbk,
+__global__ __launch_bounds__(256) void k_offsets(const int32_t* skeys, int64_t n, int nbk, int nfine, int fpb,
                                                  int32_t* off) {
+  auto bucket = [&](int fk) { return fk >= nfine ? nbk : fk / fpb; };
   for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p <= n;
        p += (int64_t)gridDim.x * 256) {
-    const int k = (p < n) ? skeys[p] : nbk + 1;
-    const int kp = (p > 0) ? skeys[p - 1] : -1;
+    const int k = (p < n) ? bucket(skeys[p]) : nbk + 1;
+    const int kp = (p > 0) ? bucket(skeys[p - 1]) : -1;
     for (int b = kp + 1; b <= k && b <= nbk; ++b) off[b] = (int32_t)p;
   }
 }
@@ -620,8 +623,8 @@ void launch_offsets_records(const ModelDev& m, const Work& w, const StatesView& 
                             int64_t n, hipStream_t s) {
   int64_t blocks = (n + 256) / 256;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_offsets, dim3((unsigned)blocks), dim3(256), 0, s, skeys, n, m.n_buckets,
-                     w.off);
+  hipLaunchKernelGGL(k_offsets, dim3((unsigned)blocks), dim3(256), 0, s, skeys, n, m.n_buckets, m.n_fine,
+                     m.fine_per_bucket, w.off);
   hipLaunchKernelGGL(k_records, dim3((unsigned)blocks), dim3(256), 0, s, m, w.slot, w.Q, w.sb, st,
                      w.lpack, svals, w.off, w.max_lines, w.rnu, w.rgref, w.rnexp, w.rgpre, w.ridx, w.rEs, w.rS,
                      w.cut_class, w.rkc, w.rdel, w.rwin);

@@ -223,6 +223,8 @@ void derive(xs_plan* p) {
   d.n_cond = (int32_t)p->conds.size();
   d.bucket_bins = p->bucket_bins;
   d.n_buckets = (int32_t)((p->grid.n_bins + p->bucket_bins - 1) / p->bucket_bins);
+  d.n_fine = (int32_t)((p->grid.n_bins + kFineBins - 1) / kFineBins);
+  d.fine_per_bucket = p->bucket_bins / kFineBins;
   // intensity slots: distinct population temperatures
   p->sdev.clear();
   p->cdev.clear();
@@ -402,7 +404,7 @@ int preprocess(xs_plan* p, const xs_states* st, const xs_lines* ln) {
   launch_partition(p->md, p->w, sv, p->stream);
   launch_lines_pass1(p->md, p->w, sv, lv, p->stream);
   int32_t *sk = nullptr, *svv = nullptr;
-  launch_radix_sort(p->md, p->w, lv.n, p->md.n_buckets, p->stream, &sk, &svv);
+  launch_radix_sort(p->md, p->w, lv.n, p->md.n_fine, p->stream, &sk, &svv);
   p->has_tau = st->lifetime != nullptr;
   launch_offsets_records(p->md, kernel_work(p), sv, lv, sk ? sk : p->w.keyA, svv ? svv : p->w.valA, lv.n,
                          p->stream);

@@ -32,6 +32,7 @@ constexpr int kSortItems = 16;    // keys per thread in the radix sort (4096 per
 // [4..5] lines per item, [8] cooling-function runs.
 constexpr int kCounterInts = 64;
 constexpr int kSortBlock = 256 * kSortItems;
+constexpr int kFineBins = 64;  // grid points per sort key (the smallest bucket size)
 
 // Per-condition scalars, uploaded with the workspace.
 struct CondDev {
@@ -59,7 +60,11 @@ struct ModelDev {
   int64_t n_bins;
   double T_ref, P_ref, hwhm_fixed, mass_amu;
   int32_t n_cond, n_slots;
-  int32_t bucket_bins, n_buckets;  // lines bucketed by k_c / bucket_bins; key n_buckets = dropped
+  int32_t bucket_bins, n_buckets;  // lines bucketed by k_c / bucket_bins
+  // Lines are sorted by the finer key k_c / kFineBins (key n_fine = dropped),
+  // whatever the bucket size, so that neighbouring sorted lines have nearly
+  // equal home bins; a bucket is fine_per_bucket consecutive fine keys.
+  int32_t n_fine, fine_per_bucket;
   int32_t n_cut_classes;           // distinct cut-offs (window statistics)
   double max_cut;
 };
