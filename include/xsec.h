@@ -339,11 +339,13 @@ int xs_plan_replay(xs_plan* plan);
 /* Time the candidate kernel configurations on these inputs (sigma is used as
  * scratch and overwritten): the plan's bucket size and the other of 64 and
  * 256 points (the lines are re-bucketed in the plan's workspace), each with
- * 256-, 512- and 1024-point tiles and three launch modes.  Keeps the fastest
- * and caches it under cache_path (JSON, keyed by device, profile, precision,
- * window size and line count; NULL: no file).  A cached entry is reused
- * without timing.  When the chosen bucket size is not the last one tried, the
- * next xs_cross_section re-buckets the lines. */
+ * 256-, 512- and 1024-point tiles and three launch modes; then, for LTE
+ * sampled profiles, the adjoint's grid of 4096, 8192, 16384 or 32768 blocks
+ * (sigma serves as its cotangent).  Keeps the fastest and caches it under
+ * cache_path (JSON, keyed by device, profile, precision, window size, line
+ * count and number of conditions; NULL: no file).  A cached entry is reused
+ * without timing.  When the chosen bucket size is not the last one tried,
+ * the next xs_cross_section re-buckets the lines. */
 int xs_plan_autotune(xs_plan* plan, const xs_states* states, const xs_lines* lines,
                      double* sigma, const char* cache_path);
 
