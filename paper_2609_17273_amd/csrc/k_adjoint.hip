@@ -314,10 +314,21 @@ struct GSrc {
 // other combinations are sums of positive terms (bar -c/d^2, with c/d below
 // 0.09 for every level) or enter scaled by 4 tau/d against it.  For larger y
 // (u may reach 0) the per-point form is kept.
-template <typename R, int PROF, int NP, bool SY = false, bool C0 = false>
+//
+// UF, the u-form of the one-pair level for waves with larger y (where the
+// block-summed form's S1 - h S0 would cancel): four sums in u = x^2 taken
+// directly, S0 = sum g/d, U1 = sum g u/d, U2 = sum g u/d^2, U3 = sum g u^2/d^2.
+// With d = u^2 + q u + p^2 and 2p - q = 4 tau, e^2 = 1/d + 4 tau u/d^2, so
+//   sum g e = U1 + p S0,  sum g e^2 = S0 + 4 tau U2,
+//   sum g t = 4 tau (p U2 - U3) - U1,
+// where only the last difference changes sign (at u = p) and so cancels as
+// the sum's own terms do.  A point costs u, d, 1/d and four sums (12 VALU
+// instructions against 16.5 for the per-point form).
+template <typename R, int PROF, int NP, bool SY = false, bool C0 = false, bool UF = false>
 __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G, int r0, int r1,
                                            double& sA, double& sB, double& sC) {
   static_assert(!C0 || (SY && NP == 2 && sizeof(R) == 8), "the node at 0 has its own form in FP64 block sums");
+  static_assert(!UF || (!SY && NP == 1), "the u-form is the one-pair level's");
   // the lanes running this loop (the wave's active lines) share the refills
   const unsigned long long act = __ballot(1);
   const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(act >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)act, 0u));
@@ -385,6 +396,16 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
           B[1][0] = fma(gv, rd[1], B[1][0]);
           B[1][1] += gv;
         }
+      } else if constexpr (UF) {
+        // s1 = S0, s2 = U1, s3 = U2, s4 = U3
+        const PairD<R>& P = L.P[0];
+        const R rd = arcp(fma(u, u + P.q, P.p2));
+        const R gr = gk * rd;
+        s1 += gr;
+        s2 = fma(gr, u, s2);
+        const R v = (gr * rd) * u;
+        s3 += v;
+        s4 = fma(v, u, s4);
       } else if constexpr (NP == 1) {
         // s1 = sum g e, s2 = sum g t, s3 = sum g / d, s4 = sum g e^2
         R e, rd, t;
@@ -500,12 +521,19 @@ __device__ __forceinline__ void fast_range(const AdjLine<R>& L, const GSrc<R>& G
       sA += (double)s1;
       sC += (double)s1 - 2.0 * (double)s2;
     } else {
-      const double k = (NP == 1 && !SY) ? (double)L.P[0].K : 1.0;
+      const double k = (NP == 1 && !SY && !UF) ? (double)L.P[0].K : 1.0;
       const double y2 = L.y * L.y;
       // sums of g e, g t, g/d, g e^2 (K-weighted over the pairs but for the
       // one-pair per-point form)
       double ge = (double)s1, gt = (double)s2, gd = (double)s3, ge2 = (double)s4;
-      if constexpr (SY) {
+      if constexpr (UF) {
+        const double K = (double)L.P[0].K, t4 = -(double)L.P[0].k2, p = (double)L.P[0].p;
+        const double S0 = (double)s1, U1 = (double)s2, U2 = (double)s3, U3 = (double)s4;
+        ge = K * (U1 + p * S0);
+        gd = K * S0;
+        ge2 = K * (S0 + t4 * U2);
+        gt = K * (t4 * (p * U2 - U3) - U1);
+      } else if constexpr (SY) {
         ge = gt = gd = ge2 = 0.0;
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
@@ -541,7 +569,8 @@ __device__ __forceinline__ void fast_level(int level, const AdjLine<R>& L, const
     else fast_range<R, PROF, 3, true>(L, G, r0, r1, sA, sB, sC);
     return;
   }
-  if (PROF != XS_VOIGT || level == 0) fast_range<R, PROF, 1>(L, G, r0, r1, sA, sB, sC);
+  if (PROF == XS_VOIGT && level == 0) fast_range<R, PROF, 1, false, false, true>(L, G, r0, r1, sA, sB, sC);
+  else if (PROF != XS_VOIGT || level == 0) fast_range<R, PROF, 1>(L, G, r0, r1, sA, sB, sC);
   else if (sizeof(R) == 4 || level <= 2) fast_range<R, PROF, 2>(L, G, r0, r1, sA, sB, sC);
   else if constexpr (sizeof(R) == 8) fast_range<R, PROF, 3>(L, G, r0, r1, sA, sB, sC);
 }

@@ -6,8 +6,9 @@ term.
 For a line with y and points x_k carrying cotangents g_k, the kernel's window
 sums are A = sum g Re w, B = sum g (Re w + x dRe w/dx + y dRe w/dy) and
 C = -sum g dRe w/dy, with the rule's Re w = (y/pi) sum_j W_j / ((x - t_j)^2 + y^2).
-Two forms are checked: the per-point one (e, t, 1/d and e^2 of each node pair)
-and the block-summed one (four sums S0..S3 per pair, combined once per block),
+Three forms are checked: the per-point one (e, t, 1/d and e^2 of each node
+pair), the block-summed one (four sums S0..S3 per pair in s = u + h, combined
+once per block) and the u-form of waves with larger y (four sums in u),
 for one pair, the three-point rule (a pair and the node at 0, which the block
 form reduces to sum g/v and sum g/v^2) and two pairs."""
 import numpy as np
@@ -105,6 +106,29 @@ def block(rule, x, y, g):
     return finish(y, ge, gt, gd, ge2)
 
 
+def u_form(rule, x, y, g):
+    """The one-pair form of waves with larger y: four sums in u = x^2 taken
+    directly, S0 = sum g/d, U1 = sum g u/d, U2 = sum g u/d^2 and
+    U3 = sum g u^2/d^2, with e^2 = 1/d + 4 tau u/d^2 (from
+    d = u^2 + q u + p^2 and 2 p - q = 4 tau):
+    sum g e = U1 + p S0, sum g e^2 = S0 + 4 tau U2,
+    sum g t = 4 tau (p U2 - U3) - U1."""
+    u = x * x
+    y2 = y * y
+    ge = gt = gd = ge2 = 0.0
+    for tau, K in kernel_pairs(rule, y):
+        p, q = y2 + tau, 2.0 * y2 - 2.0 * tau
+        rd = 1.0 / (u * (u + q) + p * p)
+        gr = g * rd
+        v = gr * rd * u
+        S0, U1, U2, U3 = np.sum(gr), np.sum(gr * u), np.sum(v), np.sum(v * u)
+        ge += K * (U1 + p * S0)
+        gd += K * S0
+        ge2 += K * (S0 + 4.0 * tau * U2)
+        gt += K * (4.0 * tau * (p * U2 - U3) - U1)
+    return finish(y, ge, gt, gd, ge2)
+
+
 def finish(y, ge, gt, gd, ge2):
     y2 = y * y
     w = ge + 2.0 * y2 * gd - 4.0 * y2 * ge2  # dRe w/dy summed against g
@@ -115,7 +139,7 @@ LEVEL_RHO = {"one pair": 9.0e6, "three-point": 4.5e4, "two pairs": 4000.0}
 
 
 @pytest.mark.parametrize("rule", list(RULES))
-@pytest.mark.parametrize("y", [1e-6, 1e-3, 0.3, 5.0, 40.0])
+@pytest.mark.parametrize("y", [1e-6, 1e-3, 0.3, 5.0, 40.0, 300.0, 3e4])
 def test_far_level_forms_match_the_rule(rule, y):
     """Both forms equal the rule's direct derivatives over a window of points
     in the level's region (|z|^2 >= its bound; the block form as the kernel
@@ -129,6 +153,8 @@ def test_far_level_forms_match_the_rule(rule, y):
         ref, scale = direct(rule, x, y, g)
         pp = np.array(per_point(rule, x, y, g))
         assert np.all(np.abs(pp - ref) <= 1e-12 * scale), (rule, y, pp, ref)
+        uf = np.array(u_form(rule, x, y, g))
+        assert np.all(np.abs(uf - ref) <= 1e-12 * scale), (rule, y, uf, ref)
         if y * y <= 0.5 * R:
             bk = np.array(block(rule, x, y, g))
             assert np.all(np.abs(bk - ref) <= 1e-11 * scale), (rule, y, bk, ref)
