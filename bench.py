@@ -57,13 +57,14 @@ sys.path.insert(0, ROOT)
 #                 region's rho bound (the block-summed form), x 2 and per
 #                 pair s 2, d 2, rcp 1, g/d and g/d^2 2, sums of g/d, g s/d,
 #                 g/d^2, g s/d^2 6 = 13: 1 pair 15, 2 pairs 28 (3 pairs 41);
-#                 in the other waves (per-point form) 1 pair: x 2, u 1, d 3,
-#                 rcp 1, e 2, t 6, four sums 8 = 23; 2 pairs: x 2, u 1, per pair
+#                 in the other waves 1 pair takes the u-form: x 2, u 1, d 3,
+#                 rcp 1, g/d 1, g u/d^2 2, sums of g/d, g u/d, g u/d^2,
+#                 g u^2/d^2 6 = 16; 2 pairs the per-point form: x 2, u 1, per pair
 #                 d, rcp, e, t 12 and their K-weighted sums 8, four
 #                 accumulations 8 = 51; core: w (N = 24, both
 #                 parts: 14 + 97 + 17), w' = -2zw + 2i/sqrt(pi) and Re G 13,
 #                 x, |z|^2 5, three accumulations 6 = 152.
-#   adjoint FP64: 1/2/3 pairs 15/28/41 (per-point form 23/51/71); the
+#   adjoint FP64: 1/2/3 pairs 15/28/41 (other waves 16/51/71); the
 #                 three-point rule 22 (x 2, its pair 13, the node at 0: v 2,
 #                 rcp 1, g/v 1, sums of g/v and g/v^2 3; per-point form, as
 #                 two pairs, 51); 4/6 pairs (general form) 113/161;
@@ -76,7 +77,7 @@ FLOP_REGIONS = {
 }
 # adjoint regions with a block-summed form (the table's figure): the flops of
 # the per-point form used in the other waves
-ADJ_POINT_FLOPS = {"f32": [23, 51], "f64": [23, 51, 51, 71]}
+ADJ_POINT_FLOPS = {"f32": [16, 51], "f64": [16, 51, 51, 71]}
 # MI355X vector peaks, no packed-FP32 (the kernels are compiled without packed FP32):
 # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP32
 # and FP64 alike.  The published 157.3 TFLOP/s FP32 figure needs packed math.
