@@ -301,7 +301,9 @@ void derive(xs_plan* p) {
 
 // item_target: gather work items aimed at when tiles are split (sizes the
 // partial-row buffer, 2 item_target rows); 0 = kItemsPerCU per compute unit.
-size_t layout(xs_plan* p, char* base, Work* w, int64_t item_target = 0) {
+// with_adjoint: carve the adjoint's per-block partial sums (the
+// allocation-free forward path leaves them out).
+size_t layout(xs_plan* p, char* base, Work* w, int64_t item_target = 0, bool with_adjoint = true) {
   const ModelDev& d = p->md;
   const int64_t L = p->max_lines;
   const int nsb = (int)((L + kSortBlock - 1) / kSortBlock);
@@ -355,7 +357,7 @@ size_t layout(xs_plan* p, char* base, Work* w, int64_t item_target = 0) {
     x.part = (double*)take(sizeof(double) * 2 * (size_t)x.item_target * 1024);
   }
   x.stats = (unsigned long long*)take(8 * 8);
-  x.adjpart = (double*)take(sizeof(double) * d.n_cond * 2 * kAdjBlocksMax);
+  x.adjpart = with_adjoint ? (double*)take(sizeof(double) * d.n_cond * 2 * kAdjBlocksMax) : nullptr;
   x.gmax = (unsigned long long*)take(sizeof(unsigned long long) * d.n_cond);
   x.cut_class = (double*)take(sizeof(double) * d.n_cut_classes);
   x.cut_mult = (int32_t*)take(sizeof(int32_t) * d.n_cut_classes);
@@ -782,7 +784,7 @@ int xs_cross_section_noalloc(xs_plan* p, const xs_states* st, const xs_lines* ln
   if (!sigma) return fail(XS_EINVAL, "sigma is NULL");
   if (accumulate != 0 && accumulate != 1) return fail(XS_EINVAL, "accumulate must be 0 or 1");
   const int64_t items = (int64_t)kNoallocItemsPerCU * std::max(1, p->n_cu);
-  const size_t need = layout(p, nullptr, nullptr, items);
+  const size_t need = layout(p, nullptr, nullptr, items, false);
   if (need > kScratchBytes)
     return fail(XS_EWORKSPACE, "the plan needs " + std::to_string(need) + " bytes of scratch, more than the " +
                                    std::to_string(kScratchBytes) +
@@ -799,7 +801,7 @@ int xs_cross_section_noalloc(xs_plan* p, const xs_states* st, const xs_lines* ln
   const size_t keep_bytes = p->ws_bytes;
   const bool keep_prepared = p->prepared, keep_tau = p->has_tau;
   const int64_t keep_last = p->last_lines_in;
-  layout(p, (char*)base, &p->w, items);
+  layout(p, (char*)base, &p->w, items, false);
   p->ws = base;
   p->ws_bytes = kScratchBytes;
   rc = upload(p);
