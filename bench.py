@@ -191,7 +191,7 @@ def valu_from_profiles(kernel_key: str, ms: float, sclk_mhz=None):
     VALU instruction per 16-lane SIMD per 4 cycles at 2.4 GHz, the clock of
     the 78.6 TFLOP/s peak (transcendentals counted as one instruction).  A
     share near 1 means the kernel keeps the VALU saturated; the FP32
-    adjoint reads 1.00-1.04, so some of its instructions (adds, products,
+    adjoint reads 1.00-1.05, so some of its instructions (adds, products,
     moves) take fewer than 4 cycles, and the share can come out slightly
     above 1.  The shader clock sampled from sysfs during the timed steps (the
     DPM level) is reported beside it, not used."""
