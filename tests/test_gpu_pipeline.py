@@ -94,7 +94,7 @@ def test_all_configurations_agree(prec):
     plan = make_plan(wl, prec, ln.n)
     ds, dl = gpu_inputs(wl, ln)
     for tile in (256, 512, 1024):
-        for bucket, chunk in ((128, 0), (256, 64), (1024, 640), (256, 0)):
+        for bucket, chunk in ((128, 0), (256, 64), (1024, 640), (256, 0), (4096, 0)):
             for pers in (0, 1):
                 plan.set_config(tile_bins=tile, bucket_bins=bucket, persistent=pers, waves_per_cu=8,
                                 chunk_lines=chunk)
