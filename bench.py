@@ -190,11 +190,13 @@ def valu_from_profiles(kernel_key: str, ms: float, sclk_mhz=None):
     share of the peak issue rate over the measured launch time: one wave64
     VALU instruction per 16-lane SIMD per 4 cycles at 2.4 GHz, the clock of
     the 78.6 TFLOP/s peak (transcendentals counted as one instruction).  A
-    share near 1 means the kernel keeps the VALU saturated; the FP32
-    adjoint reads 1.00-1.05, so some of its instructions (adds, products,
-    moves) take fewer than 4 cycles, and the share can come out slightly
-    above 1.  The shader clock sampled from sysfs during the timed steps (the
-    DPM level) is reported beside it, not used."""
+    share near 1 means the kernel keeps the VALU saturated.  The share of
+    all VALU instructions can exceed 1 (the FP32 adjoint reads 1.00-1.05):
+    transcendentals (reciprocals, exponentials) issue to a unit of their own
+    and overlap the others, so issue_frac_excl_transcendental, the share of
+    the rest, is reported too and stays at or below about 1.  The shader
+    clock sampled from sysfs during the timed steps (the DPM level) is
+    reported beside it, not used."""
     path = os.path.join(ROOT, "profiles", "pmc_valu.json")
     if not os.path.exists(path):
         return None
@@ -208,7 +210,25 @@ def valu_from_profiles(kernel_key: str, ms: float, sclk_mhz=None):
     return {"wave_instructions": n, "per_eval": round(n * 64 / e["evals"], 3),
             "transcendental_per_eval": round(e["SQ_INSTS_VALU_TRANS"] * 64 / e["evals"], 3),
             "issue_frac": round(4.0 * n / cycles, 4),
+            "issue_frac_excl_transcendental": round(4.0 * (n - e["SQ_INSTS_VALU_TRANS"]) / cycles, 4),
             "sclk_MHz_sampled": round(sclk_mhz, 1) if sclk_mhz else None}
+
+
+def issue_roofline(kernel_key: str, ms: float, kernel: str):
+    """ALU roofline of a kernel whose per-evaluation formula has no flop
+    count in the convention above (bin integrals through arctangents, error
+    functions): VALU lane-instructions per second from the committed SQ
+    counters against the peak issue rate 256 CU x 64 lanes x 2.4 GHz (as for
+    the cooling function), or None when the counters were taken on other
+    sources."""
+    v = valu_from_profiles(kernel_key, ms)
+    if v is None:
+        return None
+    ach = v["wave_instructions"] * 64 / (ms / 1e3)
+    return {"bound": "alu", "achieved": round(ach / 1e12, 3), "peak": round(256 * 64 * 2.4e9 / 1e12, 3),
+            "unit": "T VALU lane-instructions/s", "frac": round(ach / (256 * 64 * 2.4e9), 4), "kernel": kernel,
+            "avg_launch_ms": round(ms, 3), "instr_per_eval": v["per_eval"],
+            "frac_excl_transcendental": v["issue_frac_excl_transcendental"]}
 
 
 def run_step(plan, ds, dl, sig, w, target, ev):
@@ -403,7 +423,8 @@ def pseudo_voigt(X, wl, ds, dl, n_lines, cfg, sampled_ms):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 3
         out[name] = {"profile_pass_ms": round(ms, 3), "evals_per_s": pairs / (ms / 1e3),
-                     "over_sampled_voigt_f32": round(ms / sampled_ms, 3)}
+                     "over_sampled_voigt_f32": round(ms / sampled_ms, 3),
+                     "roofline": issue_roofline(f"{name}_1e7", ms, f"k_gather<float,{name.split('_')[0]}>")}
         log(f"pseudo-Voigt {name}: {ms:.2f} ms")
         p.close()
         del sig
@@ -434,7 +455,9 @@ def binned_voigt(X, wl, ds, dl, n_lines, cfg, sampled_ms):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        out[name] = {"profile_pass_ms": round(ms, 3), "evals_per_s": pairs / (ms / 1e3), "window_pairs": pairs}
+        out[name] = {"profile_pass_ms": round(ms, 3), "evals_per_s": pairs / (ms / 1e3), "window_pairs": pairs,
+                     "roofline": issue_roofline(f"binned_voigt1e7_{name}", ms,
+                                                f"k_gather<{'float' if name == 'f32' else 'double'},BinVoigt>")}
         log(f"binned voigt {name}: {ms:.2f} ms")
         p.close()
         del sig
